@@ -1,0 +1,394 @@
+/*
+ * CPU oracle for the GPU filtering stage of the multi-tiered IVF-PQ index.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  The GPU search path
+ * never links, loads or calls it, and it shares no code with that path.
+ *
+ * Plain scalar C, one query at a time, in the order the paper describes the
+ * online search (Sec. 3, steps 1-8):
+ *   probe   the top-m nearest posting lists                   (Sec. 2.1, step 2)
+ *   lut     the per-query distance table                      (Sec. 2.2, step 1)
+ *   gather  the vector IDs of the probed lists (a multiset)   (Sec. 4.1, step 3)
+ *   dedup   remove the duplicates left by replication         (step 5, Sec. 5)
+ *   adc     approximate distance by table lookups             (Eq. 1, step 6)
+ *   topn    the n best approximate distances                  (step 7)
+ *   rerank  exact distance on raw vectors, keep the top-k     (step 8, fixed n)
+ * plus brute-force exact kNN for recall.
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *  - dist() of Eq. 1 is the squared Euclidean distance of the subvectors, so
+ *    the table sum equals the squared distance to the decoded vector.
+ *  - Non-residual PQ: one table per query, built before the lists are known.
+ *  - The probe is exact over all centroids (no navigation graph).
+ *  - Every distance that decides a selection is a float32 value: exact
+ *    squared distances are evaluated in float64 (sequential over dimensions)
+ *    or in integers, then rounded to nearest-even float32.  The table sum of
+ *    Eq. 1 is a float32 sum over subspaces m = 0..M-1 in that order, starting
+ *    from +0.0f, with plain additions (no fused multiply-add anywhere; build
+ *    with -ffp-contract=off).
+ *  - Every selection orders by (distance, id) lexicographically: ties go to
+ *    the lower list ID / lower external vector ID.
+ *  - For uint8/int8 datasets the float32 queries are first converted to the
+ *    data type: round half to even, then saturate to the type's range.
+ *  - Fewer candidates than n (or k): all are kept; outputs are padded with
+ *    id -1 and distance +inf.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { ORC_F32 = 0, ORC_U8 = 1, ORC_I8 = 2 };
+
+/* The index as the oracle sees it: external vector order, arrays owned by the
+ * caller (read from the index file by the oracle's own reader). */
+typedef struct {
+  int32_t dtype; /* ORC_F32 / ORC_U8 / ORC_I8 */
+  int32_t dim;
+  int64_t n;
+  int32_t nlist;
+  int32_t m;
+  int32_t ksub;
+  int32_t dsub;
+  int32_t r;
+  int32_t pad_;
+  const float* centroids;   /* nlist x dim */
+  const float* codebooks;   /* m x ksub x dsub */
+  const uint8_t* codes;     /* n x m */
+  const void* vectors;      /* n x dim of dtype */
+  const int64_t* offsets;   /* nlist + 1 */
+  const int32_t* entries;   /* offsets[nlist] external ids */
+} orc_index;
+
+/* ------------------------------------------------------------------------ */
+/* Query conversion (reading: integer datasets take integer queries).        */
+
+static void convert_query(const orc_index* ix, const float* q, double* out) {
+  for (int t = 0; t < ix->dim; ++t) {
+    double v = (double)q[t];
+    if (ix->dtype == ORC_U8) {
+      v = nearbyint(v);
+      if (v < 0.0) v = 0.0;
+      if (v > 255.0) v = 255.0;
+    } else if (ix->dtype == ORC_I8) {
+      v = nearbyint(v);
+      if (v < -128.0) v = -128.0;
+      if (v > 127.0) v = 127.0;
+    }
+    out[t] = v;
+  }
+}
+
+/* Squared Euclidean distance in float64, sequential over t, rounded once to
+ * float32.  Exact for integer-valued inputs (every partial sum < 2^53). */
+static float sqdist_f64(const double* q, const float* c, int d) {
+  double acc = 0.0;
+  for (int t = 0; t < d; ++t) {
+    double u = q[t] - (double)c[t];
+    double sq = u * u;
+    acc = acc + sq;
+  }
+  return (float)acc;
+}
+
+/* Exact squared distance between the converted query and raw vector v.
+ * Integer datasets: exact in 32-bit integers (|q_t - x_t| <= 255, so the sum
+ * stays below 2^31 for dim < 33025), then converted to float32. */
+static float exact_dist(const orc_index* ix, const double* q, const int32_t* qi, int64_t v) {
+  const int d = ix->dim;
+  if (ix->dtype == ORC_F32) return sqdist_f64(q, (const float*)ix->vectors + v * d, d);
+  int32_t acc = 0;
+  if (ix->dtype == ORC_U8) {
+    const uint8_t* x = (const uint8_t*)ix->vectors + v * d;
+    for (int t = 0; t < d; ++t) {
+      int32_t u = qi[t] - (int32_t)x[t];
+      acc += u * u;
+    }
+  } else {
+    const int8_t* x = (const int8_t*)ix->vectors + v * d;
+    for (int t = 0; t < d; ++t) {
+      int32_t u = qi[t] - (int32_t)x[t];
+      acc += u * u;
+    }
+  }
+  return (float)acc;
+}
+
+static void int_query(const orc_index* ix, const double* q, int32_t* qi) {
+  for (int t = 0; t < ix->dim; ++t) qi[t] = (int32_t)q[t];
+}
+
+/* ------------------------------------------------------------------------ */
+/* (distance, id) pairs and their lexicographic order.                       */
+
+typedef struct {
+  float d;
+  int32_t id;
+} pair_t;
+
+static int pair_cmp(const void* a, const void* b) {
+  const pair_t* x = (const pair_t*)a;
+  const pair_t* y = (const pair_t*)b;
+  if (x->d < y->d) return -1;
+  if (x->d > y->d) return 1;
+  return (x->id > y->id) - (x->id < y->id);
+}
+
+static int i32_cmp(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step 2: top-m nearest posting lists (exact probe over all centroids).     */
+
+static int probe_one(const orc_index* ix, const double* q, int np, int32_t* out_l, float* out_d,
+                     pair_t* scratch) {
+  for (int l = 0; l < ix->nlist; ++l) {
+    scratch[l].d = sqdist_f64(q, ix->centroids + (int64_t)l * ix->dim, ix->dim);
+    scratch[l].id = l;
+  }
+  qsort(scratch, (size_t)ix->nlist, sizeof(pair_t), pair_cmp);
+  if (np > ix->nlist) np = ix->nlist;
+  for (int p = 0; p < np; ++p) {
+    out_l[p] = scratch[p].id;
+    if (out_d) out_d[p] = scratch[p].d;
+  }
+  return np;
+}
+
+/* Step 1: distance table L[m][j] = sum_t (q[m*dsub+t] - CB[m][j][t])^2. */
+static void lut_one(const orc_index* ix, const double* q, float* lut32, double* lut64) {
+  for (int m = 0; m < ix->m; ++m) {
+    for (int j = 0; j < ix->ksub; ++j) {
+      const float* c = ix->codebooks + ((int64_t)m * ix->ksub + j) * ix->dsub;
+      double acc = 0.0;
+      for (int t = 0; t < ix->dsub; ++t) {
+        double u = q[m * ix->dsub + t] - (double)c[t];
+        double sq = u * u;
+        acc = acc + sq;
+      }
+      lut32[m * ix->ksub + j] = (float)acc;
+      if (lut64) lut64[m * ix->ksub + j] = acc;
+    }
+  }
+}
+
+/* Steps 3 and 5: the multiset of IDs of the probed lists, then its set of
+ * distinct IDs in ascending order.  Returns the multiset size. */
+static int64_t gather_dedup(const orc_index* ix, const int32_t* probe, int np, int32_t* buf,
+                            int64_t* n_unique) {
+  int64_t g = 0;
+  for (int p = 0; p < np; ++p) {
+    int32_t l = probe[p];
+    for (int64_t e = ix->offsets[l]; e < ix->offsets[l + 1]; ++e) buf[g++] = ix->entries[e];
+  }
+  qsort(buf, (size_t)g, sizeof(int32_t), i32_cmp);
+  int64_t u = 0;
+  for (int64_t i = 0; i < g; ++i)
+    if (u == 0 || buf[u - 1] != buf[i]) buf[u++] = buf[i];
+  *n_unique = u;
+  return g;
+}
+
+/* Step 6, Eq. 1: float32 sum of table entries over m = 0..M-1. */
+static float adc_one(const orc_index* ix, const float* lut32, int64_t v) {
+  const uint8_t* code = ix->codes + v * ix->m;
+  float a = 0.0f;
+  for (int m = 0; m < ix->m; ++m) a = a + lut32[m * ix->ksub + code[m]];
+  return a;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Public entry points.  All arrays are host arrays owned by the caller.     */
+
+/* Step 2 for a batch.  probe/pdist: nq x nprobe_max, padded with -1/+inf. */
+void orc_probe(const orc_index* ix, const float* Q, int64_t nq, const int32_t* nprobe,
+               int32_t nprobe_max, int32_t* probe, float* pdist, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+  {
+    double* q = (double*)malloc(sizeof(double) * ix->dim);
+    pair_t* scratch = (pair_t*)malloc(sizeof(pair_t) * ix->nlist);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 4)
+#endif
+    for (int64_t i = 0; i < nq; ++i) {
+      convert_query(ix, Q + i * ix->dim, q);
+      int np = nprobe[i];
+      int32_t* pl = probe + i * nprobe_max;
+      float* pd = pdist ? pdist + i * nprobe_max : NULL;
+      int got = probe_one(ix, q, np, pl, pd, scratch);
+      for (int p = got; p < nprobe_max; ++p) {
+        pl[p] = -1;
+        if (pd) pd[p] = INFINITY;
+      }
+    }
+    free(q);
+    free(scratch);
+  }
+}
+
+/* Step 1 for a batch.  lut32: nq x M x ksub; lut64 optional (same shape). */
+void orc_lut(const orc_index* ix, const float* Q, int64_t nq, float* lut32, double* lut64) {
+  double* q = (double*)malloc(sizeof(double) * ix->dim);
+  int64_t per = (int64_t)ix->m * ix->ksub;
+  for (int64_t i = 0; i < nq; ++i) {
+    convert_query(ix, Q + i * ix->dim, q);
+    lut_one(ix, q, lut32 + i * per, lut64 ? lut64 + i * per : NULL);
+  }
+  free(q);
+}
+
+/* Steps 3+5 for one probe list: writes the distinct IDs (ascending) into
+ * out (capacity >= multiset size), returns the multiset size. */
+int64_t orc_gather_dedup(const orc_index* ix, const int32_t* probe, int32_t np, int32_t* out,
+                         int64_t* n_unique) {
+  return gather_dedup(ix, probe, np, out, n_unique);
+}
+
+/* Step 6 for explicit IDs with a given table (M x ksub): float32 sums and,
+ * optionally, float64 sums of the float64 table. */
+void orc_adc(const orc_index* ix, const float* lut32, const double* lut64, const int32_t* ids,
+             int64_t n, float* adc32, double* adc64) {
+  for (int64_t i = 0; i < n; ++i) {
+    adc32[i] = adc_one(ix, lut32, ids[i]);
+    if (adc64) {
+      const uint8_t* code = ix->codes + (int64_t)ids[i] * ix->m;
+      double a = 0.0;
+      for (int m = 0; m < ix->m; ++m) a = a + lut64[m * ix->ksub + code[m]];
+      adc64[i] = a;
+    }
+  }
+}
+
+/* Exact squared distances of explicit IDs to one query (after conversion). */
+void orc_exact(const orc_index* ix, const float* q32, const int32_t* ids, int64_t n, float* out) {
+  double* q = (double*)malloc(sizeof(double) * ix->dim);
+  int32_t* qi = (int32_t*)malloc(sizeof(int32_t) * ix->dim);
+  convert_query(ix, q32, q);
+  int_query(ix, q, qi);
+  for (int64_t i = 0; i < n; ++i) out[i] = exact_dist(ix, q, qi, ids[i]);
+  free(q);
+  free(qi);
+}
+
+/*
+ * Steps 1-8 for a batch of queries.
+ *   nprobe[i]            lists probed by query i (clamped to nlist)
+ *   ids, dists           nq x k final results (-1 / +inf padded)
+ *   topn_ids, topn_adc   optional nq x rerank_n: the step-7 selection, ascending
+ *   ncand                optional nq: distinct candidates scored by Eq. 1
+ *   nentries             optional nq: list entries gathered (with duplicates)
+ */
+void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* nprobe,
+                int32_t k, int32_t rerank_n, int64_t* ids, float* dists, int32_t* topn_ids,
+                float* topn_adc, int64_t* ncand, int64_t* nentries, int nthreads) {
+  int64_t maxg = ix->offsets[ix->nlist];
+  if (maxg < 1) maxg = 1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+  {
+    double* q = (double*)malloc(sizeof(double) * ix->dim);
+    int32_t* qi = (int32_t*)malloc(sizeof(int32_t) * ix->dim);
+    pair_t* scratch = (pair_t*)malloc(sizeof(pair_t) * (ix->nlist > maxg ? ix->nlist : maxg));
+    int32_t* probe = (int32_t*)malloc(sizeof(int32_t) * ix->nlist);
+    float* lut = (float*)malloc(sizeof(float) * ix->m * ix->ksub);
+    int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * maxg);
+    pair_t* rr = (pair_t*)malloc(sizeof(pair_t) * (rerank_n > 0 ? rerank_n : 1));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+    for (int64_t i = 0; i < nq; ++i) {
+      convert_query(ix, Q + i * ix->dim, q);
+      int_query(ix, q, qi);
+      lut_one(ix, q, lut, NULL);                                   /* step 1 */
+      int np = probe_one(ix, q, nprobe[i], probe, NULL, scratch);  /* step 2 */
+      int64_t nu = 0;
+      int64_t g = gather_dedup(ix, probe, np, buf, &nu);           /* steps 3, 5 */
+      for (int64_t c = 0; c < nu; ++c) {                           /* step 6 */
+        scratch[c].d = adc_one(ix, lut, buf[c]);
+        scratch[c].id = buf[c];
+      }
+      qsort(scratch, (size_t)nu, sizeof(pair_t), pair_cmp);        /* step 7 */
+      int64_t nn = nu < rerank_n ? nu : rerank_n;
+      if (topn_ids) {
+        for (int64_t c = 0; c < rerank_n; ++c) {
+          topn_ids[i * rerank_n + c] = c < nn ? scratch[c].id : -1;
+          topn_adc[i * rerank_n + c] = c < nn ? scratch[c].d : INFINITY;
+        }
+      }
+      for (int64_t c = 0; c < nn; ++c) {                           /* step 8 */
+        rr[c].id = scratch[c].id;
+        rr[c].d = exact_dist(ix, q, qi, scratch[c].id);
+      }
+      qsort(rr, (size_t)nn, sizeof(pair_t), pair_cmp);
+      for (int c = 0; c < k; ++c) {
+        ids[i * k + c] = c < nn ? (int64_t)rr[c].id : -1;
+        dists[i * k + c] = c < nn ? rr[c].d : INFINITY;
+      }
+      if (ncand) ncand[i] = nu;
+      if (nentries) nentries[i] = g;
+    }
+    free(q);
+    free(qi);
+    free(scratch);
+    free(probe);
+    free(lut);
+    free(buf);
+    free(rr);
+  }
+}
+
+/* Exact k nearest neighbours over all N vectors, ordered by (distance, id). */
+void orc_bruteforce(const orc_index* ix, const float* Q, int64_t nq, int32_t k, int64_t* ids,
+                    float* dists, int nthreads) {
+  if (k <= 0) return;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+  {
+    double* q = (double*)malloc(sizeof(double) * ix->dim);
+    int32_t* qi = (int32_t*)malloc(sizeof(int32_t) * ix->dim);
+    pair_t* best = (pair_t*)malloc(sizeof(pair_t) * (k + 1));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+    for (int64_t i = 0; i < nq; ++i) {
+      convert_query(ix, Q + i * ix->dim, q);
+      int_query(ix, q, qi);
+      int cnt = 0;
+      for (int64_t v = 0; v < ix->n; ++v) {
+        pair_t p;
+        p.d = exact_dist(ix, q, qi, v);
+        p.id = (int32_t)v;
+        if (cnt == k && pair_cmp(&p, &best[k - 1]) >= 0) continue;
+        /* insertion into the sorted best list */
+        int pos = cnt < k ? cnt : k - 1;
+        while (pos > 0 && pair_cmp(&p, &best[pos - 1]) < 0) {
+          best[pos] = best[pos - 1];
+          --pos;
+        }
+        best[pos] = p;
+        if (cnt < k) ++cnt;
+      }
+      for (int c = 0; c < k; ++c) {
+        ids[i * k + c] = c < cnt ? (int64_t)best[c].id : -1;
+        dists[i * k + c] = c < cnt ? best[c].d : INFINITY;
+      }
+    }
+    free(q);
+    free(qi);
+    free(best);
+  }
+}

@@ -1,0 +1,321 @@
+"""Offline IVF-PQ index construction and the index file writer.
+
+The index follows the paper's offline processing (Sec. 3, Sec. 4.1): the
+dataset is clustered into posting lists, boundary vectors are replicated into
+neighbouring lists by the rule of Eq. 2 (at most R lists per vector), the
+posting lists are reduced to vector IDs, and every vector gets one M-byte PQ
+code (Sec. 2.2).  The navigation graph over centroids is not built: the search
+probes centroids exactly.
+
+Clustering is flat k-means for up to ``FLAT_MAX_LISTS`` lists and two-level
+(hierarchical) k-means above that, following the paper's hierarchical
+clustering of the dataset.  For uint8/int8 data the list centroids and the PQ
+codebooks are rounded to the integer grid of the data type, so every distance
+the search computes between a query and a centroid, a codeword or a vector is
+an exact integer.
+
+File layout (little-endian), as read by ``ann_load_index``:
+
+======  ============  =====================================================
+offset  type          field
+======  ============  =====================================================
+0       char[8]       magic ``FANNIDX1``
+8       u32           version (1)
+12      u32           header bytes (512)
+16      u32           dtype: 0 float32, 1 uint8, 2 int8
+20      u32           dimension D
+24      u64           N vectors
+32      u32           nlist
+36      u32           M subspaces
+40      u32           ksub (256)
+44      u32           dsub = D / M
+48      u32           R, max lists per vector
+52      u32           flags: bit 0 = centroids and codebooks are integers
+56      f32           eps of Eq. 2 used at build time
+60      u32           number of sections (7)
+64      u64           E, total posting-list entries
+128     7 x 24 bytes  sections: u64 offset, u64 bytes, u32 crc32, u32 0
+508     u32           crc32 of header bytes 0..507
+======  ============  =====================================================
+
+Sections, each starting on a 4096-byte boundary, all in external vector order:
+0 centroids f32 [nlist, D]; 1 codebooks f32 [M, ksub, dsub]; 2 codes u8
+[N, M]; 3 vectors [N, D] of dtype; 4 list offsets i64 [nlist + 1]; 5 list
+entries i32 [E] (external IDs, ascending inside each list); 6 assignment i32
+[N, R] (each vector's lists, nearest first, -1 padded).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import struct
+import subprocess
+import zlib
+from dataclasses import dataclass
+
+import numpy as np
+
+from .. import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ivfpq_build.cpp")
+LIB = os.path.join(HERE, "_ivfpq_build.so")
+
+MAGIC = b"FANNIDX1"
+HEADER_BYTES = 512
+DTYPE_CODE = {"f32": 0, "u8": 1, "i8": 2}
+NP_DTYPE = {"f32": np.float32, "u8": np.uint8, "i8": np.int8}
+FLAT_MAX_LISTS = 4096
+ROW_CHUNK = 1 << 20
+
+_lib = None
+
+
+def compile_builder(force: bool = False) -> str:
+    """Compile the C++ helpers with g++ (OpenMP) into an in-tree shared object."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        cmd = ["g++", "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared",
+               "-std=c++17", SRC, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(compile_builder())
+        P = ctypes.c_void_p
+        i64, i32, f32 = ctypes.c_int64, ctypes.c_int, ctypes.c_float
+        lib.bld_kmeans.argtypes = [P, i64, i32, P, i32, i32]
+        lib.bld_nearest.argtypes = [P, i64, i32, P, i32, P, P]
+        lib.bld_assign_flat.argtypes = [P, i64, i32, P, i32, i32, f32, P]
+        lib.bld_assign_hier.argtypes = [P, i64, i32, P, i32, P, P, i32, i32, f32, P]
+        lib.bld_pq_encode.argtypes = [P, i64, i32, P, i32, i32, i32, P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags.c_contiguous
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+@dataclass
+class BuildParams:
+    nlist: int
+    M: int
+    R: int = 2
+    eps: float = 0.1
+    ksub: int = 256
+    kmeans_iters: int = 10
+    pq_iters: int = 20
+    train_per_list: int = 40
+    pq_train_rows: int = 65536
+    hier_top_probe: int = 2
+    seed: int = 0
+    init_centroids: np.ndarray | None = None  # optional initial list centroids
+
+
+def _rows_f32(X: np.ndarray, r0: int, r1: int) -> np.ndarray:
+    return np.ascontiguousarray(X[r0:r1], dtype=np.float32)
+
+
+def kmeans(Xs: np.ndarray, k: int, iters: int, seed: int, init: np.ndarray | None = None) -> np.ndarray:
+    """Lloyd k-means on float32 rows, initialised from k distinct seeded rows."""
+    lib = _load()
+    Xs = np.ascontiguousarray(Xs, dtype=np.float32)
+    n, d = Xs.shape
+    if init is None:
+        rng = np.random.default_rng(seed)
+        if n >= k:
+            pick = rng.choice(n, size=k, replace=False)
+        else:
+            pick = rng.choice(n, size=k, replace=True)
+        C = np.ascontiguousarray(Xs[pick])
+        if n < k:  # duplicate rows: separate them slightly so all clusters can be used
+            C = C + rng.standard_normal(C.shape).astype(np.float32) * 1e-3
+    else:
+        C = np.ascontiguousarray(init, dtype=np.float32).copy()
+    lib.bld_kmeans(_ptr(Xs), n, d, _ptr(C), k, iters)
+    return C
+
+
+def _grid(a: np.ndarray, kind: str) -> np.ndarray:
+    if kind == "u8":
+        return np.clip(np.rint(a), 0, 255).astype(np.float32)
+    if kind == "i8":
+        return np.clip(np.rint(a), -128, 127).astype(np.float32)
+    return a.astype(np.float32)
+
+
+def train_ivf(X: np.ndarray, kind: str, p: BuildParams):
+    """Return (centroids [nlist, D] f32, hierarchy or None)."""
+    n, d = X.shape
+    ns = min(n, max(p.nlist * p.train_per_list, 1))
+    rows = inputs.sample_rows(p.seed, n, ns)
+    Xs = np.ascontiguousarray(X[rows], dtype=np.float32)
+    if p.init_centroids is not None or p.nlist <= FLAT_MAX_LISTS:
+        C = kmeans(Xs, p.nlist, p.kmeans_iters, p.seed + 1, init=p.init_centroids)
+        return _grid(C, kind), None
+    # Two-level: ktop clusters, then each split into sub-lists proportional to its size.
+    ktop = 1 << int(np.ceil(np.log2(np.sqrt(p.nlist))))
+    ktop = min(ktop, p.nlist)
+    Ctop = kmeans(Xs, ktop, p.kmeans_iters, p.seed + 2)
+    lib = _load()
+    lab = np.empty(ns, dtype=np.int32)
+    lib.bld_nearest(_ptr(Xs), ns, d, _ptr(Ctop), ktop, _ptr(lab), None)
+    sizes = np.bincount(lab, minlength=ktop).astype(np.float64)
+    share = sizes / sizes.sum() * p.nlist
+    cnt = np.maximum(np.floor(share).astype(np.int64), 1)
+    while cnt.sum() > p.nlist:
+        j = int(np.argmax(cnt - share))
+        cnt[j] -= 1
+    rem = share - cnt
+    order = np.argsort(-rem, kind="stable")
+    i = 0
+    while cnt.sum() < p.nlist:
+        cnt[order[i % ktop]] += 1
+        i += 1
+    subs = []
+    for a in range(ktop):
+        Xa = Xs[lab == a]
+        if len(Xa) == 0:
+            Xa = Ctop[a:a + 1]
+        subs.append(kmeans(Xa, int(cnt[a]), p.kmeans_iters, p.seed + 1000 + a))
+    Csub = np.ascontiguousarray(np.concatenate(subs, axis=0))
+    off = np.zeros(ktop + 1, dtype=np.int32)
+    off[1:] = np.cumsum(cnt)
+    return _grid(Csub, kind), (_grid(Ctop, kind) if kind != "f32" else Ctop.astype(np.float32), off)
+
+
+def assign_lists(X: np.ndarray, C: np.ndarray, hier, p: BuildParams) -> np.ndarray:
+    lib = _load()
+    n, d = X.shape
+    A = np.empty((n, p.R), dtype=np.int32)
+    for r0 in range(0, n, ROW_CHUNK):
+        r1 = min(n, r0 + ROW_CHUNK)
+        Xc = _rows_f32(X, r0, r1)
+        out = np.empty((r1 - r0, p.R), dtype=np.int32)
+        if hier is None:
+            lib.bld_assign_flat(_ptr(Xc), r1 - r0, d, _ptr(C), C.shape[0], p.R, p.eps, _ptr(out))
+        else:
+            Ctop, off = hier
+            Ctop = np.ascontiguousarray(Ctop, dtype=np.float32)
+            lib.bld_assign_hier(_ptr(Xc), r1 - r0, d, _ptr(Ctop), Ctop.shape[0], _ptr(C),
+                                _ptr(off), p.hier_top_probe, p.R, p.eps, _ptr(out))
+        A[r0:r1] = out
+    return A
+
+
+def train_pq(X: np.ndarray, kind: str, p: BuildParams) -> np.ndarray:
+    n, d = X.shape
+    dsub = d // p.M
+    rows = inputs.sample_rows(p.seed + 5, n, p.pq_train_rows)
+    Xs = np.ascontiguousarray(X[rows], dtype=np.float32)
+    CB = np.empty((p.M, p.ksub, dsub), dtype=np.float32)
+    for m in range(p.M):
+        sub = np.ascontiguousarray(Xs[:, m * dsub:(m + 1) * dsub])
+        CB[m] = kmeans(sub, p.ksub, p.pq_iters, p.seed + 7000 + m)
+    return _grid(CB, kind).reshape(p.M, p.ksub, dsub)
+
+
+def encode_pq(X: np.ndarray, CB: np.ndarray) -> np.ndarray:
+    lib = _load()
+    n, d = X.shape
+    M, ksub, dsub = CB.shape
+    CBc = np.ascontiguousarray(CB, dtype=np.float32)
+    codes = np.empty((n, M), dtype=np.uint8)
+    for r0 in range(0, n, ROW_CHUNK):
+        r1 = min(n, r0 + ROW_CHUNK)
+        Xc = _rows_f32(X, r0, r1)
+        out = np.empty((r1 - r0, M), dtype=np.uint8)
+        lib.bld_pq_encode(_ptr(Xc), r1 - r0, d, _ptr(CBc), M, ksub, dsub, _ptr(out))
+        codes[r0:r1] = out
+    return codes
+
+
+def lists_from_assignment(A: np.ndarray, nlist: int):
+    """CSR posting lists (external IDs ascending inside each list) from [N, R] assignment."""
+    n, R = A.shape
+    ids = np.repeat(np.arange(n, dtype=np.int64), R)
+    lst = A.reshape(-1).astype(np.int64)
+    keep = lst >= 0
+    ids, lst = ids[keep], lst[keep]
+    order = np.lexsort((ids, lst))
+    entries = ids[order].astype(np.int32)
+    counts = np.bincount(lst, minlength=nlist)
+    offsets = np.zeros(nlist + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(counts)
+    return offsets, entries
+
+
+@dataclass
+class IndexArrays:
+    kind: str
+    centroids: np.ndarray
+    codebooks: np.ndarray
+    codes: np.ndarray
+    vectors: np.ndarray
+    offsets: np.ndarray
+    entries: np.ndarray
+    assign: np.ndarray
+    eps: float
+    int_grid: bool
+
+
+def build_arrays(X: np.ndarray, kind: str, p: BuildParams) -> IndexArrays:
+    assert X.dtype == NP_DTYPE[kind] and X.ndim == 2
+    n, d = X.shape
+    if d % p.M:
+        raise ValueError(f"D={d} is not a multiple of M={p.M}")
+    C, hier = train_ivf(X, kind, p)
+    A = assign_lists(X, C, hier, p)
+    CB = train_pq(X, kind, p)
+    codes = encode_pq(X, CB)
+    offsets, entries = lists_from_assignment(A, p.nlist)
+    return IndexArrays(kind, C, CB, codes, X, offsets, entries, A, p.eps, kind != "f32")
+
+
+def write_index(path: str, ix: IndexArrays) -> None:
+    n, d = ix.vectors.shape
+    nlist = ix.centroids.shape[0]
+    M, ksub, dsub = ix.codebooks.shape
+    R = ix.assign.shape[1]
+    secs = [
+        np.ascontiguousarray(ix.centroids, dtype=np.float32),
+        np.ascontiguousarray(ix.codebooks, dtype=np.float32),
+        np.ascontiguousarray(ix.codes, dtype=np.uint8),
+        np.ascontiguousarray(ix.vectors, dtype=NP_DTYPE[ix.kind]),
+        np.ascontiguousarray(ix.offsets, dtype=np.int64),
+        np.ascontiguousarray(ix.entries, dtype=np.int32),
+        np.ascontiguousarray(ix.assign, dtype=np.int32),
+    ]
+    table = []
+    off = HEADER_BYTES
+    for s in secs:
+        off = (off + 4095) // 4096 * 4096
+        mv = memoryview(s).cast("B")
+        table.append((off, s.nbytes, zlib.crc32(mv) & 0xFFFFFFFF))
+        off += s.nbytes
+    hdr = bytearray(HEADER_BYTES)
+    struct.pack_into("<8sIIIIQIIIIIIfIQ", hdr, 0, MAGIC, 1, HEADER_BYTES, DTYPE_CODE[ix.kind], d,
+                     n, nlist, M, ksub, dsub, R, 1 if ix.int_grid else 0, float(ix.eps),
+                     len(secs), int(ix.entries.shape[0]))
+    for i, (o, b, c) in enumerate(table):
+        struct.pack_into("<QQII", hdr, 128 + 24 * i, o, b, c, 0)
+    struct.pack_into("<I", hdr, 508, zlib.crc32(bytes(hdr[:508])) & 0xFFFFFFFF)
+    tmp = path + ".tmp"
+    with open(tmp, "wb") as f:
+        f.write(hdr)
+        for (o, b, c), s in zip(table, secs):
+            f.seek(o)
+            f.write(memoryview(s).cast("B"))
+    os.replace(tmp, path)
+
+
+def build_index(path: str, X: np.ndarray, kind: str, p: BuildParams) -> IndexArrays:
+    ix = build_arrays(X, kind, p)
+    write_index(path, ix)
+    return ix

@@ -1,0 +1,104 @@
+"""Offline index construction: Eq. 2 replication, list metadata, PQ codes, file format."""
+import numpy as np
+import pytest
+from scipy.spatial.distance import cdist
+
+from paper_2409_16576_amd import builder, inputs, workloads
+from tests import fixtures as fx
+
+
+@pytest.mark.parametrize("kind,nlist", [("f32", 24), ("u8", 24), ("u8", 5000)])
+def test_assignment_follows_eq2(tmp_path, orc, kind, nlist):
+    """Every vector sits in 1..R lists; the first is the nearest candidate list;
+    each further list satisfies Dist(v, C_i) <= (1 + eps) Dist(v, C_1) (Eq. 2);
+    no closer qualifying list was skipped."""
+    n = 6000 if nlist < 1000 else 12000
+    X = fx.mixture(21, n, 16, kind, n_centres=12, hi=255)
+    R, eps = 3, 0.15
+    path, ix = fx.built(tmp_path, "asg", X, kind, nlist=nlist, M=4, R=R, eps=eps,
+                        train_per_list=2 if nlist > 1000 else 40)
+    A = ix.assign
+    assert (A[:, 0] >= 0).all()
+    D = np.sqrt(cdist(X.astype(np.float64), ix.centroids.astype(np.float64), "sqeuclidean"))
+    rows = np.arange(n)
+    d1 = D[rows, A[:, 0]]
+    hier = nlist > builder.FLAT_MAX_LISTS
+    if not hier:  # flat: the first list is the global nearest (ties: lower id)
+        assert np.array_equal(A[:, 0], np.argmin(D, axis=1))
+    for s in range(1, R):
+        ok = A[:, s] >= 0
+        assert (D[rows[ok], A[ok, s]] <= (1 + eps) * d1[ok] * (1 + 1e-6) + 1e-6).all()
+        assert (D[rows[ok], A[ok, s]] >= D[rows[ok], A[ok, s - 1]] * (1 - 1e-6) - 1e-6).all()
+        # once a slot is empty, all later slots are empty
+        if s + 1 < R:
+            assert (A[~ok, s + 1] == -1).all()
+    if not hier:
+        for v in range(0, n, 97):
+            qual = np.where(D[v] <= (1 + eps) * d1[v] * (1 - 1e-6))[0]
+            got = set(A[v][A[v] >= 0].tolist())
+            if len(qual) <= R:
+                assert set(qual.tolist()) <= got
+    assert 0 < (A[:, 1] >= 0).mean() < 1
+
+
+def test_lists_and_assignment_agree(tmp_path, orc):
+    X = fx.mixture(22, 4000, 16, "i8", lo=-128, hi=127)
+    path, ix = fx.built(tmp_path, "lst", X, "i8", nlist=20, M=8)
+    o = orc.read_index(path)
+    assert o.entries.shape[0] == int((o.assign >= 0).sum())
+    for l in range(o.nlist):
+        e = o.entries[o.offsets[l]:o.offsets[l + 1]]
+        assert (np.diff(e) > 0).all()
+        assert set(e.tolist()) == set(np.where((o.assign == l).any(1))[0].tolist())
+
+
+@pytest.mark.parametrize("kind", ["u8", "i8", "f32"])
+def test_pq_codes_are_nearest_codewords(tmp_path, kind):
+    lo, hi = (-128, 127) if kind == "i8" else (0, 255)
+    X = fx.mixture(23, 3000, 24, kind, lo=lo, hi=hi)
+    path, ix = fx.built(tmp_path, "pq", X, kind, nlist=8, M=6)
+    dsub = 4
+    for m in range(6):
+        sub = X[:, m * dsub:(m + 1) * dsub].astype(np.float64)
+        D = cdist(sub, ix.codebooks[m].astype(np.float64), "sqeuclidean")
+        best = D.min(1)
+        got = D[np.arange(len(X)), ix.codes[:, m]]
+        if kind == "f32":
+            np.testing.assert_allclose(got, best, rtol=1e-5, atol=1e-4)
+        else:
+            assert np.array_equal(ix.codes[:, m], np.argmin(D, axis=1))
+    if kind != "f32":
+        for a in (ix.centroids, ix.codebooks):
+            assert np.array_equal(a, np.rint(a)) and a.min() >= lo and a.max() <= hi
+
+
+def test_file_roundtrip_and_checksums(tmp_path, orc):
+    X = fx.mixture(24, 1000, 8, "u8", hi=255)
+    path, ix = fx.built(tmp_path, "rt", X, "u8", nlist=6, M=2)
+    o = orc.read_index(path)
+    for a, b in ((o.centroids, ix.centroids), (o.codebooks, ix.codebooks), (o.codes, ix.codes),
+                 (o.vectors, ix.vectors), (o.offsets, ix.offsets), (o.entries, ix.entries),
+                 (o.assign, ix.assign)):
+        assert np.array_equal(a, b)
+    raw = bytearray(open(path, "rb").read())
+    raw[-3] ^= 0xFF  # corrupt the last section
+    bad = tmp_path / "bad.fidx"
+    bad.write_bytes(bytes(raw))
+    with pytest.raises(ValueError):
+        orc.read_index(str(bad))
+
+
+def test_generators_are_deterministic_and_chunk_independent():
+    c = inputs.mixture_centres(5, 10, 6, 0, 255)
+    a = inputs.mixture_points(9, 150_000, c, 10.0, "u8")
+    b = inputs.mixture_points(9, 150_000, c, 10.0, "u8")
+    assert np.array_equal(a, b)
+    # a prefix of a larger draw equals the smaller draw (fixed chunking)
+    s = inputs.mixture_points(9, 70_000, c, 10.0, "u8")
+    assert np.array_equal(a[:65536], s[:65536])
+    assert not np.array_equal(inputs.mixture_points(10, 1000, c, 10.0, "u8"), a[:1000])
+    w = workloads.scaled(workloads.ZIPF_F32_5M, n=20000, nlist=64, nq=50)
+    x = workloads.base_vectors(w)
+    np.testing.assert_allclose(np.linalg.norm(x, axis=1), 1.0, rtol=1e-5)
+    npb = workloads.nprobe_per_query(w)
+    assert npb.min() >= 8 and npb.max() <= 128

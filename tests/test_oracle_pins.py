@@ -1,0 +1,255 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test names the property it pins and what it rules out.  None of them
+re-derives an expected value through the oracle itself.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import cdist
+
+from tests import fixtures as fx
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _toy(tmp_path):
+    g = json.load(open(os.path.join(GOLDEN, "toy_adc_search.json")))
+    path, _ = fx.write_arrays(tmp_path, "toy", "f32", np.array(g["centroids"], np.float32),
+                              np.array(g["codebooks"], np.float32), np.array(g["codes"], np.uint8),
+                              np.array(g["vectors"], np.float32), np.array(g["assign"], np.int32))
+    return g, path
+
+
+def test_toy_hand_worked_example(tmp_path, orc):
+    """Hand-computed table, Eq. 1 sums, dedup, tie-break and re-rank (golden fixture)."""
+    g, path = _toy(tmp_path)
+    e = g["expect"]
+    ix = orc.read_index(path)
+    q = np.array([g["query"]], np.float32)
+    lists, d = orc.probe(ix, q, 2)
+    assert lists[0].tolist() == [0, 1] and d[0].tolist() == e["coarse_dists"]
+    l32, l64 = orc.lut(ix, q)
+    assert l32[0].tolist() == e["lut"]
+    assert orc.adc(ix, l32[0], np.arange(5)).tolist() == e["adc"]
+    assert orc.exact(ix, q[0], np.arange(5)).tolist() == e["exact"]
+    for l, want in enumerate(e["lists"]):
+        assert ix.entries[ix.offsets[l]:ix.offsets[l + 1]].tolist() == want
+    u, gsz = orc.gather_dedup(ix, [0])
+    assert u.tolist() == e["nprobe1"]["unique"] and gsz == e["nprobe1"]["gathered"]
+    u, gsz = orc.gather_dedup(ix, [0, 1])
+    assert u.tolist() == e["nprobe2"]["unique"] and gsz == e["nprobe2"]["gathered"]
+    for key, n in (("search_nprobe2_n3_k2", 3), ("search_nprobe2_n2_k2", 2)):
+        r = orc.search(ix, q, 2, 2, n)
+        assert r.topn_ids[0].tolist() == e[key]["topn_ids"]
+        assert r.topn_adc[0].tolist() == e[key]["topn_adc"]
+        assert r.ids[0].tolist() == e[key]["ids"] and r.dists[0].tolist() == e[key]["dists"]
+    ids, dd = orc.bruteforce(ix, q, 3)
+    assert ids[0].tolist() == e["bruteforce_k3"]["ids"] and dd[0].tolist() == e["bruteforce_k3"]["dists"]
+
+
+@pytest.mark.parametrize("kind", ["f32", "u8", "i8"])
+def test_eq1_identity_table_sum_is_decoded_distance(tmp_path, orc, kind):
+    """Eq. 1 with dist = squared L2: sum_m L[m][code_m] == ||q - decode(v)||^2.
+
+    decode(v) concatenates the codewords named by the code; the right-hand
+    side is computed on whole vectors with numpy, so a wrong subspace offset,
+    a transposed codebook or a dropped subspace breaks the equality.
+    """
+    lo, hi = (-128, 127) if kind == "i8" else (0, 255 if kind == "u8" else 100)
+    X = fx.mixture(3, 3000, 32, kind, lo=lo, hi=hi)
+    path, _ = fx.built(tmp_path, "eq1", X, kind, nlist=16, M=8)
+    ix = orc.read_index(path)
+    Q = fx.mixture(5, 7, 32, kind, lo=lo, hi=hi).astype(np.float32)
+    l32, l64 = orc.lut(ix, Q)
+    ids = np.arange(0, 3000, 7, dtype=np.int32)
+    dec = np.concatenate([ix.codebooks[m][ix.codes[ids, m]] for m in range(ix.M)], axis=1)
+    for i in range(len(Q)):
+        a32, a64 = orc.adc(ix, l32[i], ids, l64[i])
+        ref = ((Q[i].astype(np.float64)[None, :] - dec.astype(np.float64)) ** 2).sum(1)
+        np.testing.assert_allclose(a64, ref, rtol=1e-12, atol=1e-9)
+        # float32 sum of M correctly rounded terms: relative error <= M * 2^-24
+        np.testing.assert_allclose(a32, ref, rtol=ix.M * 2.0 ** -23)
+        if kind != "f32":  # integer grid: every value exact
+            assert np.array_equal(a32.astype(np.float64), ref)
+
+
+def test_table_is_zero_at_the_query_codeword(tmp_path, orc):
+    """dist(q_m, c) >= 0 with equality exactly where the subvector is a codeword."""
+    X = fx.mixture(4, 2000, 16, "f32")
+    path, _ = fx.built(tmp_path, "zero", X, "f32", nlist=8, M=4)
+    ix = orc.read_index(path)
+    j = np.array([5, 17, 200, 255])
+    q = np.concatenate([ix.codebooks[m][j[m]] for m in range(4)])[None].astype(np.float32)
+    l32, _ = orc.lut(ix, q)
+    assert (l32 >= 0).all()
+    for m in range(4):
+        assert l32[0, m, j[m]] == 0.0
+        assert np.count_nonzero(l32[0, m] == 0.0) == np.count_nonzero(
+            (ix.codebooks[m] == ix.codebooks[m][j[m]]).all(1))
+
+
+@pytest.mark.parametrize("kind", ["u8", "f32"])
+def test_probe_is_sorted_nearest_lists(tmp_path, orc, kind):
+    """Step 2: the m nearest centroids, ordered by (distance, list id) — scipy cdist."""
+    X = fx.mixture(6, 4000, 16, kind, hi=255)
+    path, _ = fx.built(tmp_path, "probe", X, kind, nlist=64, M=4)
+    ix = orc.read_index(path)
+    Q = fx.mixture(8, 25, 16, kind, hi=255).astype(np.float32)
+    lists, d = orc.probe(ix, Q, 10)
+    D = cdist(Q.astype(np.float64), ix.centroids.astype(np.float64), "sqeuclidean")
+    for i in range(len(Q)):
+        if kind == "u8":  # integers: cdist is exact, so the order must match exactly
+            want = np.lexsort((np.arange(ix.nlist), D[i]))[:10]
+            assert lists[i].tolist() == want.tolist()
+            assert np.array_equal(d[i], D[i][want].astype(np.float32))
+        else:
+            np.testing.assert_allclose(d[i], D[i][lists[i]], rtol=1e-6)
+            assert (np.diff(d[i]) >= 0).all()
+            rest = np.setdiff1d(np.arange(ix.nlist), lists[i])
+            assert D[i][rest].min() >= d[i][-1] * (1 - 1e-6)
+
+
+def test_probe_pads_and_clamps(tmp_path, orc):
+    X = fx.mixture(9, 500, 8, "u8", hi=255)
+    path, _ = fx.built(tmp_path, "pad", X, "u8", nlist=4, M=2)
+    ix = orc.read_index(path)
+    Q = X[:3].astype(np.float32)
+    lists, d = orc.probe(ix, Q, np.array([2, 9, 4], np.int32))
+    assert (lists[0, 2:] == -1).all() and np.isinf(d[0, 2:]).all()
+    assert sorted(lists[1, :4].tolist()) == [0, 1, 2, 3] and (lists[1, 4:] == -1).all()
+
+
+def test_dedup_closed_forms(tmp_path, orc):
+    """Steps 3+5: probing every list gathers E entries and yields all N IDs once;
+    with R = 1 the multiset already is a set."""
+    X = fx.mixture(10, 3000, 16, "f32")
+    path, _ = fx.built(tmp_path, "dd", X, "f32", nlist=32, M=4, R=3, eps=0.3)
+    ix = orc.read_index(path)
+    u, g = orc.gather_dedup(ix, np.arange(ix.nlist))
+    assert g == ix.entries.shape[0] and g > ix.n  # replication happened
+    assert np.array_equal(u, np.arange(ix.n))
+    lists = [3, 30, 7, 12]
+    u, g = orc.gather_dedup(ix, lists)
+    cat = np.concatenate([ix.entries[ix.offsets[l]:ix.offsets[l + 1]] for l in lists])
+    assert g == len(cat) and np.array_equal(u, np.unique(cat))
+    path1, _ = fx.built(tmp_path, "dd1", X, "f32", nlist=32, M=4, R=1)
+    ix1 = orc.read_index(path1)
+    u, g = orc.gather_dedup(ix1, np.arange(0, 32, 3))
+    assert len(u) == g
+
+
+def test_lossless_pq_adc_top_k_is_exact_knn(tmp_path, orc):
+    """dsub = 1 and every byte value a codeword: ADC equals the exact distance,
+    so the ADC top-k with rerank_n = k is the brute-force top-k, bit for bit."""
+    path, _ = fx.lossless_u8(tmp_path, "lossless")
+    ix = orc.read_index(path)
+    rng = np.random.default_rng(1)
+    Q = rng.integers(0, 256, size=(20, ix.dim)).astype(np.float32)
+    r = orc.search(ix, Q, ix.nlist, 10, 10)
+    bi, bd = orc.bruteforce(ix, Q, 10)
+    assert np.array_equal(r.topn_ids.astype(np.int64), bi)
+    assert np.array_equal(r.topn_adc, bd)
+    assert np.array_equal(r.ids, bi) and np.array_equal(r.dists, bd)
+
+
+@pytest.mark.parametrize("kind", ["u8", "f32"])
+def test_exhaustive_search_is_bruteforce(tmp_path, orc, kind):
+    """nprobe = nlist and rerank_n >= N re-rank everything: search == brute force."""
+    X = fx.mixture(12, 700, 16, kind, hi=255)
+    path, _ = fx.built(tmp_path, "exh", X, kind, nlist=8, M=4)
+    ix = orc.read_index(path)
+    Q = fx.mixture(13, 15, 16, kind, hi=255).astype(np.float32)
+    r = orc.search(ix, Q, ix.nlist, 10, ix.n)
+    bi, bd = orc.bruteforce(ix, Q, 10)
+    assert np.array_equal(r.ids, bi) and np.array_equal(r.dists, bd)
+    assert (r.ncand == ix.n).all()
+
+
+def test_bruteforce_matches_numpy_exact(tmp_path, orc):
+    """Brute force on uint8 data vs numpy integer distances and lexsort."""
+    X = fx.mixture(14, 900, 24, "u8", hi=255)
+    path, _ = fx.built(tmp_path, "bf", X, "u8", nlist=4, M=6)
+    ix = orc.read_index(path)
+    Q = fx.mixture(15, 12, 24, "u8", hi=255).astype(np.float32)
+    bi, bd = orc.bruteforce(ix, Q, 7)
+    D = ((Q[:, None, :].astype(np.int64) - X[None].astype(np.int64)) ** 2).sum(-1)
+    for i in range(len(Q)):
+        want = np.lexsort((np.arange(len(X)), D[i]))[:7]
+        assert bi[i].tolist() == want.tolist()
+        assert bd[i].tolist() == D[i][want].astype(np.float32).tolist()
+
+
+def test_identical_vectors_break_ties_by_lower_id(tmp_path, orc):
+    """All vectors equal: every distance ties, so the results are IDs 0..k-1."""
+    X = np.full((50, 8), 7, np.uint8)
+    cb = np.tile(np.arange(256, dtype=np.float32).reshape(1, 256, 1), (8, 1, 1))
+    assign = np.stack([np.arange(50) % 3, -np.ones(50, int)], 1)
+    cent = np.full((3, 8), 7, np.float32)
+    path, _ = fx.write_arrays(tmp_path, "same", "u8", cent, cb, X.copy(), X, assign)
+    ix = orc.read_index(path)
+    Q = np.array([[0] * 8, [9] * 8], np.float32)
+    r = orc.search(ix, Q, 3, 5, 20)
+    assert r.ids.tolist() == [[0, 1, 2, 3, 4]] * 2
+    assert r.topn_ids.tolist() == [list(range(20))] * 2
+    bi, _ = orc.bruteforce(ix, Q, 4)
+    assert bi.tolist() == [[0, 1, 2, 3]] * 2
+
+
+def test_topn_and_rerank_are_valid_selections(tmp_path, orc):
+    """Step 7 keeps the n smallest (adc, id) of the deduplicated candidates;
+    step 8 returns them re-ordered by (exact distance, id)."""
+    X = fx.mixture(16, 5000, 32, "u8", hi=255)
+    path, _ = fx.built(tmp_path, "sel", X, "u8", nlist=32, M=8)
+    ix = orc.read_index(path)
+    Q = fx.mixture(17, 10, 32, "u8", hi=255).astype(np.float32)
+    n, k, npb = 40, 10, 5
+    r = orc.search(ix, Q, npb, k, n)
+    lists, _ = orc.probe(ix, Q, npb)
+    l32, l64 = orc.lut(ix, Q)
+    for i in range(len(Q)):
+        cand = np.unique(np.concatenate([ix.entries[ix.offsets[l]:ix.offsets[l + 1]] for l in lists[i]]))
+        assert r.ncand[i] == len(cand)
+        dec = np.concatenate([ix.codebooks[m][ix.codes[cand, m]] for m in range(ix.M)], axis=1)
+        adc = ((Q[i][None].astype(np.float64) - dec) ** 2).sum(1)  # integers: exact
+        want = cand[np.lexsort((cand, adc))][:n]
+        assert r.topn_ids[i].tolist() == want.tolist()
+        ex = ((Q[i][None].astype(np.int64) - X[want].astype(np.int64)) ** 2).sum(1)
+        order = np.lexsort((want, ex))[:k]
+        assert r.ids[i].tolist() == want[order].tolist()
+        assert r.dists[i].tolist() == ex[order].astype(np.float32).tolist()
+
+
+def test_integer_queries_are_rounded_and_saturated(tmp_path, orc):
+    """uint8 index: a query is rounded half to even and clipped before use."""
+    path, _ = fx.lossless_u8(tmp_path, "conv", n=64, dim=4)
+    ix = orc.read_index(path)
+    raw = np.array([[2.5, 3.5, -7.0, 300.0]], np.float32)
+    conv = np.array([[2.0, 4.0, 0.0, 255.0]], np.float32)
+    l_raw, _ = orc.lut(ix, raw)
+    l_conv, _ = orc.lut(ix, conv)
+    assert np.array_equal(l_raw, l_conv)
+    assert np.array_equal(orc.bruteforce(ix, raw, 5)[0], orc.bruteforce(ix, conv, 5)[0])
+
+
+def test_padding_when_fewer_candidates_than_k(tmp_path, orc):
+    g, path = _toy(tmp_path)
+    ix = orc.read_index(path)
+    r = orc.search(ix, np.array([g["query"]], np.float32), 1, 8, 6)
+    assert r.ids[0].tolist()[:4] == [0, 3, 1, 4] and r.ids[0].tolist()[4:] == [-1] * 4
+    assert np.isinf(r.dists[0, 4:]).all()
+    assert r.topn_ids[0].tolist()[4:] == [-1, -1]
+
+
+def test_recall_rises_to_one_with_rerank_n(tmp_path, orc):
+    """More re-ranked candidates never lose recall at fixed nprobe (same top-n prefix)."""
+    X = fx.mixture(18, 20000, 32, "f32", n_centres=32)
+    path, _ = fx.built(tmp_path, "rec", X, "f32", nlist=128, M=8)
+    ix = orc.read_index(path)
+    Q = fx.mixture(19, 40, 32, "f32", n_centres=32).astype(np.float32)
+    bi, _ = orc.bruteforce(ix, Q, 10)
+    rec = [orc.recall_at_k(orc.search(ix, Q, 128, 10, n).ids, bi, 10) for n in (10, 50, 200, 20000)]
+    assert all(a <= b + 1e-12 for a, b in zip(rec, rec[1:]))
+    assert rec[-1] == 1.0

@@ -1,0 +1,167 @@
+/*
+ * ann.h — C ABI of the MI355X filtering stage of a multi-tiered IVF-PQ index.
+ *
+ * The library implements the GPU-side online search of the paper's
+ * multi-tiered index (Sec. 3, steps 1-8), with the PQ codes, the posting-list
+ * metadata and the raw vectors all resident in HBM:
+ *   step 1  per-query PQ distance table                         (Sec. 2.2)
+ *   step 2  top-m nearest posting lists (exact over centroids)  (Sec. 2.1)
+ *   step 3  gather the vector IDs of those lists                (Sec. 4.1)
+ *   step 5  remove the duplicate IDs replication creates        (Eq. 2, Sec. 5)
+ *   step 6  approximate distances by table lookups              (Eq. 1)
+ *   step 7  keep the n best (rerank_n, the paper's top-n)
+ *   step 8  re-rank those n by exact squared L2, keep the top-k
+ *
+ * Conventions shared by every entry point:
+ *  - Every pointer named d_* is device memory on the index's device; every
+ *    other pointer is host memory.  Device arrays are row-major and densely
+ *    packed.  `stream` is a hipStream_t (NULL = the null stream).  Work is
+ *    enqueued on `stream` and the call returns without synchronising;
+ *    outputs are valid once the stream reaches that point.  The library
+ *    keeps no caller pointer after the call returns.
+ *  - Vector IDs are external IDs: row numbers of the vectors in the index
+ *    file.  List IDs are 0..nlist-1.
+ *  - Distances are squared Euclidean distances (float32).  Every selection
+ *    orders by (distance, id): ties go to the lower ID.
+ *  - Queries are float32 [nq, dim].  For uint8 / int8 indexes each query
+ *    value is first rounded half to even and saturated to the data type.
+ *  - Outputs are padded with id -1 and distance +inf where fewer than the
+ *    requested results exist.
+ *  - Errors: a non-zero ann_status; ann_last_error() then returns a message
+ *    (thread-local, valid until the next call on the same thread).  No
+ *    argument is modified on error except that partially enqueued work may
+ *    have written outputs.
+ */
+#ifndef ANN_H
+#define ANN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ANN_OK = 0,
+  ANN_EINVAL = 1,      /* bad argument: shape, k, rerank_n, nprobe, NULL pointer */
+  ANN_ENOMEM = 2,      /* device or host allocation failed */
+  ANN_EIO = 3,         /* index file cannot be read */
+  ANN_EFORMAT = 4,     /* bad magic, version, sizes or checksum */
+  ANN_EDEVICE = 5,     /* a HIP runtime call failed */
+  ANN_EUNSUPPORTED = 6 /* valid but not supported by this build (e.g. ksub != 256) */
+} ann_status;
+
+typedef struct ann_index ann_index; /* opaque */
+
+typedef struct {
+  int64_t n;               /* vectors */
+  int32_t dim;             /* dimension D */
+  int32_t dtype;           /* 0 float32, 1 uint8, 2 int8 */
+  int32_t nlist;           /* posting lists */
+  int32_t m;               /* PQ subspaces */
+  int32_t ksub;            /* codewords per subspace (256) */
+  int32_t dsub;            /* D / m */
+  int32_t r;               /* max lists per vector (Eq. 2 cap) */
+  int32_t int_grid;        /* 1: integer arithmetic is exact on this index */
+  int64_t entries;         /* posting-list entries, duplicates included */
+  int64_t replica_entries; /* entries that are not a vector's first list */
+  int64_t max_list;        /* longest posting list (entries) */
+  int64_t hbm_bytes;       /* device memory held by the index */
+  int32_t device;
+  int32_t max_rerank_n;    /* largest rerank_n accepted */
+} ann_index_desc;
+
+/*
+ * Load an index file (format: the paper's offline output, Sec. 3 / Sec. 4.1:
+ * centroids, PQ codebooks, one M-byte code per vector, raw vectors, posting
+ * lists of external IDs and each vector's list assignment) onto `device`.
+ * The file is validated (magic, version, sizes, CRC32 of every section,
+ * list / assignment consistency) and copied to HBM with the code rows and raw
+ * vectors reordered by first list.  *out receives an index owned by the
+ * caller, freed with ann_free_index.  Errors: ANN_EIO, ANN_EFORMAT,
+ * ANN_EUNSUPPORTED (ksub != 256, R > 15, N >= 2^28), ANN_ENOMEM, ANN_EDEVICE.
+ */
+ann_status ann_load_index(const char* path, int device, ann_index** out);
+
+/* Describe a loaded index.  Errors: ANN_EINVAL (NULL). */
+ann_status ann_index_info(const ann_index* ix, ann_index_desc* out);
+
+/* Release every device and host resource of the index (NULL is a no-op).
+ * The caller must ensure no enqueued work still uses it. */
+void ann_free_index(ann_index* ix);
+
+/* Message of the last error on this thread ("" if none). */
+const char* ann_last_error(void);
+
+/*
+ * Steps 1-8 (plain form): search nq queries.
+ *   d_queries   float32 [nq, dim]
+ *   d_nprobe    int32 [nq] lists to probe per query, or NULL: every query
+ *               probes nprobe_max lists.  Values are clamped to
+ *               [0, min(nprobe_max, nlist)].
+ *   nprobe_max  >= 1, upper bound of the per-query values
+ *   k           >= 1 results per query
+ *   rerank_n    k <= rerank_n <= max_rerank_n: candidates re-ranked (top-n)
+ *   d_out_ids   int64 [nq, k], d_out_dists float32 [nq, k]
+ * nq = 0 is a no-op.  Errors: ANN_EINVAL, ANN_ENOMEM, ANN_EDEVICE.
+ */
+ann_status ann_search(ann_index* ix, const float* d_queries, int64_t nq, const int32_t* d_nprobe,
+                      int32_t nprobe_max, int32_t k, int32_t rerank_n, int64_t* d_out_ids,
+                      float* d_out_dists, void* stream);
+
+/*
+ * Steps 1-7: like ann_search but returns the rerank_n best approximate
+ * candidates (ascending by (ADC distance, id)) instead of re-ranking them.
+ *   d_out_ids int32 [nq, rerank_n] (-1 padded), d_out_adc float32 [nq, rerank_n]
+ *   d_out_ncand optional int64 [nq]: distinct candidates scored per query.
+ */
+ann_status ann_search_topn(ann_index* ix, const float* d_queries, int64_t nq,
+                           const int32_t* d_nprobe, int32_t nprobe_max, int32_t rerank_n,
+                           int32_t* d_out_ids, float* d_out_adc, int64_t* d_out_ncand,
+                           void* stream);
+
+/*
+ * Step 2 alone: the nearest lists of each query, ascending by
+ * (centroid distance, list id).
+ *   d_out_lists int32 [nq, nprobe_max] (-1 padded)
+ *   d_out_dists optional float32 [nq, nprobe_max] (+inf padded)
+ */
+ann_status ann_probe(ann_index* ix, const float* d_queries, int64_t nq, const int32_t* d_nprobe,
+                     int32_t nprobe_max, int32_t* d_out_lists, float* d_out_dists, void* stream);
+
+/*
+ * Step 1 alone: d_out_lut float32 [nq, m, ksub], entry [q][s][j] = squared
+ * distance between subvector s of query q and codeword j of subspace s.
+ */
+ann_status ann_lut(ann_index* ix, const float* d_queries, int64_t nq, float* d_out_lut,
+                   void* stream);
+
+/*
+ * Steps 3, 5 and 6 for given lists and tables (trace form, for testing):
+ * every distinct candidate of each query with its Eq. 1 distance.
+ *   d_lists     int32 [nq, nprobe_max], -1 entries ignored (as ann_probe writes)
+ *   d_lut       float32 [nq, m, ksub]
+ *   capacity    slots per query in the outputs
+ *   d_out_ids   int32 [nq, capacity] external IDs, in no particular order
+ *   d_out_adc   float32 [nq, capacity]
+ *   d_out_count int64 [nq]: candidates found (may exceed capacity; only the
+ *               first `capacity` are written)
+ */
+ann_status ann_scan_trace(ann_index* ix, const int32_t* d_lists, int64_t nq, int32_t nprobe_max,
+                          const float* d_lut, int64_t capacity, int32_t* d_out_ids,
+                          float* d_out_adc, int64_t* d_out_count, void* stream);
+
+/*
+ * Step 8 alone: exact re-rank of given candidates.
+ *   d_cand_ids  int32 [nq, n] external IDs (-1 = empty slot)
+ *   d_out_ids   int64 [nq, k], d_out_dists float32 [nq, k]
+ * Requires 1 <= k <= n <= max_rerank_n.
+ */
+ann_status ann_rerank(ann_index* ix, const float* d_queries, int64_t nq, const int32_t* d_cand_ids,
+                      int32_t n, int32_t k, int64_t* d_out_ids, float* d_out_dists, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ANN_H */

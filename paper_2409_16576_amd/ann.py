@@ -1,0 +1,187 @@
+"""Thin ctypes binding of the C ABI in include/ann.h.
+
+Argument marshalling only: every step of the search runs in the HIP kernels
+of ``libann.so``.  Torch tensors provide device memory and the current HIP
+stream; outputs are allocated here with torch and filled by the library.
+There is no CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBANN = os.path.join(HERE, "libann.so")
+
+ANN_OK = 0
+_STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EIO", 4: "EFORMAT", 5: "EDEVICE", 6: "EUNSUPPORTED"}
+
+
+class AnnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ann {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class IndexDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("nlist", ctypes.c_int32), ("m", ctypes.c_int32), ("ksub", ctypes.c_int32),
+        ("dsub", ctypes.c_int32), ("r", ctypes.c_int32), ("int_grid", ctypes.c_int32),
+        ("entries", ctypes.c_int64), ("replica_entries", ctypes.c_int64),
+        ("max_list", ctypes.c_int64), ("hbm_bytes", ctypes.c_int64), ("device", ctypes.c_int32),
+        ("max_rerank_n", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libann.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBANN):
+            raise RuntimeError(f"{LIBANN} is missing: build it with __graft_entry__.build() "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIBANN)
+        P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.ann_last_error.restype = ctypes.c_char_p
+        L.ann_load_index.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(P)]
+        L.ann_index_info.argtypes = [P, ctypes.POINTER(IndexDesc)]
+        L.ann_free_index.argtypes = [P]
+        L.ann_free_index.restype = None
+        L.ann_search.argtypes = [P, P, i64, P, i32, i32, i32, P, P, P]
+        L.ann_search_topn.argtypes = [P, P, i64, P, i32, i32, P, P, P, P]
+        L.ann_probe.argtypes = [P, P, i64, P, i32, P, P, P]
+        L.ann_lut.argtypes = [P, P, i64, P, P]
+        L.ann_scan_trace.argtypes = [P, P, i64, i32, P, i64, P, P, P, P]
+        L.ann_rerank.argtypes = [P, P, i64, P, i32, i32, P, P, P]
+        for f in ("ann_load_index", "ann_index_info", "ann_search", "ann_search_topn", "ann_probe",
+                  "ann_lut", "ann_scan_trace", "ann_rerank"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != ANN_OK:
+        raise AnnError(status, lib().ann_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device, stream):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Index:
+    """A loaded index on one GPU (see ann_load_index)."""
+
+    def __init__(self, path: str, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().ann_load_index(path.encode(), int(device), ctypes.byref(h)))
+        self._h = h
+        self.device = torch.device("cuda", int(device))
+        d = IndexDesc()
+        _check(lib().ann_index_info(self._h, ctypes.byref(d)))
+        self.desc = d.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.device)
+            lib().ann_free_index(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ---------------------------------------------------------------
+    def _queries(self, q):
+        if not (q.is_cuda and q.device == self.device and q.dtype == torch.float32
+                and q.dim() == 2 and q.shape[1] == self.desc["dim"]):
+            raise ValueError("queries must be a float32 [nq, dim] tensor on the index device")
+        return q.contiguous()
+
+    def _nprobe(self, nprobe, nq):
+        if isinstance(nprobe, int):
+            return None, int(nprobe)
+        t = nprobe.to(device=self.device, dtype=torch.int32).contiguous()
+        if t.numel() != nq:
+            raise ValueError("nprobe tensor must have one entry per query")
+        mx = int(t.max().item()) if nq else 1
+        return t, max(1, mx)
+
+    # -- entry points ------------------------------------------------------------
+    def search(self, queries, nprobe, k: int, rerank_n: int, stream=None):
+        """Steps 1-8: (ids int64 [nq, k], squared distances float32 [nq, k])."""
+        q = self._queries(queries)
+        nq = q.shape[0]
+        npt, npmax = self._nprobe(nprobe, nq)
+        ids = torch.empty((nq, k), dtype=torch.int64, device=self.device)
+        d = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        _check(lib().ann_search(self._h, _ptr(q), nq, _ptr(npt), npmax, k, rerank_n, _ptr(ids),
+                                _ptr(d), _stream(self.device, stream)))
+        return ids, d
+
+    def search_topn(self, queries, nprobe, rerank_n: int, stream=None):
+        """Steps 1-7: (ids int32 [nq, n], ADC distances float32 [nq, n], candidates int64 [nq])."""
+        q = self._queries(queries)
+        nq = q.shape[0]
+        npt, npmax = self._nprobe(nprobe, nq)
+        ids = torch.empty((nq, rerank_n), dtype=torch.int32, device=self.device)
+        adc = torch.empty((nq, rerank_n), dtype=torch.float32, device=self.device)
+        nc = torch.empty((nq,), dtype=torch.int64, device=self.device)
+        _check(lib().ann_search_topn(self._h, _ptr(q), nq, _ptr(npt), npmax, rerank_n, _ptr(ids),
+                                     _ptr(adc), _ptr(nc), _stream(self.device, stream)))
+        return ids, adc, nc
+
+    def probe(self, queries, nprobe, with_dists: bool = True, stream=None):
+        q = self._queries(queries)
+        nq = q.shape[0]
+        npt, npmax = self._nprobe(nprobe, nq)
+        lists = torch.empty((nq, npmax), dtype=torch.int32, device=self.device)
+        d = torch.empty((nq, npmax), dtype=torch.float32, device=self.device) if with_dists else None
+        _check(lib().ann_probe(self._h, _ptr(q), nq, _ptr(npt), npmax, _ptr(lists), _ptr(d),
+                               _stream(self.device, stream)))
+        return lists, d
+
+    def lut(self, queries, stream=None):
+        q = self._queries(queries)
+        nq = q.shape[0]
+        out = torch.empty((nq, self.desc["m"], self.desc["ksub"]), dtype=torch.float32,
+                          device=self.device)
+        _check(lib().ann_lut(self._h, _ptr(q), nq, _ptr(out), _stream(self.device, stream)))
+        return out
+
+    def scan_trace(self, lists, lut, capacity: int, stream=None):
+        lists = lists.to(device=self.device, dtype=torch.int32).contiguous()
+        lut = lut.to(device=self.device, dtype=torch.float32).contiguous()
+        nq, npmax = lists.shape
+        ids = torch.empty((nq, capacity), dtype=torch.int32, device=self.device)
+        adc = torch.empty((nq, capacity), dtype=torch.float32, device=self.device)
+        cnt = torch.empty((nq,), dtype=torch.int64, device=self.device)
+        _check(lib().ann_scan_trace(self._h, _ptr(lists), nq, npmax, _ptr(lut), capacity, _ptr(ids),
+                                    _ptr(adc), _ptr(cnt), _stream(self.device, stream)))
+        return ids, adc, cnt
+
+    def rerank(self, queries, cand_ids, k: int, stream=None):
+        q = self._queries(queries)
+        cand = cand_ids.to(device=self.device, dtype=torch.int32).contiguous()
+        nq, n = cand.shape
+        ids = torch.empty((nq, k), dtype=torch.int64, device=self.device)
+        d = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        _check(lib().ann_rerank(self._h, _ptr(q), nq, _ptr(cand), n, k, _ptr(ids), _ptr(d),
+                                _stream(self.device, stream)))
+        return ids, d

@@ -1,0 +1,77 @@
+"""Build the native libraries in-tree.
+
+``libann.so``: the HIP kernels and the C ABI (include/ann.h), compiled with
+hipcc for gfx950.  The index builder's CPU helper is compiled by
+``builder.compile_builder``.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIBANN = os.path.join(HERE, "libann.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+SOURCES = ["ann_kernels.hip", "ann_api.cpp"]
+
+# Packed FP32 instructions are disabled for all device code (they are not
+# needed here and some of their forms are unreliable on the test machines).
+HIP_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("command failed: " + " ".join(cmd))
+    # hipcc's host pass does not know the packed-fp32 target feature; drop that noise
+    noise = [ln for ln in (r.stdout + r.stderr).splitlines()
+             if ln.strip() and "packed-fp32-ops" not in ln and "not a recognized feature" not in ln]
+    if noise:
+        sys.stderr.write("\n".join(noise) + "\n")
+
+
+def build_libann(jobs: int = 4) -> str:
+    objs = []
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC, *HIP_FLAGS, "-x", "hip", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+               "-c", os.path.join(CSRC, src), "-o", obj]
+        procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                       text=True), cmd))
+        objs.append(obj)
+    for p, cmd in procs:
+        out, err = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out + err)
+            raise RuntimeError("compile failed: " + " ".join(cmd))
+        noise = [ln for ln in (out + err).splitlines()
+                 if ln.strip() and "packed-fp32-ops" not in ln and "not a recognized feature" not in ln]
+        if noise:
+            sys.stderr.write("\n".join(noise) + "\n")
+    tmp = LIBANN + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lz"])
+    os.replace(tmp, LIBANN)
+    for o in objs:
+        os.remove(o)
+    return LIBANN
+
+
+def build_all() -> None:
+    from .builder import compile_builder
+    compile_builder(force=True)
+    build_libann()
+
+
+if __name__ == "__main__":
+    build_all()
+    print(LIBANN)

@@ -1,0 +1,616 @@
+// C ABI of the filtering stage: index loading, HBM layout, working-memory
+// pool and the plain search pipeline.  Declarations and contracts: include/ann.h.
+#include "ann.h"
+
+#include <zlib.h>
+
+#include <algorithm>
+#include <cinttypes>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ann_internal.h"
+
+using namespace ann;
+
+namespace {
+
+thread_local std::string g_err;
+
+ann_status fail(ann_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(ANN_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));            \
+  } while (0)
+
+// Working memory for one in-flight call: one block of the index's pool (the
+// paper's per-query working-memory blocks, Sec. 5).  A block is reused only
+// after the stream work of its previous user has completed (event order).
+struct Workspace {
+  Work w;
+  size_t cap_qc = 0, cap_np = 0, cap_nlist = 0, cap_keys = 0, cap_items = 0, cap_lut = 0,
+         cap_cand = 0;
+  std::vector<void*> allocs;
+  hipEvent_t done = nullptr;
+  bool recorded = false;
+
+  void release_memory() {
+    for (void* p : allocs) (void)hipFree(p);
+    allocs.clear();
+    w = Work{};
+    cap_qc = cap_np = cap_nlist = cap_keys = cap_items = cap_lut = cap_cand = 0;
+  }
+  ~Workspace() {
+    if (recorded) (void)hipEventSynchronize(done);
+    release_memory();
+    if (done) (void)hipEventDestroy(done);
+  }
+};
+
+struct Need {
+  size_t qc, np, nlist, keys, items, lut, cand;
+};
+
+}  // namespace
+
+struct ann_index {
+  int device = 0;
+  DevIndex d{};
+  ann_index_desc desc{};
+  std::vector<void*> allocs;
+  std::mutex mu;
+  std::vector<std::unique_ptr<Workspace>> pool;
+  std::vector<Workspace*> free_ws;
+
+  ~ann_index() {
+    pool.clear();
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+template <class T>
+ann_status dev_upload(ann_index* ix, const T* host, size_t count, const T** out) {
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+  if (hipMalloc(&p, bytes) != hipSuccess)
+    return fail(ANN_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+  ix->allocs.push_back(p);
+  ix->desc.hbm_bytes += (int64_t)bytes;
+  if (count) HIP_TRY(hipMemcpy(p, host, count * sizeof(T), hipMemcpyHostToDevice));
+  *out = static_cast<const T*>(p);
+  return ANN_OK;
+}
+
+ann_status ws_alloc(Workspace* ws, size_t bytes, void** out) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess)
+    return fail(ANN_ENOMEM, "workspace hipMalloc of %zu bytes failed", bytes);
+  ws->allocs.push_back(p);
+  *out = p;
+  return ANN_OK;
+}
+
+ann_status ws_ensure(Workspace* ws, const Need& n) {
+  if (ws->cap_qc >= n.qc && ws->cap_np >= n.np && ws->cap_nlist >= n.nlist &&
+      ws->cap_keys >= n.keys && ws->cap_items >= n.items && ws->cap_lut >= n.lut &&
+      ws->cap_cand >= n.cand)
+    return ANN_OK;
+  if (ws->recorded) HIP_TRY(hipEventSynchronize(ws->done));
+  Need g{std::max(n.qc, ws->cap_qc), std::max(n.np, ws->cap_np), std::max(n.nlist, ws->cap_nlist),
+         std::max(n.keys, ws->cap_keys), std::max(n.items, ws->cap_items),
+         std::max(n.lut, ws->cap_lut), std::max(n.cand, ws->cap_cand)};
+  ws->release_memory();
+  Work& w = ws->w;
+  ann_status s;
+#define WS(ptr, bytes)                                                  \
+  if ((s = ws_alloc(ws, (bytes), reinterpret_cast<void**>(&(ptr)))) != ANN_OK) { \
+    ws->release_memory();                                               \
+    return s;                                                           \
+  }
+  WS(w.dist, g.qc * g.nlist * 4);
+  WS(w.lists, g.qc * g.np * 4);
+  WS(w.np_eff, g.qc * 4);
+  WS(w.lut, g.lut * 4);
+  WS(w.eq, g.qc * 8);
+  WS(w.sq, g.qc * 4);
+  WS(w.pkeys, g.keys * 8);
+  WS(w.pcount, g.items * 4);
+  WS(w.pscan, g.items * 4);
+  WS(w.cand, g.cand * 4);
+#undef WS
+  ws->cap_qc = g.qc; ws->cap_np = g.np; ws->cap_nlist = g.nlist; ws->cap_keys = g.keys;
+  ws->cap_items = g.items; ws->cap_lut = g.lut; ws->cap_cand = g.cand;
+  return ANN_OK;
+}
+
+// Take a pool block for this call and order it after its previous user.
+ann_status ws_acquire(ann_index* ix, const Need& need, hipStream_t st, Workspace** out) {
+  Workspace* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> g(ix->mu);
+    if (!ix->free_ws.empty()) {
+      ws = ix->free_ws.back();
+      ix->free_ws.pop_back();
+    } else {
+      ix->pool.emplace_back(new Workspace());
+      ws = ix->pool.back().get();
+    }
+  }
+  ann_status s = ANN_OK;
+  if (!ws->done && hipEventCreateWithFlags(&ws->done, hipEventDisableTiming) != hipSuccess)
+    s = fail(ANN_EDEVICE, "hipEventCreate failed");
+  if (s == ANN_OK) s = ws_ensure(ws, need);
+  if (s == ANN_OK && ws->recorded && hipStreamWaitEvent(st, ws->done, 0) != hipSuccess)
+    s = fail(ANN_EDEVICE, "hipStreamWaitEvent failed");
+  if (s != ANN_OK) {
+    std::lock_guard<std::mutex> g(ix->mu);
+    ix->free_ws.push_back(ws);
+    return s;
+  }
+  *out = ws;
+  return ANN_OK;
+}
+
+void ws_release(ann_index* ix, Workspace* ws, hipStream_t st) {
+  if (hipEventRecord(ws->done, st) == hipSuccess) ws->recorded = true;
+  std::lock_guard<std::mutex> g(ix->mu);
+  ix->free_ws.push_back(ws);
+}
+
+struct WsGuard {
+  ann_index* ix;
+  Workspace* ws;
+  hipStream_t st;
+  ~WsGuard() {
+    if (ws) ws_release(ix, ws, st);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Index file parsing.
+
+struct Section {
+  uint64_t off, bytes;
+  uint32_t crc;
+};
+
+uint32_t crc32_of(const uint8_t* p, size_t n) {
+  uLong c = crc32(0L, Z_NULL, 0);
+  while (n) {
+    const uInt chunk = (uInt)std::min<size_t>(n, 1u << 30);
+    c = crc32(c, p, chunk);
+    p += chunk;
+    n -= chunk;
+  }
+  return (uint32_t)c;
+}
+
+template <class T>
+T rd(const std::vector<uint8_t>& b, size_t off) {
+  T v;
+  std::memcpy(&v, b.data() + off, sizeof(T));
+  return v;
+}
+
+int elem_size(int dtype) { return dtype == F32 ? 4 : 1; }
+
+ann_status validate_args(ann_index* ix, const void* q, int64_t nq, int32_t np_max) {
+  if (!ix) return fail(ANN_EINVAL, "index is NULL");
+  if (nq < 0) return fail(ANN_EINVAL, "nq < 0");
+  if (nq > 0 && !q) return fail(ANN_EINVAL, "queries pointer is NULL");
+  if (np_max < 1 || np_max > 4096) return fail(ANN_EINVAL, "nprobe_max must be in [1, 4096]");
+  return ANN_OK;
+}
+
+int chunk_queries(const DevIndex& d, int64_t nq) {
+  const size_t budget = size_t(256) << 20;
+  size_t by_dist = budget / ((size_t)d.nlist * 4);
+  size_t by_lut = budget / ((size_t)d.M * kKsub * 4);
+  size_t qc = std::min<size_t>({(size_t)nq, by_dist, by_lut, size_t(16384)});
+  return (int)std::max<size_t>(qc, 1);
+}
+
+Need need_for(const DevIndex& d, int qc, int np_max, int n, int smax) {
+  Need r;
+  r.qc = (size_t)qc;
+  r.np = (size_t)np_max;
+  r.nlist = (size_t)d.nlist;
+  r.items = (size_t)qc * smax;
+  r.keys = r.items * (size_t)std::max(n, 1);
+  r.lut = (size_t)qc * d.M * kKsub;
+  r.cand = 0;
+  return r;
+}
+
+LaunchCfg cfg_for(int qc, int np_max, int n, int k) {
+  LaunchCfg c;
+  c.qc = qc;
+  c.np_max = np_max;
+  c.n = n;
+  c.k = k;
+  c.smax = scan_smax(n);
+  c.tile = 4096;
+  c.round_steps = 4;
+  return c;
+}
+
+ann_status check_lds(ann_index* ix, int np_max, int n) {
+  int max_lds = 0;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) !=
+      hipSuccess)
+    return fail(ANN_EDEVICE, "hipDeviceGetAttribute failed");
+  const size_t need = scan_lds_bytes(ix->d, np_max, n, 4);
+  if ((int64_t)need > (int64_t)max_lds)
+    return fail(ANN_EUNSUPPORTED, "scan needs %zu bytes of LDS per block, device allows %d", need,
+                max_lds);
+  return ANN_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+
+extern "C" const char* ann_last_error(void) { return g_err.c_str(); }
+
+extern "C" ann_status ann_load_index(const char* path, int device, ann_index** out) {
+  if (!path || !out) return fail(ANN_EINVAL, "NULL argument");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(ANN_EIO, "cannot open %s", path);
+  std::fseek(f, 0, SEEK_END);
+  const long fsz = std::ftell(f);
+  std::fseek(f, 0, SEEK_SET);
+  if (fsz < 512) {
+    std::fclose(f);
+    return fail(ANN_EFORMAT, "file too small");
+  }
+  std::vector<uint8_t> b((size_t)fsz);
+  const size_t got = std::fread(b.data(), 1, b.size(), f);
+  std::fclose(f);
+  if (got != b.size()) return fail(ANN_EIO, "short read of %s", path);
+
+  if (std::memcmp(b.data(), "FANNIDX1", 8) != 0) return fail(ANN_EFORMAT, "bad magic");
+  if (rd<uint32_t>(b, 8) != 1 || rd<uint32_t>(b, 12) != 512 || rd<uint32_t>(b, 60) != 7)
+    return fail(ANN_EFORMAT, "unsupported version");
+  if (crc32_of(b.data(), 508) != rd<uint32_t>(b, 508)) return fail(ANN_EFORMAT, "header checksum");
+  const int dtype = (int)rd<uint32_t>(b, 16);
+  const int dim = (int)rd<uint32_t>(b, 20);
+  const uint64_t n = rd<uint64_t>(b, 24);
+  const int nlist = (int)rd<uint32_t>(b, 32);
+  const int M = (int)rd<uint32_t>(b, 36);
+  const int ksub = (int)rd<uint32_t>(b, 40);
+  const int dsub = (int)rd<uint32_t>(b, 44);
+  const int R = (int)rd<uint32_t>(b, 48);
+  const uint32_t flags = rd<uint32_t>(b, 52);
+  const uint64_t E = rd<uint64_t>(b, 64);
+  if (dtype < 0 || dtype > 2) return fail(ANN_EFORMAT, "bad dtype %d", dtype);
+  if (dim < 1 || nlist < 1 || M < 1 || R < 1 || n < 1 || dsub < 1 || (int64_t)dsub * M != dim)
+    return fail(ANN_EFORMAT, "bad sizes");
+  if (ksub != kKsub) return fail(ANN_EUNSUPPORTED, "ksub %d (only 256)", ksub);
+  if (M > kMaxM) return fail(ANN_EUNSUPPORTED, "M %d > %d", M, kMaxM);
+  if (dim > kMaxDim) return fail(ANN_EUNSUPPORTED, "dim %d > %d", dim, kMaxDim);
+  if (R > 15) return fail(ANN_EUNSUPPORTED, "R %d > 15", R);
+  if (n >= (1ull << kRankShift)) return fail(ANN_EUNSUPPORTED, "N >= 2^28");
+  if (E > (uint64_t)INT32_MAX) return fail(ANN_EUNSUPPORTED, "more than 2^31 list entries");
+
+  Section sec[7];
+  const uint64_t want[7] = {(uint64_t)nlist * dim * 4, (uint64_t)M * ksub * dsub * 4,
+                            n * (uint64_t)M,           n * (uint64_t)dim * elem_size(dtype),
+                            (uint64_t)(nlist + 1) * 8, E * 4,
+                            n * (uint64_t)R * 4};
+  for (int i = 0; i < 7; ++i) {
+    sec[i].off = rd<uint64_t>(b, 128 + 24 * i);
+    sec[i].bytes = rd<uint64_t>(b, 128 + 24 * i + 8);
+    sec[i].crc = rd<uint32_t>(b, 128 + 24 * i + 16);
+    if (sec[i].bytes != want[i] || sec[i].off + sec[i].bytes > (uint64_t)fsz)
+      return fail(ANN_EFORMAT, "section %d size/offset", i);
+    if (crc32_of(b.data() + sec[i].off, sec[i].bytes) != sec[i].crc)
+      return fail(ANN_EFORMAT, "section %d checksum", i);
+  }
+  const float* cent = reinterpret_cast<const float*>(b.data() + sec[0].off);
+  const float* cb = reinterpret_cast<const float*>(b.data() + sec[1].off);
+  const uint8_t* codes = b.data() + sec[2].off;
+  const uint8_t* vecs = b.data() + sec[3].off;
+  std::vector<int64_t> offs(nlist + 1);
+  std::memcpy(offs.data(), b.data() + sec[4].off, sec[4].bytes);
+  const int32_t* ent = reinterpret_cast<const int32_t*>(b.data() + sec[5].off);
+  const int32_t* asg = reinterpret_cast<const int32_t*>(b.data() + sec[6].off);
+
+  // Structural checks.
+  if (offs[0] != 0 || offs[nlist] != (int64_t)E) return fail(ANN_EFORMAT, "list offsets");
+  for (int l = 0; l < nlist; ++l) {
+    if (offs[l + 1] < offs[l]) return fail(ANN_EFORMAT, "list offsets decrease");
+    for (int64_t e = offs[l]; e < offs[l + 1]; ++e) {
+      if (ent[e] < 0 || (uint64_t)ent[e] >= n) return fail(ANN_EFORMAT, "list entry out of range");
+      if (e > offs[l] && ent[e] <= ent[e - 1]) return fail(ANN_EFORMAT, "list entries not ascending");
+    }
+  }
+  uint64_t nassign = 0;
+  std::vector<int32_t> primary(n);
+  for (uint64_t v = 0; v < n; ++v) {
+    const int32_t* a = asg + v * R;
+    if (a[0] < 0 || a[0] >= nlist) return fail(ANN_EFORMAT, "vector %" PRIu64 " has no list", v);
+    primary[v] = a[0];
+    bool ended = false;
+    for (int r = 0; r < R; ++r) {
+      if (a[r] < 0) {
+        ended = true;
+        continue;
+      }
+      if (ended || a[r] >= nlist) return fail(ANN_EFORMAT, "bad assignment of vector %" PRIu64, v);
+      for (int s = 0; s < r; ++s)
+        if (a[s] == a[r]) return fail(ANN_EFORMAT, "duplicate list in assignment");
+      ++nassign;
+    }
+  }
+  if (nassign != E) return fail(ANN_EFORMAT, "assignment and lists disagree");
+  const bool int_grid = (flags & 1u) && dtype != F32;
+  if (int_grid) {
+    const float lo = dtype == U8 ? 0.f : -128.f, hi = dtype == U8 ? 255.f : 127.f;
+    auto ok = [&](const float* p, size_t cnt) {
+      for (size_t i = 0; i < cnt; ++i)
+        if (!(p[i] == std::nearbyint(p[i]) && p[i] >= lo && p[i] <= hi)) return false;
+      return true;
+    };
+    if (!ok(cent, (size_t)nlist * dim) || !ok(cb, (size_t)M * ksub * dsub))
+      return fail(ANN_EFORMAT, "integer-grid flag set but centroids/codebooks are not integers");
+  }
+
+  // Row order: vectors grouped by first list, ascending external id inside.
+  std::vector<int32_t> pstart(nlist + 1, 0);
+  for (uint64_t v = 0; v < n; ++v) pstart[primary[v] + 1]++;
+  for (int l = 0; l < nlist; ++l) pstart[l + 1] += pstart[l];
+  std::vector<int32_t> fill(pstart.begin(), pstart.end() - 1);
+  std::vector<int32_t> row2ext(n), ext2row(n);
+  for (uint64_t v = 0; v < n; ++v) {
+    const int32_t row = fill[primary[v]]++;
+    row2ext[row] = (int32_t)v;
+    ext2row[v] = row;
+  }
+  // Replica entries and list / assignment consistency.
+  std::vector<int32_t> rstart(nlist + 1, 0);
+  std::vector<int2> rep;
+  rep.reserve(E - n);
+  for (int l = 0; l < nlist; ++l) {
+    rstart[l] = (int32_t)rep.size();
+    int64_t nprim = 0;
+    for (int64_t e = offs[l]; e < offs[l + 1]; ++e) {
+      const int32_t v = ent[e];
+      const int32_t* a = asg + (uint64_t)v * R;
+      int rank = -1;
+      for (int r = 0; r < R; ++r)
+        if (a[r] == l) rank = r;
+      if (rank < 0) return fail(ANN_EFORMAT, "list %d holds vector %d not assigned to it", l, v);
+      if (rank == 0) {
+        ++nprim;
+      } else {
+        rep.push_back(make_int2((int)((uint32_t)ext2row[v] | ((uint32_t)rank << kRankShift)), a[0]));
+      }
+    }
+    if (nprim != pstart[l + 1] - pstart[l])
+      return fail(ANN_EFORMAT, "list %d misses some of its first-list vectors", l);
+  }
+  rstart[nlist] = (int32_t)rep.size();
+
+  const int row_bytes = (M + 3) / 4 * 4;
+  const int es = elem_size(dtype);
+  std::vector<uint8_t> codes_rows((size_t)n * row_bytes, 0);
+  std::vector<uint8_t> vec_rows((size_t)n * dim * es);
+  std::vector<int32_t> asg_rows((size_t)n * R);
+  for (uint64_t row = 0; row < n; ++row) {
+    const uint64_t v = (uint64_t)row2ext[row];
+    std::memcpy(&codes_rows[row * row_bytes], codes + v * M, M);
+    std::memcpy(&vec_rows[row * dim * es], vecs + v * dim * es, (size_t)dim * es);
+    std::memcpy(&asg_rows[row * R], asg + v * R, (size_t)R * 4);
+  }
+  std::vector<float> cent_t((size_t)dim * nlist);
+  for (int l = 0; l < nlist; ++l)
+    for (int t = 0; t < dim; ++t) cent_t[(size_t)t * nlist + l] = cent[(size_t)l * dim + t];
+  int64_t max_list = 0;
+  for (int l = 0; l < nlist; ++l) max_list = std::max<int64_t>(max_list, offs[l + 1] - offs[l]);
+
+  std::unique_ptr<ann_index> ix(new ann_index());
+  ix->device = device;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(ANN_EDEVICE, "device %d not available", device);
+  HIP_TRY(hipSetDevice(device));
+  DevIndex& d = ix->d;
+  d.dtype = dtype; d.dim = dim; d.nlist = nlist; d.M = M; d.row_bytes = row_bytes; d.dsub = dsub;
+  d.R = R; d.int_grid = int_grid ? 1 : 0; d.n = (int64_t)n;
+  ann_status s;
+  const uint8_t* pc = nullptr;
+  const uint8_t* pv = nullptr;
+  const int2* prep = nullptr;
+  if ((s = dev_upload(ix.get(), codes_rows.data(), codes_rows.size(), &pc)) != ANN_OK) return s;
+  if ((s = dev_upload(ix.get(), vec_rows.data(), vec_rows.size(), &pv)) != ANN_OK) return s;
+  d.codes = pc;
+  d.vecs = pv;
+  if ((s = dev_upload(ix.get(), row2ext.data(), row2ext.size(), &d.row2ext)) != ANN_OK) return s;
+  if ((s = dev_upload(ix.get(), ext2row.data(), ext2row.size(), &d.ext2row)) != ANN_OK) return s;
+  if ((s = dev_upload(ix.get(), cent, (size_t)nlist * dim, &d.centroids)) != ANN_OK) return s;
+  if ((s = dev_upload(ix.get(), cent_t.data(), cent_t.size(), &d.centroids_t)) != ANN_OK) return s;
+  if ((s = dev_upload(ix.get(), cb, (size_t)M * ksub * dsub, &d.codebooks)) != ANN_OK) return s;
+  if ((s = dev_upload(ix.get(), pstart.data(), pstart.size(), &d.pstart)) != ANN_OK) return s;
+  if ((s = dev_upload(ix.get(), rstart.data(), rstart.size(), &d.rstart)) != ANN_OK) return s;
+  if ((s = dev_upload(ix.get(), rep.data(), rep.size(), &prep)) != ANN_OK) return s;
+  d.rep = prep;
+  if ((s = dev_upload(ix.get(), asg_rows.data(), asg_rows.size(), &d.assign_rows)) != ANN_OK)
+    return s;
+
+  ann_index_desc& ds = ix->desc;
+  ds.n = (int64_t)n; ds.dim = dim; ds.dtype = dtype; ds.nlist = nlist; ds.m = M; ds.ksub = ksub;
+  ds.dsub = dsub; ds.r = R; ds.int_grid = d.int_grid; ds.entries = (int64_t)E;
+  ds.replica_entries = (int64_t)rep.size(); ds.max_list = max_list; ds.device = device;
+  ds.max_rerank_n = kMaxRerank;
+  *out = ix.release();
+  return ANN_OK;
+}
+
+extern "C" ann_status ann_index_info(const ann_index* ix, ann_index_desc* out) {
+  if (!ix || !out) return fail(ANN_EINVAL, "NULL argument");
+  *out = ix->desc;
+  return ANN_OK;
+}
+
+extern "C" void ann_free_index(ann_index* ix) { delete ix; }
+
+namespace {
+
+ann_status run_pipeline(ann_index* ix, const float* Q, int64_t nq, const int32_t* nprobe,
+                        int32_t np_max, int32_t k, int32_t n, int64_t* out_ids, float* out_d,
+                        int32_t* topn_ids, float* topn_adc, int64_t* ncand, hipStream_t st) {
+  HIP_TRY(hipSetDevice(ix->device));
+  ann_status s;
+  if ((s = check_lds(ix, np_max, n)) != ANN_OK) return s;
+  const DevIndex& d = ix->d;
+  const int qc_max = chunk_queries(d, nq);
+  const LaunchCfg c0 = cfg_for(qc_max, np_max, n, k);
+  Workspace* ws = nullptr;
+  if ((s = ws_acquire(ix, need_for(d, qc_max, np_max, n, c0.smax), st, &ws)) != ANN_OK) return s;
+  WsGuard guard{ix, ws, st};
+  for (int64_t q0 = 0; q0 < nq; q0 += qc_max) {
+    const int qc = (int)std::min<int64_t>(qc_max, nq - q0);
+    const LaunchCfg c = cfg_for(qc, np_max, n, k);
+    const float* q = Q + q0 * d.dim;
+    HIP_TRY(launch_probe(d, q, nprobe ? nprobe + q0 : nullptr, np_max, qc, ws->w, nullptr,
+                         ws->w.lists, st));
+    HIP_TRY(launch_lut(d, q, qc, ws->w.lut, st));
+    HIP_TRY(launch_scan(d, ws->w.lists, ws->w.np_eff, ws->w.lut, c, ws->w, st));
+    HIP_TRY(launch_merge(d, q, c, ws->w, topn_ids ? topn_ids + q0 * n : nullptr,
+                         topn_adc ? topn_adc + q0 * n : nullptr, ncand ? ncand + q0 : nullptr,
+                         out_ids ? out_ids + q0 * k : nullptr, out_d ? out_d + q0 * k : nullptr,
+                         st));
+  }
+  return ANN_OK;
+}
+
+}  // namespace
+
+extern "C" ann_status ann_search(ann_index* ix, const float* d_queries, int64_t nq,
+                                 const int32_t* d_nprobe, int32_t nprobe_max, int32_t k,
+                                 int32_t rerank_n, int64_t* d_out_ids, float* d_out_dists,
+                                 void* stream) {
+  ann_status s = validate_args(ix, d_queries, nq, nprobe_max);
+  if (s != ANN_OK) return s;
+  if (k < 1) return fail(ANN_EINVAL, "k must be >= 1");
+  if (rerank_n < k || rerank_n > kMaxRerank)
+    return fail(ANN_EINVAL, "rerank_n must be in [k, %d]", kMaxRerank);
+  if (nq > 0 && (!d_out_ids || !d_out_dists)) return fail(ANN_EINVAL, "output pointer is NULL");
+  if (nq == 0) return ANN_OK;
+  return run_pipeline(ix, d_queries, nq, d_nprobe, nprobe_max, k, rerank_n, d_out_ids,
+                      d_out_dists, nullptr, nullptr, nullptr, (hipStream_t)stream);
+}
+
+extern "C" ann_status ann_search_topn(ann_index* ix, const float* d_queries, int64_t nq,
+                                      const int32_t* d_nprobe, int32_t nprobe_max,
+                                      int32_t rerank_n, int32_t* d_out_ids, float* d_out_adc,
+                                      int64_t* d_out_ncand, void* stream) {
+  ann_status s = validate_args(ix, d_queries, nq, nprobe_max);
+  if (s != ANN_OK) return s;
+  if (rerank_n < 1 || rerank_n > kMaxRerank)
+    return fail(ANN_EINVAL, "rerank_n must be in [1, %d]", kMaxRerank);
+  if (nq > 0 && (!d_out_ids || !d_out_adc)) return fail(ANN_EINVAL, "output pointer is NULL");
+  if (nq == 0) return ANN_OK;
+  return run_pipeline(ix, d_queries, nq, d_nprobe, nprobe_max, 1, rerank_n, nullptr, nullptr,
+                      d_out_ids, d_out_adc, d_out_ncand, (hipStream_t)stream);
+}
+
+extern "C" ann_status ann_probe(ann_index* ix, const float* d_queries, int64_t nq,
+                                const int32_t* d_nprobe, int32_t nprobe_max, int32_t* d_out_lists,
+                                float* d_out_dists, void* stream) {
+  ann_status s = validate_args(ix, d_queries, nq, nprobe_max);
+  if (s != ANN_OK) return s;
+  if (nq > 0 && !d_out_lists) return fail(ANN_EINVAL, "output pointer is NULL");
+  if (nq == 0) return ANN_OK;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ix->device));
+  const int qc_max = chunk_queries(ix->d, nq);
+  Workspace* ws = nullptr;
+  if ((s = ws_acquire(ix, need_for(ix->d, qc_max, nprobe_max, 1, 1), st, &ws)) != ANN_OK) return s;
+  WsGuard guard{ix, ws, st};
+  for (int64_t q0 = 0; q0 < nq; q0 += qc_max) {
+    const int qc = (int)std::min<int64_t>(qc_max, nq - q0);
+    HIP_TRY(launch_probe(ix->d, d_queries + q0 * ix->d.dim, d_nprobe ? d_nprobe + q0 : nullptr,
+                         nprobe_max, qc, ws->w, d_out_dists ? d_out_dists + q0 * nprobe_max : nullptr,
+                         d_out_lists + q0 * nprobe_max, st));
+  }
+  return ANN_OK;
+}
+
+extern "C" ann_status ann_lut(ann_index* ix, const float* d_queries, int64_t nq, float* d_out_lut,
+                              void* stream) {
+  if (!ix) return fail(ANN_EINVAL, "index is NULL");
+  if (nq < 0) return fail(ANN_EINVAL, "nq < 0");
+  if (nq > 0 && (!d_queries || !d_out_lut)) return fail(ANN_EINVAL, "NULL pointer");
+  HIP_TRY(hipSetDevice(ix->device));
+  const int64_t step = 65535;
+  for (int64_t q0 = 0; q0 < nq; q0 += step) {
+    const int qc = (int)std::min<int64_t>(step, nq - q0);
+    HIP_TRY(launch_lut(ix->d, d_queries + q0 * ix->d.dim, qc,
+                       d_out_lut + q0 * (int64_t)ix->d.M * kKsub, (hipStream_t)stream));
+  }
+  return ANN_OK;
+}
+
+extern "C" ann_status ann_scan_trace(ann_index* ix, const int32_t* d_lists, int64_t nq,
+                                     int32_t nprobe_max, const float* d_lut, int64_t capacity,
+                                     int32_t* d_out_ids, float* d_out_adc, int64_t* d_out_count,
+                                     void* stream) {
+  ann_status s = validate_args(ix, d_lists, nq, nprobe_max);
+  if (s != ANN_OK) return s;
+  if (capacity < 0) return fail(ANN_EINVAL, "capacity < 0");
+  if (nq > 0 && (!d_lut || !d_out_count || (capacity > 0 && (!d_out_ids || !d_out_adc))))
+    return fail(ANN_EINVAL, "NULL pointer");
+  if (nq == 0) return ANN_OK;
+  if (nq > (1 << 24)) return fail(ANN_EINVAL, "nq too large for the trace form");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ix->device));
+  if ((s = check_lds(ix, nprobe_max, 1)) != ANN_OK) return s;
+  Workspace* ws = nullptr;
+  Need nd = need_for(ix->d, (int)nq, nprobe_max, 1, 16);
+  nd.nlist = 0;
+  nd.lut = 0;
+  if ((s = ws_acquire(ix, nd, st, &ws)) != ANN_OK) return s;
+  WsGuard guard{ix, ws, st};
+  HIP_TRY(launch_scan_trace(ix->d, d_lists, d_lut, (int)nq, nprobe_max, capacity, d_out_ids,
+                            d_out_adc, d_out_count, ws->w, st));
+  return ANN_OK;
+}
+
+extern "C" ann_status ann_rerank(ann_index* ix, const float* d_queries, int64_t nq,
+                                 const int32_t* d_cand_ids, int32_t n, int32_t k,
+                                 int64_t* d_out_ids, float* d_out_dists, void* stream) {
+  if (!ix) return fail(ANN_EINVAL, "index is NULL");
+  if (nq < 0) return fail(ANN_EINVAL, "nq < 0");
+  if (k < 1 || n < k || n > kMaxRerank) return fail(ANN_EINVAL, "need 1 <= k <= n <= %d", kMaxRerank);
+  if (nq > 0 && (!d_queries || !d_cand_ids || !d_out_ids || !d_out_dists))
+    return fail(ANN_EINVAL, "NULL pointer");
+  HIP_TRY(hipSetDevice(ix->device));
+  const int64_t step = 1 << 20;
+  for (int64_t q0 = 0; q0 < nq; q0 += step) {
+    const int qc = (int)std::min<int64_t>(step, nq - q0);
+    HIP_TRY(launch_rerank_only(ix->d, d_queries + q0 * ix->d.dim, d_cand_ids + q0 * n, qc, n, k,
+                               d_out_ids + q0 * k, d_out_dists + q0 * k, (hipStream_t)stream));
+  }
+  return ANN_OK;
+}

@@ -1,0 +1,83 @@
+// Internal declarations shared by the C-ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ann {
+
+enum DType : int { F32 = 0, U8 = 1, I8 = 2 };
+
+constexpr int kKsub = 256;
+constexpr int kBlock = 256;           // threads per block of every kernel
+constexpr int kMaxRerank = 1024;      // largest rerank_n
+constexpr int kMaxM = 64;             // largest number of PQ subspaces
+constexpr int kMaxDim = 2048;
+constexpr int kRankShift = 28;        // replica entry: row | rank << 28
+constexpr uint32_t kRowMask = (1u << kRankShift) - 1;
+
+// Device view of a loaded index.  Rows are the vectors reordered by their
+// first (nearest) posting list; a list's first-list members are one
+// contiguous row range, its other members ("replica entries") are explicit.
+struct DevIndex {
+  int dtype, dim, nlist, M, row_bytes, dsub, R, int_grid;
+  int64_t n;
+  const uint8_t* codes;       // [n, row_bytes] PQ codes by row (M used bytes)
+  const void* vecs;           // [n, dim] raw vectors by row
+  const int32_t* row2ext;     // [n]
+  const int32_t* ext2row;     // [n]
+  const float* centroids;     // [nlist, dim]
+  const float* centroids_t;   // [dim, nlist]
+  const float* codebooks;     // [M, 256, dsub]
+  const int32_t* pstart;      // [nlist + 1] first-list row ranges
+  const int32_t* rstart;      // [nlist + 1] replica entry ranges
+  const int2* rep;            // [replica entries] {row | rank << 28, first list of the vector}
+  const int32_t* assign_rows; // [n, R] lists of each row, nearest first, -1 padded
+};
+
+// Per-call working buffers (one block of the memory pool).
+struct Work {
+  float* dist = nullptr;        // [qc, nlist] coarse distances
+  int32_t* lists = nullptr;     // [qc, np_max]
+  int32_t* np_eff = nullptr;    // [qc]
+  float* lut = nullptr;         // [qc, M, 256]
+  int64_t* eq = nullptr;        // [qc] entries per query
+  int32_t* sq = nullptr;        // [qc] work items per query
+  uint64_t* pkeys = nullptr;    // [qc, smax, n] partial top-n keys
+  int32_t* pcount = nullptr;    // [qc, smax]
+  int32_t* pscan = nullptr;     // [qc, smax] candidates scored per item
+  int32_t* cand = nullptr;      // [qc, n] (rerank-only entry point)
+};
+
+struct LaunchCfg {
+  int qc;          // queries in this chunk
+  int np_max;
+  int n;           // rerank_n (top-n size)
+  int k;
+  int smax;        // work items per query (max)
+  int tile;        // target entries per work item
+  int round_steps; // entries per thread between compaction checks
+};
+
+// Kernel launchers (ann_kernels.hip).  All enqueue on `st` and return hipError_t.
+hipError_t launch_probe(const DevIndex& ix, const float* q, const int32_t* nprobe, int np_max,
+                        int qc, Work& w, float* out_dists_opt, int32_t* out_lists,
+                        hipStream_t st);
+hipError_t launch_lut(const DevIndex& ix, const float* q, int qc, float* out_lut, hipStream_t st);
+hipError_t launch_scan(const DevIndex& ix, const int32_t* lists, const int32_t* np_eff,
+                       const float* lut, const LaunchCfg& c, Work& w, hipStream_t st);
+hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const float* lut, int qc,
+                             int np_max, int64_t capacity, int32_t* out_ids, float* out_adc,
+                             int64_t* out_count, Work& w, hipStream_t st);
+hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,
+                        int32_t* topn_ids, float* topn_adc, int64_t* ncand, int64_t* out_ids,
+                        float* out_dists, hipStream_t st);
+hipError_t launch_rerank_only(const DevIndex& ix, const float* q, const int32_t* cand, int qc,
+                              int n, int k, int64_t* out_ids, float* out_dists, hipStream_t st);
+
+// Sizes of the dynamic LDS areas (bytes) for the scan kernel.
+size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n, int round_steps);
+int scan_smax(int n);
+
+}  // namespace ann

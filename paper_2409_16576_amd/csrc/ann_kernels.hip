@@ -1,0 +1,867 @@
+// HIP kernels (gfx950) of the IVF-PQ filtering stage.
+//
+//   k_probe_dist   step 2: squared distances of each query to every list centroid
+//   k_probe_select step 2: the nprobe nearest lists, ascending by (distance, list)
+//   k_lut          step 1: per-query distance table, entry = ||q_m - c_{m,j}||^2 (Sec. 2.2)
+//   k_plan         splits each query's gathered entries into work items
+//   k_scan         steps 3, 5, 6, 7 fused: walk the probed lists, drop replica
+//                  entries owned by an earlier probed list (dedup), Eq. 1 by
+//                  table lookups from LDS, keep the n best (distance, id) keys
+//   k_merge        step 7 across a query's work items, then step 8: exact
+//                  squared L2 of the n survivors, top-k
+//
+// Arithmetic contract (what makes the results bit-identical to the CPU
+// oracle): every distance that decides a selection is a float32 value that is
+// either an exact integer (uint8/int8 data on an integer-grid index: all
+// partial sums are integers below 2^24) or a float64 sum over dimensions in
+// ascending order, rounded once to float32; the Eq. 1 sum is a float32 sum
+// over subspaces m = 0..M-1 in order from +0.0f.  No fused multiply-add is
+// formed anywhere in this file.  Selections order by 64-bit keys
+// (order-preserving bits of the float32 distance, id), so ties go to the
+// lower id.
+#pragma clang fp contract(off)
+
+#include <algorithm>
+#include <utility>
+
+#include "ann_internal.h"
+
+namespace ann {
+namespace {
+
+__device__ __forceinline__ uint32_t ord32(float f) {
+  const uint32_t b = __float_as_uint(f + 0.0f);  // -0 -> +0
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ float unord32(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__device__ __forceinline__ float conv_query(float v, int dtype) {
+  if (dtype == U8) return fminf(fmaxf(rintf(v), 0.f), 255.f);
+  if (dtype == I8) return fminf(fmaxf(rintf(v), -128.f), 127.f);
+  return v;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(v, d, 64);
+    if (lane_id() >= d) v += t;
+  }
+  return v;
+}
+
+__host__ __device__ inline int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+__host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// Block-wide selection of the want-th smallest of cnt distinct 64-bit keys
+// (MSD radix, 8-bit digits, early exit once the digit bucket holds one key).
+
+struct SelScratch {
+  uint32_t hist[256];
+  uint64_t prefix;
+  uint64_t found;
+  int want;
+  int done;
+};
+
+template <class G>
+__device__ uint64_t block_kth(G get, int cnt, int want, SelScratch* s) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s->prefix = 0;
+    s->want = want;
+    s->done = 0;
+  }
+  uint64_t mask = 0;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int i = tid; i < 256; i += blockDim.x) s->hist[i] = 0;
+    __syncthreads();
+    const uint64_t prefix = s->prefix;
+    for (int i = tid; i < cnt; i += blockDim.x) {
+      const uint64_t k = get(i);
+      if ((k & mask) == prefix) atomicAdd(&s->hist[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    const uint32_t w = (uint32_t)s->want;
+    if (tid < 64) {
+      const uint32_t h0 = s->hist[4 * tid], h1 = s->hist[4 * tid + 1];
+      const uint32_t h2 = s->hist[4 * tid + 2], h3 = s->hist[4 * tid + 3];
+      const uint32_t sum = h0 + h1 + h2 + h3;
+      const uint32_t incl = wave_incl_scan(sum);
+      const uint32_t excl = incl - sum;
+      if (excl < w && w <= incl) {
+        uint32_t r = w - excl;
+        int b = 4 * tid;
+        uint32_t hb = h0;
+        if (r > h0) {
+          r -= h0; b += 1; hb = h1;
+          if (r > h1) {
+            r -= h1; b += 1; hb = h2;
+            if (r > h2) { r -= h2; b += 1; hb = h3; }
+          }
+        }
+        s->want = (int)r;
+        s->prefix = prefix | ((uint64_t)b << shift);
+        s->done = (hb == 1u);
+      }
+    }
+    __syncthreads();
+    mask |= (255ull << shift);
+    if (s->done) break;
+  }
+  const uint64_t prefix = s->prefix;
+  for (int i = tid; i < cnt; i += blockDim.x) {
+    const uint64_t k = get(i);
+    if ((k & mask) == prefix) s->found = k;
+  }
+  __syncthreads();
+  const uint64_t r = s->found;
+  __syncthreads();
+  return r;
+}
+
+// Ascending bitonic sort of s[0..p), p a power of two.
+__device__ void block_bitonic(uint64_t* s, int p) {
+  for (int k = 2; k <= p; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < p; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = s[i], b = s[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            s[i] = b;
+            s[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 2a: coarse distances.  One thread per list, QT queries per block; the
+// centroids are read transposed so consecutive threads read consecutive
+// addresses.  EXACT64: float64 sum over t in order (float data); otherwise
+// float32, exact on integer-grid indexes.
+
+constexpr int kProbeQT = 8;
+
+template <bool EXACT64>
+__global__ __launch_bounds__(kBlock) void k_probe_dist(DevIndex ix, const float* __restrict__ Q,
+                                                        int qc, float* __restrict__ dist) {
+  extern __shared__ float s_q[];  // [kProbeQT, dim]
+  const int D = ix.dim;
+  const int q0 = blockIdx.y * kProbeQT;
+  for (int i = threadIdx.x; i < kProbeQT * D; i += kBlock) {
+    const int qq = q0 + i / D;
+    s_q[i] = qq < qc ? conv_query(Q[(size_t)qq * D + (i % D)], ix.dtype) : 0.f;
+  }
+  __syncthreads();
+  const int l = blockIdx.x * kBlock + threadIdx.x;
+  if (l >= ix.nlist) return;
+  const float* ct = ix.centroids_t + l;
+  if (EXACT64) {
+    double acc[kProbeQT];
+#pragma unroll
+    for (int i = 0; i < kProbeQT; ++i) acc[i] = 0.0;
+    for (int t = 0; t < D; ++t) {
+      const double c = (double)ct[(size_t)t * ix.nlist];
+#pragma unroll
+      for (int i = 0; i < kProbeQT; ++i) {
+        const double u = (double)s_q[i * D + t] - c;
+        const double sq = u * u;
+        acc[i] = acc[i] + sq;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kProbeQT; ++i)
+      if (q0 + i < qc) dist[(size_t)(q0 + i) * ix.nlist + l] = (float)acc[i];
+  } else {
+    float acc[kProbeQT];
+#pragma unroll
+    for (int i = 0; i < kProbeQT; ++i) acc[i] = 0.f;
+    for (int t = 0; t < D; ++t) {
+      const float c = ct[(size_t)t * ix.nlist];
+#pragma unroll
+      for (int i = 0; i < kProbeQT; ++i) {
+        const float u = s_q[i * D + t] - c;
+        acc[i] = acc[i] + u * u;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kProbeQT; ++i)
+      if (q0 + i < qc) dist[(size_t)(q0 + i) * ix.nlist + l] = acc[i];
+  }
+}
+
+// Step 2b: per query, the np smallest (distance, list) keys, sorted.
+__global__ __launch_bounds__(kBlock) void k_probe_select(const float* __restrict__ dist, int nlist,
+                                                          const int32_t* __restrict__ nprobe,
+                                                          int np_max, int32_t* __restrict__ lists,
+                                                          float* __restrict__ out_d,
+                                                          int32_t* __restrict__ np_eff) {
+  extern __shared__ uint64_t s_sel[];  // [pow2(np_max)]
+  __shared__ SelScratch ss;
+  __shared__ int s_cnt;
+  const int q = blockIdx.x, tid = threadIdx.x;
+  int np = nprobe ? nprobe[q] : np_max;
+  np = max(0, min(np, min(np_max, nlist)));
+  const int P = pow2_at_least(max(np, 1));
+  const float* row = dist + (size_t)q * nlist;
+  auto get = [&](int i) -> uint64_t { return ((uint64_t)ord32(row[i]) << 32) | (uint32_t)i; };
+  if (np > 0) {
+    const uint64_t K = (np == nlist) ? ~0ull : block_kth(get, nlist, np, &ss);
+    if (tid == 0) s_cnt = 0;
+    for (int i = np + tid; i < P; i += kBlock) s_sel[i] = ~0ull;
+    __syncthreads();
+    for (int i = tid; i < nlist; i += kBlock) {
+      const uint64_t k = get(i);
+      if (k <= K) {
+        const int pos = atomicAdd(&s_cnt, 1);
+        if (pos < P) s_sel[pos] = k;
+      }
+    }
+    __syncthreads();
+    block_bitonic(s_sel, P);
+  }
+  for (int p = tid; p < np_max; p += kBlock) {
+    const bool v = p < np;
+    lists[(size_t)q * np_max + p] = v ? (int32_t)(uint32_t)s_sel[p] : -1;
+    if (out_d) out_d[(size_t)q * np_max + p] = v ? unord32((uint32_t)(s_sel[p] >> 32)) : INFINITY;
+  }
+  if (tid == 0) np_eff[q] = np;
+}
+
+__global__ void k_zero_i64(int64_t* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Number of leading non-negative list ids (for caller-provided list arrays).
+__global__ void k_count_lists(const int32_t* __restrict__ lists, int qc, int np_max, int nlist,
+                              int32_t* __restrict__ np_eff) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= qc) return;
+  int c = 0;
+  while (c < np_max) {
+    const int l = lists[(size_t)q * np_max + c];
+    if (l < 0 || l >= nlist) break;
+    ++c;
+  }
+  np_eff[q] = c;
+}
+
+// ---------------------------------------------------------------------------
+// Step 1: distance table.  Block (m, q), thread j = codeword.
+
+template <bool EXACT64>
+__global__ __launch_bounds__(kBlock) void k_lut(DevIndex ix, const float* __restrict__ Q, int qc,
+                                                 float* __restrict__ lut) {
+  const int m = blockIdx.x, q = blockIdx.y, j = threadIdx.x;
+  const float* qs = Q + (size_t)q * ix.dim + (size_t)m * ix.dsub;
+  const float* c = ix.codebooks + ((size_t)m * kKsub + j) * ix.dsub;
+  float out;
+  if (EXACT64) {
+    double acc = 0.0;
+    for (int t = 0; t < ix.dsub; ++t) {
+      const double u = (double)conv_query(qs[t], ix.dtype) - (double)c[t];
+      const double sq = u * u;
+      acc = acc + sq;
+    }
+    out = (float)acc;
+  } else {
+    float acc = 0.f;
+    for (int t = 0; t < ix.dsub; ++t) {
+      const float u = conv_query(qs[t], ix.dtype) - c[t];
+      acc = acc + u * u;
+    }
+    out = acc;
+  }
+  lut[((size_t)q * ix.M + m) * kKsub + j] = out;
+}
+
+// ---------------------------------------------------------------------------
+// Work planning: entries per query and number of work items.
+
+__global__ void k_plan(DevIndex ix, const int32_t* __restrict__ lists,
+                       const int32_t* __restrict__ np_eff, int np_max, int qc, int tile, int smax,
+                       int64_t* __restrict__ eq, int32_t* __restrict__ sq) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= qc) return;
+  int64_t e = 0;
+  const int np = np_eff[q];
+  for (int p = 0; p < np; ++p) {
+    const int l = lists[(size_t)q * np_max + p];
+    e += (int64_t)(ix.pstart[l + 1] - ix.pstart[l]) + (ix.rstart[l + 1] - ix.rstart[l]);
+  }
+  eq[q] = e;
+  const int64_t s = (e + tile - 1) / tile;
+  sq[q] = (int)max((int64_t)1, min((int64_t)smax, s));
+}
+
+// ---------------------------------------------------------------------------
+// Steps 3, 5, 6, 7: the fused scan.
+
+struct ScanLayout {
+  size_t lut, bits, list, pst, pcnt, rst, pre, buf, tmp, sel, misc, total;
+};
+
+__host__ __device__ inline ScanLayout scan_layout(int M, int nlist, int R, int np_max, int n,
+                                                  int cap) {
+  ScanLayout L;
+  size_t o = 0;
+  L.lut = o; o += (size_t)M * kKsub * 4; o = align_up(o, 16);
+  L.bits = o; o += (R > 1 ? (size_t)((nlist + 31) / 32) * 4 : 0); o = align_up(o, 16);
+  L.list = o; o += (size_t)np_max * 4;
+  L.pst = o; o += (size_t)np_max * 4;
+  L.pcnt = o; o += (size_t)np_max * 4;
+  L.rst = o; o += (size_t)np_max * 4; o = align_up(o, 16);
+  L.pre = o; o += (size_t)(np_max + 1) * 8; o = align_up(o, 16);
+  L.buf = o; o += (size_t)cap * 8;
+  L.tmp = o; o += (size_t)n * 8; o = align_up(o, 16);
+  L.sel = o; o += sizeof(SelScratch); o = align_up(o, 16);
+  L.misc = o; o += 32;
+  L.total = align_up(o, 16);
+  return L;
+}
+
+struct ScanMisc {
+  uint64_t thr;
+  int count;
+  int ncount;
+  int scanned;
+  int pad;
+};
+
+__device__ __forceinline__ bool testbit(const uint32_t* bits, int l) {
+  return (bits[l >> 5] >> (l & 31)) & 1u;
+}
+
+// Eq. 1 for one code row: float32 sum over m = 0..M-1 in order.
+template <int W>
+__device__ __forceinline__ float adc_row(const uint8_t* __restrict__ rowp,
+                                         const float* __restrict__ s_lut, int M) {
+  uint32_t w[W];
+  if constexpr (W % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < W / 4; ++i) {
+      const uint4 v = reinterpret_cast<const uint4*>(rowp)[i];
+      w[4 * i] = v.x; w[4 * i + 1] = v.y; w[4 * i + 2] = v.z; w[4 * i + 3] = v.w;
+    }
+  } else if constexpr (W % 2 == 0) {
+#pragma unroll
+    for (int i = 0; i < W / 2; ++i) {
+      const uint2 v = reinterpret_cast<const uint2*>(rowp)[i];
+      w[2 * i] = v.x; w[2 * i + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < W; ++i) w[i] = reinterpret_cast<const uint32_t*>(rowp)[i];
+  }
+  float acc = 0.f;
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int m = 4 * i + b;
+      if (i < W - 1 || m < M) acc = acc + s_lut[m * kKsub + ((w[i] >> (8 * b)) & 255u)];
+    }
+  }
+  return acc;
+}
+
+// Reduce s_buf[0..count) to its n smallest keys; threshold = the n-th key.
+__device__ void scan_compact(uint64_t* s_buf, uint64_t* s_tmp, SelScratch* ss, ScanMisc* mc, int n) {
+  const int cnt = mc->count;
+  if (cnt <= n) return;
+  const uint64_t K = block_kth([&](int i) { return s_buf[i]; }, cnt, n, ss);
+  if (threadIdx.x == 0) mc->ncount = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += kBlock) {
+    const uint64_t k = s_buf[i];
+    if (k <= K) {
+      const int pos = atomicAdd(&mc->ncount, 1);
+      if (pos < n) s_tmp[pos] = k;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) s_buf[i] = s_tmp[i];
+  if (threadIdx.x == 0) {
+    mc->count = n;
+    mc->thr = K;
+  }
+  __syncthreads();
+}
+
+template <int W, bool TRACE>
+__global__ __launch_bounds__(kBlock) void k_scan(
+    DevIndex ix, const int32_t* __restrict__ lists, const int32_t* __restrict__ np_eff, int np_max,
+    int qc, const float* __restrict__ lut, const int32_t* __restrict__ sq, int smax, int n, int cap,
+    int round_steps, uint64_t* __restrict__ pkeys, int32_t* __restrict__ pcount,
+    int32_t* __restrict__ pscan, int64_t t_capacity, int32_t* __restrict__ t_ids,
+    float* __restrict__ t_adc, unsigned long long* __restrict__ t_count) {
+  // Block -> (query, item) with all items of one query on the same XCD:
+  // blocks are dispatched round-robin over the 8 XCDs.
+  const int b = blockIdx.x;
+  const int xcd = b & 7, slot = b >> 3;
+  const int q = (slot / smax) * 8 + xcd;
+  const int j = slot % smax;
+  if (q >= qc) return;
+  const int S = sq[q];
+  if (j >= S) return;
+  const int tid = threadIdx.x;
+  const int M = ix.M;
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  const ScanLayout L = scan_layout(M, ix.nlist, ix.R, np_max, n, cap);
+  float* s_lut = reinterpret_cast<float*>(smem + L.lut);
+  uint32_t* s_bits = reinterpret_cast<uint32_t*>(smem + L.bits);
+  int32_t* s_list = reinterpret_cast<int32_t*>(smem + L.list);
+  int32_t* s_pst = reinterpret_cast<int32_t*>(smem + L.pst);
+  int32_t* s_pcnt = reinterpret_cast<int32_t*>(smem + L.pcnt);
+  int32_t* s_rst = reinterpret_cast<int32_t*>(smem + L.rst);
+  int64_t* s_pre = reinterpret_cast<int64_t*>(smem + L.pre);
+  uint64_t* s_buf = reinterpret_cast<uint64_t*>(smem + L.buf);
+  uint64_t* s_tmp = reinterpret_cast<uint64_t*>(smem + L.tmp);
+  SelScratch* ss = reinterpret_cast<SelScratch*>(smem + L.sel);
+  ScanMisc* mc = reinterpret_cast<ScanMisc*>(smem + L.misc);
+
+  // Distance table of this query into LDS.
+  {
+    const float4* src = reinterpret_cast<const float4*>(lut + (size_t)q * M * kKsub);
+    float4* dst = reinterpret_cast<float4*>(s_lut);
+    for (int i = tid; i < M * (kKsub / 4); i += kBlock) dst[i] = src[i];
+  }
+  const int nwords = (ix.nlist + 31) / 32;
+  if (ix.R > 1)
+    for (int i = tid; i < nwords; i += kBlock) s_bits[i] = 0u;
+  const int np = np_eff[q];
+  for (int p = tid; p < np; p += kBlock) {
+    const int l = lists[(size_t)q * np_max + p];
+    const int a = ix.pstart[l];
+    s_list[p] = l;
+    s_pst[p] = a;
+    s_pcnt[p] = ix.pstart[l + 1] - a;
+    s_rst[p] = ix.rstart[l];
+  }
+  if (tid == 0) {
+    mc->thr = ~0ull;
+    mc->count = 0;
+    mc->scanned = 0;
+  }
+  __syncthreads();
+  if (ix.R > 1)
+    for (int p = tid; p < np; p += kBlock) {
+      const int l = s_list[p];
+      atomicOr(&s_bits[l >> 5], 1u << (l & 31));
+    }
+  if (tid == 0) {
+    int64_t acc = 0;
+    for (int p = 0; p < np; ++p) {
+      s_pre[p] = acc;
+      acc += (int64_t)s_pcnt[p] + (ix.rstart[s_list[p] + 1] - s_rst[p]);
+    }
+    s_pre[np] = acc;
+  }
+  __syncthreads();
+
+  const int64_t E = s_pre[np];
+  const int64_t e0 = E * j / S, e1 = E * (j + 1) / S;
+  const int lane = tid & 63;
+  const uint64_t lanemask = (1ull << lane) - 1ull;
+  int scanned = 0;
+
+  for (int64_t base = e0; base < e1; base += (int64_t)kBlock * round_steps) {
+    const uint64_t thr = mc->thr;
+    const uint32_t thr_hi = (uint32_t)(thr >> 32);
+    for (int u = 0; u < round_steps; ++u) {
+      const int64_t e = base + (int64_t)u * kBlock + tid;
+      bool keep = false;
+      int row = 0;
+      if (e < e1) {
+        int lo = 0, hi = np - 1;  // last p with s_pre[p] <= e
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const int64_t o = e - s_pre[lo];
+        if (o < s_pcnt[lo]) {
+          row = s_pst[lo] + (int)o;
+          keep = true;
+        } else {
+          const int2 r = ix.rep[s_rst[lo] + (o - s_pcnt[lo])];
+          row = (int)((uint32_t)r.x & kRowMask);
+          const int rank = (int)((uint32_t)r.x >> kRankShift);
+          keep = !testbit(s_bits, r.y);
+          for (int i = 1; i < rank && keep; ++i)
+            keep = !testbit(s_bits, ix.assign_rows[(size_t)row * ix.R + i]);
+        }
+      }
+      float acc = 0.f;
+      if (keep) acc = adc_row<W>(ix.codes + (size_t)row * ix.row_bytes, s_lut, M);
+      scanned += keep ? 1 : 0;
+      if constexpr (TRACE) {
+        const uint64_t m = __ballot(keep);
+        if (m) {
+          unsigned long long bpos = 0;
+          if (lane == 0) bpos = atomicAdd(&t_count[q], (unsigned long long)__popcll(m));
+          bpos = __shfl(bpos, 0, 64);
+          if (keep) {
+            const unsigned long long pos = bpos + __popcll(m & lanemask);
+            if ((int64_t)pos < t_capacity) {
+              t_ids[(size_t)q * t_capacity + pos] = ix.row2ext[row];
+              t_adc[(size_t)q * t_capacity + pos] = acc;
+            }
+          }
+        }
+      } else {
+        bool pass = false;
+        uint64_t key = 0;
+        if (keep) {
+          const uint32_t h = ord32(acc);
+          if (h <= thr_hi) {
+            key = ((uint64_t)h << 32) | (uint32_t)ix.row2ext[row];
+            pass = key < thr;
+          }
+        }
+        const uint64_t m = __ballot(pass);
+        if (m) {
+          int bpos = 0;
+          if (lane == 0) bpos = atomicAdd(&mc->count, (int)__popcll(m));
+          bpos = __shfl(bpos, 0, 64);
+          if (pass) s_buf[bpos + __popcll(m & lanemask)] = key;
+        }
+      }
+    }
+    __syncthreads();
+    if constexpr (!TRACE) {
+      if (mc->count > cap - kBlock * round_steps) scan_compact(s_buf, s_tmp, ss, mc, n);
+    }
+  }
+  // candidates scored by this item
+  {
+    int v = scanned;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (lane == 0) atomicAdd(&mc->scanned, v);
+  }
+  __syncthreads();
+  if constexpr (!TRACE) {
+    scan_compact(s_buf, s_tmp, ss, mc, n);
+    const int cnt = min(mc->count, n);
+    uint64_t* dst = pkeys + ((size_t)q * smax + j) * n;
+    for (int i = tid; i < cnt; i += kBlock) dst[i] = s_buf[i];
+    if (tid == 0) {
+      pcount[(size_t)q * smax + j] = cnt;
+      pscan[(size_t)q * smax + j] = mc->scanned;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 8: exact squared distance of one raw row (float64 in order for float
+// data, exact integers for uint8/int8).
+
+__device__ __forceinline__ float exact_row(const DevIndex& ix, const float* __restrict__ s_q,
+                                           int row) {
+  const int D = ix.dim;
+  if (ix.dtype == F32) {
+    const float* x = static_cast<const float*>(ix.vecs) + (size_t)row * D;
+    double acc = 0.0;
+    for (int t = 0; t < D; ++t) {
+      const double u = (double)s_q[t] - (double)x[t];
+      const double sq = u * u;
+      acc = acc + sq;
+    }
+    return (float)acc;
+  }
+  int acc = 0;
+  if (ix.dtype == U8) {
+    const uint8_t* x = static_cast<const uint8_t*>(ix.vecs) + (size_t)row * D;
+    for (int t = 0; t < D; ++t) {
+      const int u = (int)s_q[t] - (int)x[t];
+      acc += u * u;
+    }
+  } else {
+    const int8_t* x = static_cast<const int8_t*>(ix.vecs) + (size_t)row * D;
+    for (int t = 0; t < D; ++t) {
+      const int u = (int)s_q[t] - (int)x[t];
+      acc += u * u;
+    }
+  }
+  return (float)acc;
+}
+
+// Re-rank s_top[0..nn) (keys of (adc, id)) by exact distance and write top-k.
+__device__ void rerank_write(const DevIndex& ix, const float* s_q, const uint64_t* s_top, int nn,
+                             uint64_t* s_key2, int P, int k, int64_t* out_ids, float* out_d) {
+  for (int i = threadIdx.x; i < P; i += kBlock) {
+    uint64_t key = ~0ull;
+    if (i < nn) {
+      const uint32_t id = (uint32_t)s_top[i];
+      const float e = exact_row(ix, s_q, ix.ext2row[id]);
+      key = ((uint64_t)ord32(e) << 32) | id;
+    }
+    s_key2[i] = key;
+  }
+  __syncthreads();
+  block_bitonic(s_key2, P);
+  for (int i = threadIdx.x; i < k; i += kBlock) {
+    const bool v = i < nn;
+    out_ids[i] = v ? (int64_t)(uint32_t)s_key2[i] : -1;
+    out_d[i] = v ? unord32((uint32_t)(s_key2[i] >> 32)) : INFINITY;
+  }
+}
+
+struct MergeLayout {
+  size_t keys, top, key2, q, sel, misc, total;
+};
+
+__host__ __device__ inline MergeLayout merge_layout(int smax, int n, int dim) {
+  MergeLayout L;
+  const int P = pow2_at_least(n);
+  size_t o = 0;
+  L.keys = o; o += (size_t)smax * n * 8;
+  L.top = o; o += (size_t)P * 8;
+  L.key2 = o; o += (size_t)P * 8;
+  L.q = o; o += (size_t)dim * 4; o = align_up(o, 16);
+  L.sel = o; o += sizeof(SelScratch); o = align_up(o, 16);
+  L.misc = o; o += 16 + 4 * 17;
+  L.total = align_up(o, 16);
+  return L;
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge(
+    DevIndex ix, const float* __restrict__ Q, int qc, const int32_t* __restrict__ sq, int smax,
+    int n, int k, const uint64_t* __restrict__ pkeys, const int32_t* __restrict__ pcount,
+    const int32_t* __restrict__ pscan, int32_t* __restrict__ topn_ids, float* __restrict__ topn_adc,
+    int64_t* __restrict__ ncand, int64_t* __restrict__ out_ids, float* __restrict__ out_dists) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const MergeLayout L = merge_layout(smax, n, ix.dim);
+  uint64_t* s_keys = reinterpret_cast<uint64_t*>(smem + L.keys);
+  uint64_t* s_top = reinterpret_cast<uint64_t*>(smem + L.top);
+  uint64_t* s_key2 = reinterpret_cast<uint64_t*>(smem + L.key2);
+  float* s_q = reinterpret_cast<float*>(smem + L.q);
+  SelScratch* ss = reinterpret_cast<SelScratch*>(smem + L.sel);
+  int* s_cnt = reinterpret_cast<int*>(smem + L.misc);
+  int* s_off = s_cnt + 1;  // [smax + 1] (smax <= 16)
+  const int q = blockIdx.x, tid = threadIdx.x;
+  const int S = sq[q];
+  const int P = pow2_at_least(n);
+  for (int t = tid; t < ix.dim; t += kBlock) s_q[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
+  if (tid == 0) {
+    int acc = 0;
+    int64_t sc = 0;
+    for (int j = 0; j < S; ++j) {
+      s_off[j] = acc;
+      acc += pcount[(size_t)q * smax + j];
+      sc += pscan[(size_t)q * smax + j];
+    }
+    s_off[S] = acc;
+    *s_cnt = 0;
+    if (ncand) ncand[q] = sc;
+  }
+  __syncthreads();
+  const int total = s_off[S];
+  for (int j = 0; j < S; ++j) {
+    const int c = s_off[j + 1] - s_off[j];
+    const uint64_t* src = pkeys + ((size_t)q * smax + j) * n;
+    for (int i = tid; i < c; i += kBlock) s_keys[s_off[j] + i] = src[i];
+  }
+  const int nn = min(n, total);
+  for (int i = nn + tid; i < P; i += kBlock) s_top[i] = ~0ull;
+  __syncthreads();
+  if (total > n) {
+    const uint64_t K = block_kth([&](int i) { return s_keys[i]; }, total, n, ss);
+    for (int i = tid; i < total; i += kBlock) {
+      const uint64_t key = s_keys[i];
+      if (key <= K) {
+        const int pos = atomicAdd(s_cnt, 1);
+        if (pos < P) s_top[pos] = key;
+      }
+    }
+  } else {
+    for (int i = tid; i < total; i += kBlock) s_top[i] = s_keys[i];
+  }
+  __syncthreads();
+  block_bitonic(s_top, P);
+  if (topn_ids) {
+    for (int i = tid; i < n; i += kBlock) {
+      const bool v = i < nn;
+      topn_ids[(size_t)q * n + i] = v ? (int32_t)(uint32_t)s_top[i] : -1;
+      topn_adc[(size_t)q * n + i] = v ? unord32((uint32_t)(s_top[i] >> 32)) : INFINITY;
+    }
+  }
+  if (out_ids)
+    rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k, out_dists + (size_t)q * k);
+}
+
+// Step 8 for caller-provided candidates.
+__global__ __launch_bounds__(kBlock) void k_rerank_only(DevIndex ix, const float* __restrict__ Q,
+                                                         const int32_t* __restrict__ cand, int n,
+                                                         int k, int64_t* __restrict__ out_ids,
+                                                         float* __restrict__ out_dists) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int P = pow2_at_least(n);
+  uint64_t* s_top = reinterpret_cast<uint64_t*>(smem);
+  uint64_t* s_key2 = s_top + P;
+  float* s_q = reinterpret_cast<float*>(s_key2 + P);
+  int* s_cnt = reinterpret_cast<int*>(s_q + ix.dim);
+  const int q = blockIdx.x, tid = threadIdx.x;
+  for (int t = tid; t < ix.dim; t += kBlock) s_q[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
+  if (tid == 0) *s_cnt = 0;
+  __syncthreads();
+  for (int i = tid; i < n; i += kBlock) {
+    const int id = cand[(size_t)q * n + i];
+    if (id >= 0 && id < ix.n) s_top[atomicAdd(s_cnt, 1)] = (uint32_t)id;
+  }
+  __syncthreads();
+  const int nn = *s_cnt;
+  rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k, out_dists + (size_t)q * k);
+}
+
+template <int W>
+hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t* np_eff,
+                         int np_max, int qc, const float* lut, const int32_t* sq, int smax, int n,
+                         int cap, int round_steps, uint64_t* pkeys, int32_t* pcount, int32_t* pscan,
+                         bool trace, int64_t t_capacity, int32_t* t_ids, float* t_adc,
+                         int64_t* t_count, hipStream_t st) {
+  const ScanLayout L = scan_layout(ix.M, ix.nlist, ix.R, np_max, n, cap);
+  const int qpad = (qc + 7) / 8 * 8;
+  const dim3 grid((unsigned)((size_t)qpad * smax));
+  if (trace) {
+    auto kern = k_scan<W, true>;
+    if (L.total > 65536)
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), L.total, st, ix, lists, np_eff, np_max, qc, lut,
+                       sq, smax, n, cap, round_steps, pkeys, pcount, pscan, t_capacity, t_ids,
+                       t_adc, reinterpret_cast<unsigned long long*>(t_count));
+  } else {
+    auto kern = k_scan<W, false>;
+    if (L.total > 65536)
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), L.total, st, ix, lists, np_eff, np_max, qc, lut,
+                       sq, smax, n, cap, round_steps, pkeys, pcount, pscan, t_capacity, t_ids,
+                       t_adc, reinterpret_cast<unsigned long long*>(t_count));
+  }
+  return hipGetLastError();
+}
+
+using ScanFn = hipError_t (*)(const DevIndex&, const int32_t*, const int32_t*, int, int,
+                              const float*, const int32_t*, int, int, int, int, uint64_t*,
+                              int32_t*, int32_t*, bool, int64_t, int32_t*, float*, int64_t*,
+                              hipStream_t);
+
+template <int... Ws>
+constexpr ScanFn scan_table_entry(int w, std::integer_sequence<int, Ws...>) {
+  ScanFn f = nullptr;
+  ((f = (w == Ws + 1) ? &launch_scan_w<Ws + 1> : f), ...);
+  return f;
+}
+
+ScanFn scan_fn(int W) {
+  return scan_table_entry(W, std::make_integer_sequence<int, kMaxM / 4>{});
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+int scan_smax(int n) { return std::max(1, std::min(16, 4096 / std::max(n, 1))); }
+
+size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n, int round_steps) {
+  return scan_layout(ix.M, ix.nlist, ix.R, np_max, n, n + kBlock * round_steps).total;
+}
+
+static bool exact64(const DevIndex& ix) { return !ix.int_grid; }
+
+hipError_t launch_probe(const DevIndex& ix, const float* q, const int32_t* nprobe, int np_max,
+                        int qc, Work& w, float* out_dists_opt, int32_t* out_lists,
+                        hipStream_t st) {
+  if (qc <= 0) return hipSuccess;
+  const dim3 g1((ix.nlist + kBlock - 1) / kBlock, (qc + kProbeQT - 1) / kProbeQT);
+  const size_t lds1 = (size_t)kProbeQT * ix.dim * 4;
+  if (exact64(ix))
+    hipLaunchKernelGGL(k_probe_dist<true>, g1, dim3(kBlock), lds1, st, ix, q, qc, w.dist);
+  else
+    hipLaunchKernelGGL(k_probe_dist<false>, g1, dim3(kBlock), lds1, st, ix, q, qc, w.dist);
+  const size_t lds2 = (size_t)pow2_at_least(np_max) * 8;
+  hipLaunchKernelGGL(k_probe_select, dim3(qc), dim3(kBlock), lds2, st, w.dist, ix.nlist, nprobe,
+                     np_max, out_lists, out_dists_opt, w.np_eff);
+  return hipGetLastError();
+}
+
+hipError_t launch_lut(const DevIndex& ix, const float* q, int qc, float* out_lut, hipStream_t st) {
+  if (qc <= 0) return hipSuccess;
+  const dim3 g(ix.M, qc);
+  if (exact64(ix))
+    hipLaunchKernelGGL(k_lut<true>, g, dim3(kKsub), 0, st, ix, q, qc, out_lut);
+  else
+    hipLaunchKernelGGL(k_lut<false>, g, dim3(kKsub), 0, st, ix, q, qc, out_lut);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const DevIndex& ix, const int32_t* lists, const int32_t* np_eff,
+                       const float* lut, const LaunchCfg& c, Work& w, hipStream_t st) {
+  if (c.qc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plan, dim3((c.qc + 255) / 256), dim3(256), 0, st, ix, lists, np_eff,
+                     c.np_max, c.qc, c.tile, c.smax, w.eq, w.sq);
+  const int W = (ix.M + 3) / 4;
+  const int cap = c.n + kBlock * c.round_steps;
+  return scan_fn(W)(ix, lists, np_eff, c.np_max, c.qc, lut, w.sq, c.smax, c.n, cap, c.round_steps,
+                    w.pkeys, w.pcount, w.pscan, false, 0, nullptr, nullptr, nullptr, st);
+}
+
+hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const float* lut, int qc,
+                             int np_max, int64_t capacity, int32_t* out_ids, float* out_adc,
+                             int64_t* out_count, Work& w, hipStream_t st) {
+  if (qc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count_lists, dim3((qc + 255) / 256), dim3(256), 0, st, lists, qc, np_max,
+                     ix.nlist, w.np_eff);
+  const int smax = 16, tile = 4096;
+  hipLaunchKernelGGL(k_plan, dim3((qc + 255) / 256), dim3(256), 0, st, ix, lists, w.np_eff, np_max,
+                     qc, tile, smax, w.eq, w.sq);
+  hipLaunchKernelGGL(k_zero_i64, dim3((qc + 255) / 256), dim3(256), 0, st, out_count, qc);
+  const int W = (ix.M + 3) / 4;
+  return scan_fn(W)(ix, lists, w.np_eff, np_max, qc, lut, w.sq, smax, 1, 1, 1, nullptr, nullptr,
+                    nullptr, true, capacity, out_ids, out_adc, out_count, st);
+}
+
+hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,
+                        int32_t* topn_ids, float* topn_adc, int64_t* ncand, int64_t* out_ids,
+                        float* out_dists, hipStream_t st) {
+  if (c.qc <= 0) return hipSuccess;
+  const MergeLayout L = merge_layout(c.smax, c.n, ix.dim);
+  if (L.total > 65536)
+    (void)hipFuncSetAttribute((const void*)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
+  hipLaunchKernelGGL(k_merge, dim3(c.qc), dim3(kBlock), L.total, st, ix, q, c.qc, w.sq, c.smax,
+                     c.n, c.k, w.pkeys, w.pcount, w.pscan, topn_ids, topn_adc, ncand, out_ids,
+                     out_dists);
+  return hipGetLastError();
+}
+
+hipError_t launch_rerank_only(const DevIndex& ix, const float* q, const int32_t* cand, int qc,
+                              int n, int k, int64_t* out_ids, float* out_dists, hipStream_t st) {
+  if (qc <= 0) return hipSuccess;
+  const int P = pow2_at_least(n);
+  const size_t lds = (size_t)P * 16 + (size_t)ix.dim * 4 + 16;
+  hipLaunchKernelGGL(k_rerank_only, dim3(qc), dim3(kBlock), lds, st, ix, q, cand, n, k, out_ids,
+                     out_dists);
+  return hipGetLastError();
+}
+
+}  // namespace ann

@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark of the GPU filtering stage on one MI355X.
+
+Workload (default): 10M uint8 vectors of dimension 128 drawn from a seeded
+Gaussian mixture (4096 centres), IVF with 16384 lists (Eq. 2 replication,
+at most 2 lists per vector), PQ with 32 subspaces x 256 codewords, 10,000
+queries, nprobe 64, rerank_n 200, k 10.  A step is one pass of the whole path
+(probe, distance table, gather + dedup, Eq. 1 scan, top-n, exact re-rank)
+over all queries, with the index and the queries already in HBM.
+
+Forms timed:
+  plain    one ann_search call per batch of 256 queries
+  batched  one ann_search call over all queries
+The headline value is the batched form's queries/s.
+
+Also reported: candidates/s, recall@10 against exact kNN of a query sample,
+bit-exact parity of a query sample against the CPU oracle, the scan kernel's
+roofline (HBM), and the CPU oracle's own throughput on a bounded sample.
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PQ-ADC candidates/s + QPS at recall@10>=0.9, batched vs plain, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+SCAN_SOURCES = ["paper_2409_16576_amd/csrc/ann_kernels.hip"]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for s in SCAN_SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM traffic per scan launch from the committed counter summary, if it
+    was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", f"scan_traffic_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("kernel_sha") != kernel_hash():
+        return None
+    return t
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ivf_u8_10m")
+    ap.add_argument("--plain-batch", type=int, default=256)
+    ap.add_argument("--cpu-queries", type=int, default=1024)
+    ap.add_argument("--recall-queries", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--forms", default="plain,batched")
+    ap.add_argument("--build-only", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); every box in this "
+              "setup has a single MI355X and the search path uses no collectives.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+
+    from paper_2409_16576_amd import builder, workloads
+
+    w = workloads.ALL[args.workload]
+    t0 = time.time()
+    path = workloads.ensure_index(w, verbose=True)
+    log(f"index ready in {time.time() - t0:.1f}s: {path}")
+    if args.build_only:
+        return
+
+    import torch
+
+    from paper_2409_16576_amd import ann
+
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    g = ann.Index(path, 0)
+    log(f"index loaded to HBM in {time.time() - t0:.1f}s, {g.desc['hbm_bytes'] / 2**30:.2f} GiB")
+    Qh = workloads.queries(w)
+    nq = Qh.shape[0]
+    Q = torch.from_numpy(Qh).to(dev)
+    npq = workloads.nprobe_per_query(w)
+    fixed_np = isinstance(w.nprobe, int)
+    nprobe_arg = int(w.nprobe) if fixed_np else torch.from_numpy(npq).to(dev)
+    k, n = w.k, w.rerank_n
+    st = torch.cuda.current_stream(dev)
+
+    # ---- work counts (untimed): candidates scored and replica entries walked
+    _, _, ncand = g.search_topn(Q, nprobe_arg, n)
+    lists, _ = g.probe(Q, nprobe_arg, with_dists=False)
+    torch.cuda.synchronize()
+    ncand = ncand.cpu().numpy()
+    lists = lists.cpu().numpy()
+    sizes, primary = builder.read_list_meta(path)
+    valid = lists >= 0
+    lsafe = np.where(valid, lists, 0)
+    entries_q = (sizes[lsafe] * valid).sum(1)
+    rep_q = ((sizes - primary)[lsafe] * valid).sum(1)
+    cand_per_step = int(ncand.sum())
+    M = g.desc["m"]
+    row_bytes = (M + 3) // 4 * 4
+    scan_alg_bytes = cand_per_step * row_bytes + int(rep_q.sum()) * 8 + nq * M * 256 * 4
+    log(f"per step: {cand_per_step} candidates, {int(entries_q.sum())} list entries, "
+        f"{int(rep_q.sum())} replica entries; scan algorithmic bytes {scan_alg_bytes / 1e9:.2f} GB")
+
+    def step_plain():
+        for b0 in range(0, nq, args.plain_batch):
+            b1 = min(nq, b0 + args.plain_batch)
+            npb = nprobe_arg if fixed_np else nprobe_arg[b0:b1]
+            g.search(Q[b0:b1], npb, k, n)
+
+    out = {}
+
+    def step_batched():
+        out["res"] = g.search(Q, nprobe_arg, k, n)
+
+    forms = {"plain": step_plain, "batched": step_batched}
+    results = {}
+    for name in args.forms.split(","):
+        fn = forms[name]
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        g.set_profiling(True)
+        g.get_profile(reset=True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(st)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        ev1.record(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = ev0.elapsed_time(ev1) / args.steps
+        prof = g.get_profile(reset=True)
+        g.set_profiling(False)
+        results[name] = {"ms_per_step": ms, "qps": nq / (ms / 1e3),
+                         "candidates_per_s": cand_per_step / (ms / 1e3),
+                         "wall_ms_per_step": wall * 1e3 / args.steps,
+                         "stage_ms_per_step": {s: v["ms"] / args.steps for s, v in prof.items()},
+                         "stage_launches_per_step": {s: v["launches"] // args.steps
+                                                     for s, v in prof.items()}}
+        log(f"{name}: {ms:.3f} ms/step, {results[name]['qps']:.0f} q/s, "
+            f"{results[name]['candidates_per_s'] / 1e9:.2f} G cand/s, stages "
+            + ", ".join(f"{s} {v['ms'] / args.steps:.3f}ms" for s, v in prof.items()))
+
+    head = "batched" if "batched" in results else list(results)[0]
+    R = results[head]
+    scan_ms = R["stage_ms_per_step"]["scan"]
+    scan_launches = max(1, R["stage_launches_per_step"]["scan"])
+    achieved = scan_alg_bytes / (scan_ms / 1e3) / 1e9
+    tr = load_traffic(w.name)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": (tr["bytes_per_step"] if tr else None),
+                "kernel": "k_scan (fused gather/dedup/Eq.1/top-n)",
+                "scan_ms_per_launch": round(scan_ms / scan_launches, 4),
+                "scan_launches_per_step": scan_launches,
+                "algorithmic_bytes_per_step": scan_alg_bytes}
+
+    line = {
+        "metric": METRIC, "value": round(R["qps"], 1), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(R["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {**w.describe(), "data_dtype": w.kind, "form": head,
+                   "plain_batch": args.plain_batch},
+        "candidates_per_s": round(R["candidates_per_s"], 1),
+        "candidates_per_query": round(cand_per_step / nq, 1),
+        "forms": {k_: {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()}
+                  for k_, r in results.items()},
+        "roofline": roofline,
+    }
+    if "plain" in results and "batched" in results:
+        line["batched_over_plain"] = round(results["batched"]["qps"] / results["plain"]["qps"], 3)
+
+    if not args.no_cpu:
+        import oracle
+
+        log("oracle leg: reading the index on the host")
+        oracle.build(force=False)
+        oix = oracle.read_index(path, verify=False)
+        threads = os.cpu_count() or 1
+        ns = min(args.cpu_queries, nq)
+        t0 = time.perf_counter()
+        r = oracle.search(oix, Qh[:ns], npq[:ns], k, n, threads=threads)
+        cpu_s = time.perf_counter() - t0
+        log(f"oracle: {ns} queries in {cpu_s:.2f}s on {threads} threads")
+        ids_gpu, d_gpu = out["res"] if "res" in out else g.search(Q, nprobe_arg, k, n)
+        ids_gpu = ids_gpu[:ns].cpu().numpy()
+        d_gpu = d_gpu[:ns].cpu().numpy()
+        line["parity_sample"] = {"queries": ns, "ids_equal": bool(np.array_equal(ids_gpu, r.ids)),
+                                 "dists_equal": bool(np.array_equal(d_gpu, r.dists))}
+        line["cpu_baseline"] = {"value": round(ns / cpu_s, 1), "unit": "queries/s",
+                                "cores": threads, "kind": "oracle",
+                                "sample": f"first {ns} of {nq} queries, full index, same knobs",
+                                "candidates_per_s": round(float(r.ncand.sum()) / cpu_s, 1)}
+        nr = min(args.recall_queries, nq)
+        t0 = time.perf_counter()
+        gt, _ = oracle.bruteforce(oix, Qh[:nr], k, threads=threads)
+        log(f"brute force of {nr} queries in {time.perf_counter() - t0:.1f}s")
+        line["recall_at_10"] = round(oracle.recall_at_k(ids_gpu[:nr], gt, k), 4)
+        line["recall_queries"] = nr
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -160,6 +160,23 @@ ann_status ann_scan_trace(ann_index* ix, const int32_t* d_lists, int64_t nq, int
 ann_status ann_rerank(ann_index* ix, const float* d_queries, int64_t nq, const int32_t* d_cand_ids,
                       int32_t n, int32_t k, int64_t* d_out_ids, float* d_out_dists, void* stream);
 
+/*
+ * Stage timing (measurement support, not part of the paper's method).
+ * When enabled, every kernel stage launched by the search entry points on
+ * this index is bracketed by a pair of HIP events recorded on the caller's
+ * stream.  ann_get_profile waits for the recorded events, returns the summed
+ * elapsed times and launch counts, and (reset != 0) clears them.
+ * Stages: 0 probe (distances + selection), 1 distance table, 2 scan
+ * (planning + fused gather/dedup/Eq. 1/top-n), 3 merge + exact re-rank.
+ */
+typedef struct {
+  double ms[4];
+  int64_t launches[4];
+} ann_profile;
+
+ann_status ann_set_profiling(ann_index* ix, int enable);
+ann_status ann_get_profile(ann_index* ix, ann_profile* out, int reset);
+
 #ifdef __cplusplus
 }
 #endif

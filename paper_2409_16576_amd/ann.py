@@ -39,6 +39,12 @@ class IndexDesc(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4)]
+
+
+STAGES = ("probe", "lut", "scan", "merge_rerank")
+
 _lib = None
 
 
@@ -62,8 +68,11 @@ def lib():
         L.ann_lut.argtypes = [P, P, i64, P, P]
         L.ann_scan_trace.argtypes = [P, P, i64, i32, P, i64, P, P, P, P]
         L.ann_rerank.argtypes = [P, P, i64, P, i32, i32, P, P, P]
+        L.ann_set_profiling.argtypes = [P, ctypes.c_int]
+        L.ann_get_profile.argtypes = [P, ctypes.POINTER(Profile), ctypes.c_int]
         for f in ("ann_load_index", "ann_index_info", "ann_search", "ann_search_topn", "ann_probe",
-                  "ann_lut", "ann_scan_trace", "ann_rerank"):
+                  "ann_lut", "ann_scan_trace", "ann_rerank", "ann_set_profiling",
+                  "ann_get_profile"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -185,3 +194,12 @@ class Index:
         _check(lib().ann_rerank(self._h, _ptr(q), nq, _ptr(cand), n, k, _ptr(ids), _ptr(d),
                                 _stream(self.device, stream)))
         return ids, d
+
+    # -- measurement -------------------------------------------------------------
+    def set_profiling(self, enable: bool):
+        _check(lib().ann_set_profiling(self._h, 1 if enable else 0))
+
+    def get_profile(self, reset: bool = True) -> dict:
+        p = Profile()
+        _check(lib().ann_get_profile(self._h, ctypes.byref(p), 1 if reset else 0))
+        return {s: {"ms": p.ms[i], "launches": p.launches[i]} for i, s in enumerate(STAGES)}

@@ -319,3 +319,22 @@ def build_index(path: str, X: np.ndarray, kind: str, p: BuildParams) -> IndexArr
     ix = build_arrays(X, kind, p)
     write_index(path, ix)
     return ix
+
+
+def read_list_meta(path: str):
+    """(list sizes, first-list member counts) of an index file, without the big sections."""
+    with open(path, "rb") as f:
+        hdr = f.read(HEADER_BYTES)
+        if hdr[:8] != MAGIC:
+            raise ValueError("not an index file")
+        n, nlist = struct.unpack_from("<Q", hdr, 24)[0], struct.unpack_from("<I", hdr, 32)[0]
+        R = struct.unpack_from("<I", hdr, 48)[0]
+        offs_off, offs_bytes = struct.unpack_from("<QQ", hdr, 128 + 24 * 4)
+        asg_off, asg_bytes = struct.unpack_from("<QQ", hdr, 128 + 24 * 6)
+        f.seek(offs_off)
+        offsets = np.frombuffer(f.read(offs_bytes), dtype=np.int64)
+        f.seek(asg_off)
+        first = np.frombuffer(f.read(asg_bytes), dtype=np.int32).reshape(n, R)[:, 0]
+    sizes = np.diff(offsets)
+    primary = np.bincount(first, minlength=nlist).astype(np.int64)
+    return sizes, primary

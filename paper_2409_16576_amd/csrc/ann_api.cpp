@@ -70,6 +70,11 @@ struct Need {
 
 }  // namespace
 
+struct ProfMark {
+  int stage;
+  hipEvent_t a, b;
+};
+
 struct ann_index {
   int device = 0;
   DevIndex d{};
@@ -78,9 +83,20 @@ struct ann_index {
   std::mutex mu;
   std::vector<std::unique_ptr<Workspace>> pool;
   std::vector<Workspace*> free_ws;
+  // stage timing
+  bool profiling = false;
+  std::mutex prof_mu;
+  std::vector<ProfMark> marks;
+  std::vector<hipEvent_t> spare_events;
 
   ~ann_index() {
     pool.clear();
+    for (auto& m : marks) {
+      (void)hipEventSynchronize(m.b);
+      (void)hipEventDestroy(m.a);
+      (void)hipEventDestroy(m.b);
+    }
+    for (auto e : spare_events) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
   }
 };
@@ -182,6 +198,38 @@ struct WsGuard {
   hipStream_t st;
   ~WsGuard() {
     if (ws) ws_release(ix, ws, st);
+  }
+};
+
+// Brackets one kernel stage with an event pair when profiling is enabled.
+struct StageMark {
+  ann_index* ix;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+
+  static hipEvent_t take(ann_index* ix) {
+    std::lock_guard<std::mutex> g(ix->prof_mu);
+    hipEvent_t e = nullptr;
+    if (!ix->spare_events.empty()) {
+      e = ix->spare_events.back();
+      ix->spare_events.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  StageMark(ann_index* ix_, int stage_, hipStream_t st_) : ix(ix_), stage(stage_), st(st_) {
+    if (!ix->profiling) return;
+    a = take(ix);
+    b = take(ix);
+    if (a) (void)hipEventRecord(a, st);
+  }
+  ~StageMark() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> g(ix->prof_mu);
+    ix->marks.push_back({stage, a, b});
   }
 };
 
@@ -492,14 +540,26 @@ ann_status run_pipeline(ann_index* ix, const float* Q, int64_t nq, const int32_t
     const int qc = (int)std::min<int64_t>(qc_max, nq - q0);
     const LaunchCfg c = cfg_for(qc, np_max, n, k);
     const float* q = Q + q0 * d.dim;
-    HIP_TRY(launch_probe(d, q, nprobe ? nprobe + q0 : nullptr, np_max, qc, ws->w, nullptr,
-                         ws->w.lists, st));
-    HIP_TRY(launch_lut(d, q, qc, ws->w.lut, st));
-    HIP_TRY(launch_scan(d, ws->w.lists, ws->w.np_eff, ws->w.lut, c, ws->w, st));
-    HIP_TRY(launch_merge(d, q, c, ws->w, topn_ids ? topn_ids + q0 * n : nullptr,
-                         topn_adc ? topn_adc + q0 * n : nullptr, ncand ? ncand + q0 : nullptr,
-                         out_ids ? out_ids + q0 * k : nullptr, out_d ? out_d + q0 * k : nullptr,
-                         st));
+    {
+      StageMark m(ix, 0, st);
+      HIP_TRY(launch_probe(d, q, nprobe ? nprobe + q0 : nullptr, np_max, qc, ws->w, nullptr,
+                           ws->w.lists, st));
+    }
+    {
+      StageMark m(ix, 1, st);
+      HIP_TRY(launch_lut(d, q, qc, ws->w.lut, st));
+    }
+    {
+      StageMark m(ix, 2, st);
+      HIP_TRY(launch_scan(d, ws->w.lists, ws->w.np_eff, ws->w.lut, c, ws->w, st));
+    }
+    {
+      StageMark m(ix, 3, st);
+      HIP_TRY(launch_merge(d, q, c, ws->w, topn_ids ? topn_ids + q0 * n : nullptr,
+                           topn_adc ? topn_adc + q0 * n : nullptr, ncand ? ncand + q0 : nullptr,
+                           out_ids ? out_ids + q0 * k : nullptr, out_d ? out_d + q0 * k : nullptr,
+                           st));
+    }
   }
   return ANN_OK;
 }
@@ -611,6 +671,33 @@ extern "C" ann_status ann_rerank(ann_index* ix, const float* d_queries, int64_t 
     const int qc = (int)std::min<int64_t>(step, nq - q0);
     HIP_TRY(launch_rerank_only(ix->d, d_queries + q0 * ix->d.dim, d_cand_ids + q0 * n, qc, n, k,
                                d_out_ids + q0 * k, d_out_dists + q0 * k, (hipStream_t)stream));
+  }
+  return ANN_OK;
+}
+
+extern "C" ann_status ann_set_profiling(ann_index* ix, int enable) {
+  if (!ix) return fail(ANN_EINVAL, "index is NULL");
+  ix->profiling = enable != 0;
+  return ANN_OK;
+}
+
+extern "C" ann_status ann_get_profile(ann_index* ix, ann_profile* out, int reset) {
+  if (!ix || !out) return fail(ANN_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> g(ix->prof_mu);
+  *out = ann_profile{};
+  for (auto& m : ix->marks) {
+    HIP_TRY(hipEventSynchronize(m.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, m.a, m.b));
+    out->ms[m.stage] += ms;
+    out->launches[m.stage] += 1;
+  }
+  if (reset) {
+    for (auto& m : ix->marks) {
+      ix->spare_events.push_back(m.a);
+      ix->spare_events.push_back(m.b);
+    }
+    ix->marks.clear();
   }
   return ANN_OK;
 }

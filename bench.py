@@ -68,10 +68,14 @@ def parse():
     ap.add_argument("--workload", default="ivf_u8_10m")
     ap.add_argument("--plain-batch", type=int, default=256)
     ap.add_argument("--cpu-queries", type=int, default=1024)
-    ap.add_argument("--recall-queries", type=int, default=200)
+    ap.add_argument("--recall-queries", type=int, default=500)
+    ap.add_argument("--rerank-n", type=int, default=0,
+                    help="top-n re-ranked (default: the workload's recall>=0.9 operating point)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--forms", default="plain,batched")
     ap.add_argument("--build-only", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this size (counter calibration)")
     return ap.parse_args()
 
 
@@ -98,6 +102,14 @@ def main():
     from paper_2409_16576_amd import ann
 
     dev = torch.device("cuda", 0)
+    if args.copy_calibration_mib:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {nb} bytes done")
+        del src, dst
     t0 = time.time()
     g = ann.Index(path, 0)
     log(f"index loaded to HBM in {time.time() - t0:.1f}s, {g.desc['hbm_bytes'] / 2**30:.2f} GiB")
@@ -107,7 +119,8 @@ def main():
     npq = workloads.nprobe_per_query(w)
     fixed_np = isinstance(w.nprobe, int)
     nprobe_arg = int(w.nprobe) if fixed_np else torch.from_numpy(npq).to(dev)
-    k, n = w.k, w.rerank_n
+    k = w.k
+    n = args.rerank_n or w.rerank_n_op or w.rerank_n
     st = torch.cuda.current_stream(dev)
 
     # ---- work counts (untimed): candidates scored and replica entries walked
@@ -190,8 +203,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(R["ms_per_step"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {**w.describe(), "data_dtype": w.kind, "form": head,
-                   "plain_batch": args.plain_batch},
+        "config": {**w.describe(), "rerank_n": n, "rerank_n_config": w.rerank_n,
+                   "data_dtype": w.kind, "form": head, "plain_batch": args.plain_batch},
         "candidates_per_s": round(R["candidates_per_s"], 1),
         "candidates_per_query": round(cand_per_step / nq, 1),
         "forms": {k_: {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()}

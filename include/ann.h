@@ -177,6 +177,18 @@ typedef struct {
 ann_status ann_set_profiling(ann_index* ix, int enable);
 ann_status ann_get_profile(ann_index* ix, ann_profile* out, int reset);
 
+/*
+ * Tuning knobs of the scan work split (no effect on any result: the top-n of
+ * a query is the same however its gathered entries are split into items).
+ *   ANN_OPT_SCAN_TILE   target entries per work item, in [64, 2^30] (default 65536)
+ *   ANN_OPT_SCAN_SPLIT  most work items per query, in [1, 16] (default 16;
+ *                       the kernel also caps it at max(1, 4096 / rerank_n))
+ * Errors: ANN_EINVAL for an unknown option or an out-of-range value.
+ */
+enum { ANN_OPT_SCAN_TILE = 1, ANN_OPT_SCAN_SPLIT = 2 };
+ann_status ann_set_option(ann_index* ix, int option, int64_t value);
+ann_status ann_get_option(ann_index* ix, int option, int64_t* value);
+
 #ifdef __cplusplus
 }
 #endif

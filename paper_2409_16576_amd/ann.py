@@ -70,9 +70,11 @@ def lib():
         L.ann_rerank.argtypes = [P, P, i64, P, i32, i32, P, P, P]
         L.ann_set_profiling.argtypes = [P, ctypes.c_int]
         L.ann_get_profile.argtypes = [P, ctypes.POINTER(Profile), ctypes.c_int]
+        L.ann_set_option.argtypes = [P, ctypes.c_int, i64]
+        L.ann_get_option.argtypes = [P, ctypes.c_int, ctypes.POINTER(i64)]
         for f in ("ann_load_index", "ann_index_info", "ann_search", "ann_search_topn", "ann_probe",
                   "ann_lut", "ann_scan_trace", "ann_rerank", "ann_set_profiling",
-                  "ann_get_profile"):
+                  "ann_get_profile", "ann_set_option", "ann_get_option"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -203,3 +205,15 @@ class Index:
         p = Profile()
         _check(lib().ann_get_profile(self._h, ctypes.byref(p), 1 if reset else 0))
         return {s: {"ms": p.ms[i], "launches": p.launches[i]} for i, s in enumerate(STAGES)}
+
+    # -- tuning --------------------------------------------------------------------
+    OPT_SCAN_TILE = 1
+    OPT_SCAN_SPLIT = 2
+
+    def set_option(self, option: int, value: int):
+        _check(lib().ann_set_option(self._h, int(option), int(value)))
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int64()
+        _check(lib().ann_get_option(self._h, int(option), ctypes.byref(v)))
+        return v.value

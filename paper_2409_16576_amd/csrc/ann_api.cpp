@@ -83,6 +83,9 @@ struct ann_index {
   std::mutex mu;
   std::vector<std::unique_ptr<Workspace>> pool;
   std::vector<Workspace*> free_ws;
+  // tuning (ann_set_option); never changes results
+  int64_t opt_tile = 65536;
+  int64_t opt_split = 16;
   // stage timing
   bool profiling = false;
   std::mutex prof_mu;
@@ -270,10 +273,10 @@ ann_status validate_args(ann_index* ix, const void* q, int64_t nq, int32_t np_ma
 }
 
 int chunk_queries(const DevIndex& d, int64_t nq) {
-  const size_t budget = size_t(256) << 20;
+  // the coarse-distance matrix of a chunk is the largest working buffer
+  const size_t budget = size_t(1) << 30;
   size_t by_dist = budget / ((size_t)d.nlist * 4);
-  size_t by_lut = budget / ((size_t)d.M * kKsub * 4);
-  size_t qc = std::min<size_t>({(size_t)nq, by_dist, by_lut, size_t(16384)});
+  size_t qc = std::min<size_t>({(size_t)nq, by_dist, size_t(16384)});
   return (int)std::max<size_t>(qc, 1);
 }
 
@@ -284,20 +287,22 @@ Need need_for(const DevIndex& d, int qc, int np_max, int n, int smax) {
   r.nlist = (size_t)d.nlist;
   r.items = (size_t)qc * smax;
   r.keys = r.items * (size_t)std::max(n, 1);
-  r.lut = (size_t)qc * d.M * kKsub;
+  r.lut = 0;  // the scan builds each query's table in LDS
   r.cand = 0;
   return r;
 }
 
-LaunchCfg cfg_for(int qc, int np_max, int n, int k) {
+// Items of up to `tile` entries (default 64k: one per query at typical probe
+// sizes, so the table is loaded once per query and the threshold filter sees
+// long streams); very long queries are split across up to smax items.
+LaunchCfg cfg_for(int qc, int np_max, int n, int k, int64_t tile, int64_t split) {
   LaunchCfg c;
   c.qc = qc;
   c.np_max = np_max;
   c.n = n;
   c.k = k;
-  c.smax = scan_smax(n);
-  c.tile = 4096;
-  c.round_steps = 4;
+  c.smax = std::max(1, std::min<int>((int)split, scan_smax(n)));
+  c.tile = (int)tile;
   return c;
 }
 
@@ -306,7 +311,7 @@ ann_status check_lds(ann_index* ix, int np_max, int n) {
   if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) !=
       hipSuccess)
     return fail(ANN_EDEVICE, "hipDeviceGetAttribute failed");
-  const size_t need = scan_lds_bytes(ix->d, np_max, n, 4);
+  const size_t need = scan_lds_bytes(ix->d, np_max, n);
   if ((int64_t)need > (int64_t)max_lds)
     return fail(ANN_EUNSUPPORTED, "scan needs %zu bytes of LDS per block, device allows %d", need,
                 max_lds);
@@ -504,6 +509,24 @@ extern "C" ann_status ann_load_index(const char* path, int device, ann_index** o
   d.rep = prep;
   if ((s = dev_upload(ix.get(), asg_rows.data(), asg_rows.size(), &d.assign_rows)) != ANN_OK)
     return s;
+  // Integer-grid indexes probe on the int8 matrix cores: shifted, padded centroids.
+  d.dim_pad = (dim + 63) / 64 * 64;
+  d.shift8 = dtype == U8 ? 128 : 0;
+  if (int_grid && d.dim_pad <= 512) {
+    std::vector<int8_t> c8((size_t)nlist * d.dim_pad, 0);
+    std::vector<int32_t> cn(nlist, 0);
+    for (int l = 0; l < nlist; ++l) {
+      int32_t acc = 0;
+      for (int t = 0; t < dim; ++t) {
+        const int v = (int)cent[(size_t)l * dim + t] - d.shift8;
+        c8[(size_t)l * d.dim_pad + t] = (int8_t)v;
+        acc += v * v;
+      }
+      cn[l] = acc;
+    }
+    if ((s = dev_upload(ix.get(), c8.data(), c8.size(), &d.cent8)) != ANN_OK) return s;
+    if ((s = dev_upload(ix.get(), cn.data(), cn.size(), &d.cnorm8)) != ANN_OK) return s;
+  }
 
   ann_index_desc& ds = ix->desc;
   ds.n = (int64_t)n; ds.dim = dim; ds.dtype = dtype; ds.nlist = nlist; ds.m = M; ds.ksub = ksub;
@@ -532,13 +555,13 @@ ann_status run_pipeline(ann_index* ix, const float* Q, int64_t nq, const int32_t
   if ((s = check_lds(ix, np_max, n)) != ANN_OK) return s;
   const DevIndex& d = ix->d;
   const int qc_max = chunk_queries(d, nq);
-  const LaunchCfg c0 = cfg_for(qc_max, np_max, n, k);
+  const LaunchCfg c0 = cfg_for(qc_max, np_max, n, k, ix->opt_tile, ix->opt_split);
   Workspace* ws = nullptr;
   if ((s = ws_acquire(ix, need_for(d, qc_max, np_max, n, c0.smax), st, &ws)) != ANN_OK) return s;
   WsGuard guard{ix, ws, st};
   for (int64_t q0 = 0; q0 < nq; q0 += qc_max) {
     const int qc = (int)std::min<int64_t>(qc_max, nq - q0);
-    const LaunchCfg c = cfg_for(qc, np_max, n, k);
+    const LaunchCfg c = cfg_for(qc, np_max, n, k, ix->opt_tile, ix->opt_split);
     const float* q = Q + q0 * d.dim;
     {
       StageMark m(ix, 0, st);
@@ -546,12 +569,8 @@ ann_status run_pipeline(ann_index* ix, const float* Q, int64_t nq, const int32_t
                            ws->w.lists, st));
     }
     {
-      StageMark m(ix, 1, st);
-      HIP_TRY(launch_lut(d, q, qc, ws->w.lut, st));
-    }
-    {
-      StageMark m(ix, 2, st);
-      HIP_TRY(launch_scan(d, ws->w.lists, ws->w.np_eff, ws->w.lut, c, ws->w, st));
+      StageMark m(ix, 2, st);  // steps 1, 3, 5, 6, 7: the table is built inside the scan
+      HIP_TRY(launch_scan(d, ws->w.lists, ws->w.np_eff, q, c, ws->w, st));
     }
     {
       StageMark m(ix, 3, st);
@@ -700,4 +719,29 @@ extern "C" ann_status ann_get_profile(ann_index* ix, ann_profile* out, int reset
     ix->marks.clear();
   }
   return ANN_OK;
+}
+
+extern "C" ann_status ann_set_option(ann_index* ix, int option, int64_t value) {
+  if (!ix) return fail(ANN_EINVAL, "index is NULL");
+  switch (option) {
+    case ANN_OPT_SCAN_TILE:
+      if (value < 64 || value > (int64_t)1 << 30) return fail(ANN_EINVAL, "tile must be in [64, 2^30]");
+      ix->opt_tile = value;
+      return ANN_OK;
+    case ANN_OPT_SCAN_SPLIT:
+      if (value < 1 || value > 16) return fail(ANN_EINVAL, "split must be in [1, 16]");
+      ix->opt_split = value;
+      return ANN_OK;
+    default:
+      return fail(ANN_EINVAL, "unknown option %d", option);
+  }
+}
+
+extern "C" ann_status ann_get_option(ann_index* ix, int option, int64_t* value) {
+  if (!ix || !value) return fail(ANN_EINVAL, "NULL argument");
+  switch (option) {
+    case ANN_OPT_SCAN_TILE: *value = ix->opt_tile; return ANN_OK;
+    case ANN_OPT_SCAN_SPLIT: *value = ix->opt_split; return ANN_OK;
+    default: return fail(ANN_EINVAL, "unknown option %d", option);
+  }
 }

@@ -10,8 +10,10 @@ namespace ann {
 enum DType : int { F32 = 0, U8 = 1, I8 = 2 };
 
 constexpr int kKsub = 256;
-constexpr int kBlock = 256;           // threads per block of every kernel
-constexpr int kMaxRerank = 1024;      // largest rerank_n
+constexpr int kBlock = 256;           // threads per block (all kernels but the scan)
+constexpr int kScanBlock = 1024;      // threads per block of the scan kernel
+constexpr int kScanRT = 2;            // entries per scan thread per round
+constexpr int kMaxRerank = 4096;      // largest rerank_n
 constexpr int kMaxM = 64;             // largest number of PQ subspaces
 constexpr int kMaxDim = 2048;
 constexpr int kRankShift = 28;        // replica entry: row | rank << 28
@@ -34,6 +36,11 @@ struct DevIndex {
   const int32_t* rstart;      // [nlist + 1] replica entry ranges
   const int2* rep;            // [replica entries] {row | rank << 28, first list of the vector}
   const int32_t* assign_rows; // [n, R] lists of each row, nearest first, -1 padded
+  // integer-grid indexes only (else null): centroids shifted to int8, zero-padded
+  const int8_t* cent8;        // [nlist, dim_pad], value - shift8
+  const int32_t* cnorm8;      // [nlist] sum of squares of the shifted centroid
+  int dim_pad;                // dim rounded up to 64
+  int shift8;                 // 128 for uint8, 0 for int8
 };
 
 // Per-call working buffers (one block of the memory pool).
@@ -57,7 +64,6 @@ struct LaunchCfg {
   int k;
   int smax;        // work items per query (max)
   int tile;        // target entries per work item
-  int round_steps; // entries per thread between compaction checks
 };
 
 // Kernel launchers (ann_kernels.hip).  All enqueue on `st` and return hipError_t.
@@ -65,8 +71,9 @@ hipError_t launch_probe(const DevIndex& ix, const float* q, const int32_t* nprob
                         int qc, Work& w, float* out_dists_opt, int32_t* out_lists,
                         hipStream_t st);
 hipError_t launch_lut(const DevIndex& ix, const float* q, int qc, float* out_lut, hipStream_t st);
+// The scan computes each query's distance table itself (step 1 fused).
 hipError_t launch_scan(const DevIndex& ix, const int32_t* lists, const int32_t* np_eff,
-                       const float* lut, const LaunchCfg& c, Work& w, hipStream_t st);
+                       const float* q, const LaunchCfg& c, Work& w, hipStream_t st);
 hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const float* lut, int qc,
                              int np_max, int64_t capacity, int32_t* out_ids, float* out_adc,
                              int64_t* out_count, Work& w, hipStream_t st);
@@ -77,7 +84,7 @@ hipError_t launch_rerank_only(const DevIndex& ix, const float* q, const int32_t*
                               int n, int k, int64_t* out_ids, float* out_dists, hipStream_t st);
 
 // Sizes of the dynamic LDS areas (bytes) for the scan kernel.
-size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n, int round_steps);
+size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n);
 int scan_smax(int n);
 
 }  // namespace ann

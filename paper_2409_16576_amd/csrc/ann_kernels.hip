@@ -71,6 +71,7 @@ struct SelScratch {
   uint32_t hist[256];
   uint64_t prefix;
   uint64_t found;
+  uint64_t lo, hi;
   int want;
   int done;
 };
@@ -79,12 +80,42 @@ template <class G>
 __device__ uint64_t block_kth(G get, int cnt, int want, SelScratch* s) {
   const int tid = threadIdx.x;
   if (tid == 0) {
-    s->prefix = 0;
     s->want = want;
     s->done = 0;
+    s->lo = ~0ull;
+    s->hi = 0ull;
   }
-  uint64_t mask = 0;
-  for (int shift = 56; shift >= 0; shift -= 8) {
+  // Bytes shared by every key need no histogram pass: start below them.
+  {
+    uint64_t lo = ~0ull, hi = 0ull;
+    for (int i = tid; i < cnt; i += blockDim.x) {
+      const uint64_t k = get(i);
+      lo = k < lo ? k : lo;
+      hi = k > hi ? k : hi;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      const uint64_t a = __shfl_xor(lo, d, 64), b = __shfl_xor(hi, d, 64);
+      lo = a < lo ? a : lo;
+      hi = b > hi ? b : hi;
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) {
+      atomicMin(&s->lo, lo);
+      atomicMax(&s->hi, hi);
+    }
+    __syncthreads();
+  }
+  const uint64_t diff = s->lo ^ s->hi;
+  if (diff == 0) {  // a single distinct key
+    const uint64_t r = s->lo;
+    __syncthreads();
+    return r;
+  }
+  const int top_shift = ((63 - __clzll((long long)diff)) / 8) * 8;
+  uint64_t mask = top_shift >= 56 ? 0ull : ~((1ull << (top_shift + 8)) - 1ull);
+  if (tid == 0) s->prefix = s->lo & mask;
+  for (int shift = top_shift; shift >= 0; shift -= 8) {
     for (int i = tid; i < 256; i += blockDim.x) s->hist[i] = 0;
     __syncthreads();
     const uint64_t prefix = s->prefix;
@@ -207,35 +238,160 @@ __global__ __launch_bounds__(kBlock) void k_probe_dist(DevIndex ix, const float*
   }
 }
 
+// Step 2a on integer-grid indexes, as an int8 contraction on the matrix cores:
+// ||q - c||^2 = ||q'||^2 + ||c'||^2 - 2 q'.c' with q' = q - s, c' = c - s
+// (s = 128 for uint8, 0 for int8) so both operands fit int8; every term is an
+// exact int32, hence the float32 result equals the oracle's exact value.
+// Block: 64 queries x 256 lists; wave w: all 64 queries x lists
+// [64w, 64w + 64) as 4 x 4 tiles of v_mfma_i32_16x16x64_i8 (K = 64 per step).
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+constexpr int kPM = 64;   // queries per probe block
+constexpr int kPN = 256;  // lists per probe block
+
+__global__ __launch_bounds__(kBlock) void k_probe_mfma(DevIndex ix, const float* __restrict__ Q,
+                                                        int qc, float* __restrict__ dist) {
+  extern __shared__ __align__(16) int8_t s_q8[];  // [kPM, dim_pad] then int32 norms [kPM]
+  const int Dp = ix.dim_pad, D = ix.dim;
+  int* s_qn = reinterpret_cast<int*>(s_q8 + kPM * Dp);
+  const int q0 = blockIdx.y * kPM;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < kPM * Dp; i += kBlock) {
+    const int qq = q0 + i / Dp, t = i % Dp;
+    int v = 0;
+    if (qq < qc && t < D) v = (int)conv_query(Q[(size_t)qq * D + t], ix.dtype) - ix.shift8;
+    s_q8[i] = (int8_t)v;
+  }
+  __syncthreads();
+  if (tid < kPM) {
+    int s = 0;
+    for (int t = 0; t < Dp; ++t) {
+      const int v = s_q8[tid * Dp + t];
+      s += v * v;
+    }
+    s_qn[tid] = s;
+  }
+  const int l0 = blockIdx.x * kPN + w * 64;
+  const int r16 = lane & 15, g = lane >> 4;
+  v4i_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4i_t{0, 0, 0, 0};
+  for (int k0 = 0; k0 < Dp; k0 += 64) {
+    v4i_t fa[4], fb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      fa[a] = *reinterpret_cast<const v4i_t*>(s_q8 + (a * 16 + r16) * Dp + k0 + 16 * g);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int l = l0 + b * 16 + r16;
+      fb[b] = l < ix.nlist
+                  ? *reinterpret_cast<const v4i_t*>(ix.cent8 + (size_t)l * Dp + k0 + 16 * g)
+                  : v4i_t{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+  }
+  __syncthreads();  // s_qn
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int l = l0 + b * 16 + r16;  // output column = lane % 16
+    if (l >= ix.nlist) continue;
+    const int cn = ix.cnorm8[l];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = a * 16 + 4 * g + r;  // output row = 4 * (lane / 16) + r
+        if (q0 + m < qc)
+          dist[(size_t)(q0 + m) * ix.nlist + l] = (float)(s_qn[m] + cn - 2 * acc[a][b][r]);
+      }
+    }
+  }
+}
+
 // Step 2b: per query, the np smallest (distance, list) keys, sorted.
+// Fast path (np <= kBlock): each thread takes the minimum key of its strided
+// share of the row; the np-th smallest of those minima is a threshold with at
+// least np keys at or below it, usually only a few more.  Those keys are
+// collected and sorted.  Otherwise (or if too many keys tie below the
+// threshold) a block radix select finds the exact np-th key.
+constexpr int kSelCand = 1024;
+
 __global__ __launch_bounds__(kBlock) void k_probe_select(const float* __restrict__ dist, int nlist,
                                                           const int32_t* __restrict__ nprobe,
                                                           int np_max, int32_t* __restrict__ lists,
                                                           float* __restrict__ out_d,
                                                           int32_t* __restrict__ np_eff) {
-  extern __shared__ uint64_t s_sel[];  // [pow2(np_max)]
+  extern __shared__ __align__(16) uint64_t s_sel[];  // [max(pow2(np_max), kSelCand)]
   __shared__ SelScratch ss;
+  __shared__ uint64_t s_min[kBlock];
   __shared__ int s_cnt;
-  const int q = blockIdx.x, tid = threadIdx.x;
+  const int q = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   int np = nprobe ? nprobe[q] : np_max;
   np = max(0, min(np, min(np_max, nlist)));
-  const int P = pow2_at_least(max(np, 1));
   const float* row = dist + (size_t)q * nlist;
   auto get = [&](int i) -> uint64_t { return ((uint64_t)ord32(row[i]) << 32) | (uint32_t)i; };
+  int P = pow2_at_least(max(np, 1));
   if (np > 0) {
-    const uint64_t K = (np == nlist) ? ~0ull : block_kth(get, nlist, np, &ss);
-    if (tid == 0) s_cnt = 0;
-    for (int i = np + tid; i < P; i += kBlock) s_sel[i] = ~0ull;
-    __syncthreads();
-    for (int i = tid; i < nlist; i += kBlock) {
-      const uint64_t k = get(i);
-      if (k <= K) {
-        const int pos = atomicAdd(&s_cnt, 1);
-        if (pos < P) s_sel[pos] = k;
+    bool done = false;
+    if (np < nlist && np <= kBlock) {
+      uint64_t mn = ~0ull;
+      for (int i = tid; i < nlist; i += kBlock) {
+        const uint64_t k = get(i);
+        mn = k < mn ? k : mn;
+      }
+      s_min[tid] = mn;
+      if (tid == 0) s_cnt = 0;
+      __syncthreads();
+      block_bitonic(s_min, kBlock);
+      const uint64_t tau = s_min[np - 1];
+      for (int i0 = 0; i0 < nlist; i0 += kBlock) {
+        const int i = i0 + tid;
+        uint64_t k = ~0ull;
+        bool take = false;
+        if (i < nlist) {
+          k = get(i);
+          take = k <= tau;
+        }
+        const uint64_t m = __ballot(take);
+        if (m) {
+          int base = 0;
+          if (lane == 0) base = atomicAdd(&s_cnt, (int)__popcll(m));
+          base = __shfl(base, 0, 64);
+          const int pos = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+          if (take && pos < kSelCand) s_sel[pos] = k;
+        }
+      }
+      __syncthreads();
+      const int cnt = s_cnt;
+      if (cnt <= kSelCand) {
+        P = pow2_at_least(cnt);
+        for (int i = cnt + tid; i < P; i += kBlock) s_sel[i] = ~0ull;
+        __syncthreads();
+        block_bitonic(s_sel, P);
+        done = true;
       }
     }
-    __syncthreads();
-    block_bitonic(s_sel, P);
+    if (!done) {
+      P = pow2_at_least(np);
+      const uint64_t K = (np == nlist) ? ~0ull : block_kth(get, nlist, np, &ss);
+      if (tid == 0) s_cnt = 0;
+      for (int i = np + tid; i < P; i += kBlock) s_sel[i] = ~0ull;
+      __syncthreads();
+      for (int i = tid; i < nlist; i += kBlock) {
+        const uint64_t k = get(i);
+        if (k <= K) {
+          const int pos = atomicAdd(&s_cnt, 1);
+          if (pos < P) s_sel[pos] = k;
+        }
+      }
+      __syncthreads();
+      block_bitonic(s_sel, P);
+    }
   }
   for (int p = tid; p < np_max; p += kBlock) {
     const bool v = p < np;
@@ -265,32 +421,37 @@ __global__ void k_count_lists(const int32_t* __restrict__ lists, int qc, int np_
 }
 
 // ---------------------------------------------------------------------------
-// Step 1: distance table.  Block (m, q), thread j = codeword.
+// Step 1: distance table entry [m][j] of one query (qrow = the query's raw
+// float32 values).  Integer-grid indexes: float32, exact; otherwise a float64
+// sum over t in order, rounded once.
 
-template <bool EXACT64>
-__global__ __launch_bounds__(kBlock) void k_lut(DevIndex ix, const float* __restrict__ Q, int qc,
-                                                 float* __restrict__ lut) {
-  const int m = blockIdx.x, q = blockIdx.y, j = threadIdx.x;
-  const float* qs = Q + (size_t)q * ix.dim + (size_t)m * ix.dsub;
+__device__ __forceinline__ float lut_entry(const DevIndex& ix, const float* __restrict__ qrow,
+                                           int m, int j) {
+  const float* qs = qrow + (size_t)m * ix.dsub;
   const float* c = ix.codebooks + ((size_t)m * kKsub + j) * ix.dsub;
-  float out;
-  if (EXACT64) {
+  if (!ix.int_grid) {
     double acc = 0.0;
     for (int t = 0; t < ix.dsub; ++t) {
       const double u = (double)conv_query(qs[t], ix.dtype) - (double)c[t];
       const double sq = u * u;
       acc = acc + sq;
     }
-    out = (float)acc;
-  } else {
-    float acc = 0.f;
-    for (int t = 0; t < ix.dsub; ++t) {
-      const float u = conv_query(qs[t], ix.dtype) - c[t];
-      acc = acc + u * u;
-    }
-    out = acc;
+    return (float)acc;
   }
-  lut[((size_t)q * ix.M + m) * kKsub + j] = out;
+  float acc = 0.f;
+  for (int t = 0; t < ix.dsub; ++t) {
+    const float u = conv_query(qs[t], ix.dtype) - c[t];
+    acc = acc + u * u;
+  }
+  return acc;
+}
+
+// One block per query, thread = codeword, loop over subspaces.
+__global__ __launch_bounds__(kBlock) void k_lut(DevIndex ix, const float* __restrict__ Q, int qc,
+                                                 float* __restrict__ lut) {
+  const int q = blockIdx.x, j = threadIdx.x;
+  const float* qrow = Q + (size_t)q * ix.dim;
+  for (int m = 0; m < ix.M; ++m) lut[((size_t)q * ix.M + m) * kKsub + j] = lut_entry(ix, qrow, m, j);
 }
 
 // ---------------------------------------------------------------------------
@@ -330,11 +491,12 @@ __host__ __device__ inline ScanLayout scan_layout(int M, int nlist, int R, int n
   L.pcnt = o; o += (size_t)np_max * 4;
   L.rst = o; o += (size_t)np_max * 4; o = align_up(o, 16);
   L.pre = o; o += (size_t)(np_max + 1) * 8; o = align_up(o, 16);
-  L.buf = o; o += (size_t)cap * 8;
-  L.tmp = o; o += (size_t)n * 8; o = align_up(o, 16);
+  L.buf = o; o += (size_t)cap * 8; o = align_up(o, 16);
+  L.tmp = o; o += (size_t)(kScanBlock / 64) * 4; o = align_up(o, 16);  // per-wave sums
   L.sel = o; o += sizeof(SelScratch); o = align_up(o, 16);
   L.misc = o; o += 32;
   L.total = align_up(o, 16);
+  (void)n;
   return L;
 }
 
@@ -346,15 +508,31 @@ struct ScanMisc {
   int pad;
 };
 
+// Exclusive prefix sum of v over the block (in thread order); s_wsum holds
+// one int per wave.  All threads must call.
+__device__ __forceinline__ int block_excl_scan(int v, int* s_wsum) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  if (lane == 63) s_wsum[wv] = incl;
+  __syncthreads();
+  int before = 0;
+  for (int i = 0; i < wv; ++i) before += s_wsum[i];
+  (void)nw;
+  return before + incl - v;
+}
+
 __device__ __forceinline__ bool testbit(const uint32_t* bits, int l) {
   return (bits[l >> 5] >> (l & 31)) & 1u;
 }
 
-// Eq. 1 for one code row: float32 sum over m = 0..M-1 in order.
+// Code row -> W dwords (natural alignment: rows are 4*W bytes apart).
 template <int W>
-__device__ __forceinline__ float adc_row(const uint8_t* __restrict__ rowp,
-                                         const float* __restrict__ s_lut, int M) {
-  uint32_t w[W];
+__device__ __forceinline__ void load_row(const uint8_t* __restrict__ rowp, uint32_t (&w)[W]) {
   if constexpr (W % 4 == 0) {
 #pragma unroll
     for (int i = 0; i < W / 4; ++i) {
@@ -371,6 +549,12 @@ __device__ __forceinline__ float adc_row(const uint8_t* __restrict__ rowp,
 #pragma unroll
     for (int i = 0; i < W; ++i) w[i] = reinterpret_cast<const uint32_t*>(rowp)[i];
   }
+}
+
+// Eq. 1 for one code row: float32 sum over m = 0..M-1 in order.
+template <int W>
+__device__ __forceinline__ float adc_words(const uint32_t (&w)[W], const float* __restrict__ s_lut,
+                                           int M) {
   float acc = 0.f;
 #pragma unroll
   for (int i = 0; i < W; ++i) {
@@ -384,21 +568,33 @@ __device__ __forceinline__ float adc_row(const uint8_t* __restrict__ rowp,
 }
 
 // Reduce s_buf[0..count) to its n smallest keys; threshold = the n-th key.
-__device__ void scan_compact(uint64_t* s_buf, uint64_t* s_tmp, SelScratch* ss, ScanMisc* mc, int n) {
+// In place: each thread stages a contiguous chunk of the buffer in registers,
+// the survivors' positions come from a block prefix sum, and every survivor
+// moves to a position no later than its own (all reads precede all writes).
+constexpr int kCompactChunk = 8;  // cap <= kCompactChunk * kScanBlock
+
+__device__ void scan_compact(uint64_t* s_buf, int* s_wsum, SelScratch* ss, ScanMisc* mc, int n) {
   const int cnt = mc->count;
   if (cnt <= n) return;
   const uint64_t K = block_kth([&](int i) { return s_buf[i]; }, cnt, n, ss);
-  if (threadIdx.x == 0) mc->ncount = 0;
-  __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += kBlock) {
-    const uint64_t k = s_buf[i];
-    if (k <= K) {
-      const int pos = atomicAdd(&mc->ncount, 1);
-      if (pos < n) s_tmp[pos] = k;
+  const int ch = (cnt + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int b0 = threadIdx.x * ch;
+  uint64_t r[kCompactChunk];
+  int c = 0;
+#pragma unroll
+  for (int i = 0; i < kCompactChunk; ++i) {
+    uint64_t k = ~0ull;
+    if (i < ch && b0 + i < cnt) {
+      k = s_buf[b0 + i];
+      if (k > K) k = ~0ull;
     }
+    r[i] = k;
+    c += k != ~0ull ? 1 : 0;
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += kBlock) s_buf[i] = s_tmp[i];
+  int pos = block_excl_scan(c, s_wsum);  // contains a barrier: all reads are done
+#pragma unroll
+  for (int i = 0; i < kCompactChunk; ++i)
+    if (r[i] != ~0ull) s_buf[pos++] = r[i];
   if (threadIdx.x == 0) {
     mc->count = n;
     mc->thr = K;
@@ -406,13 +602,19 @@ __device__ void scan_compact(uint64_t* s_buf, uint64_t* s_tmp, SelScratch* ss, S
   __syncthreads();
 }
 
+// One block = one work item (a contiguous range of one query's gathered
+// entries).  Each round, every thread takes kScanRT entries (stride
+// kScanBlock), resolves them to code rows, issues all row loads, then scores
+// them; keys below the current threshold go to the LDS buffer, which is cut
+// back to the n best whenever it holds more than n.
 template <int W, bool TRACE>
-__global__ __launch_bounds__(kBlock) void k_scan(
+__global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_scan(
     DevIndex ix, const int32_t* __restrict__ lists, const int32_t* __restrict__ np_eff, int np_max,
-    int qc, const float* __restrict__ lut, const int32_t* __restrict__ sq, int smax, int n, int cap,
-    int round_steps, uint64_t* __restrict__ pkeys, int32_t* __restrict__ pcount,
-    int32_t* __restrict__ pscan, int64_t t_capacity, int32_t* __restrict__ t_ids,
-    float* __restrict__ t_adc, unsigned long long* __restrict__ t_count) {
+    int qc, const float* __restrict__ Q, const float* __restrict__ lut,
+    const int32_t* __restrict__ sq, int smax, int n, int cap,
+    uint64_t* __restrict__ pkeys, int32_t* __restrict__ pcount, int32_t* __restrict__ pscan,
+    int64_t t_capacity, int32_t* __restrict__ t_ids, float* __restrict__ t_adc,
+    unsigned long long* __restrict__ t_count) {
   // Block -> (query, item) with all items of one query on the same XCD:
   // blocks are dispatched round-robin over the 8 XCDs.
   const int b = blockIdx.x;
@@ -435,21 +637,25 @@ __global__ __launch_bounds__(kBlock) void k_scan(
   int32_t* s_rst = reinterpret_cast<int32_t*>(smem + L.rst);
   int64_t* s_pre = reinterpret_cast<int64_t*>(smem + L.pre);
   uint64_t* s_buf = reinterpret_cast<uint64_t*>(smem + L.buf);
-  uint64_t* s_tmp = reinterpret_cast<uint64_t*>(smem + L.tmp);
+  int* s_wsum = reinterpret_cast<int*>(smem + L.tmp);
   SelScratch* ss = reinterpret_cast<SelScratch*>(smem + L.sel);
   ScanMisc* mc = reinterpret_cast<ScanMisc*>(smem + L.misc);
 
-  // Distance table of this query into LDS.
-  {
+  // Distance table of this query into LDS: computed here (step 1 fused into
+  // the scan) unless the caller passed one in.
+  if (lut) {
     const float4* src = reinterpret_cast<const float4*>(lut + (size_t)q * M * kKsub);
     float4* dst = reinterpret_cast<float4*>(s_lut);
-    for (int i = tid; i < M * (kKsub / 4); i += kBlock) dst[i] = src[i];
+    for (int i = tid; i < M * (kKsub / 4); i += kScanBlock) dst[i] = src[i];
+  } else {
+    const float* qrow = Q + (size_t)q * ix.dim;
+    for (int i = tid; i < M * kKsub; i += kScanBlock) s_lut[i] = lut_entry(ix, qrow, i >> 8, i & 255);
   }
   const int nwords = (ix.nlist + 31) / 32;
   if (ix.R > 1)
-    for (int i = tid; i < nwords; i += kBlock) s_bits[i] = 0u;
+    for (int i = tid; i < nwords; i += kScanBlock) s_bits[i] = 0u;
   const int np = np_eff[q];
-  for (int p = tid; p < np; p += kBlock) {
+  for (int p = tid; p < np; p += kScanBlock) {
     const int l = lists[(size_t)q * np_max + p];
     const int a = ix.pstart[l];
     s_list[p] = l;
@@ -464,7 +670,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(
   }
   __syncthreads();
   if (ix.R > 1)
-    for (int p = tid; p < np; p += kBlock) {
+    for (int p = tid; p < np; p += kScanBlock) {
       const int l = s_list[p];
       atomicOr(&s_bits[l >> 5], 1u << (l & 31));
     }
@@ -483,46 +689,62 @@ __global__ __launch_bounds__(kBlock) void k_scan(
   const int lane = tid & 63;
   const uint64_t lanemask = (1ull << lane) - 1ull;
   int scanned = 0;
+  int cur = 0;  // list slot of this thread's current entry (entries only increase)
 
-  for (int64_t base = e0; base < e1; base += (int64_t)kBlock * round_steps) {
+  for (int64_t base = e0; base < e1; base += (int64_t)kScanBlock * kScanRT) {
     const uint64_t thr = mc->thr;
     const uint32_t thr_hi = (uint32_t)(thr >> 32);
-    for (int u = 0; u < round_steps; ++u) {
-      const int64_t e = base + (int64_t)u * kBlock + tid;
-      bool keep = false;
-      int row = 0;
+    int rows[kScanRT];
+    bool keep[kScanRT];
+    // resolve entries -> rows; replica entries owned by an earlier probed list are dropped
+#pragma unroll
+    for (int u = 0; u < kScanRT; ++u) {
+      const int64_t e = base + (int64_t)u * kScanBlock + tid;
+      keep[u] = false;
+      rows[u] = 0;
       if (e < e1) {
-        int lo = 0, hi = np - 1;  // last p with s_pre[p] <= e
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
-        }
-        const int64_t o = e - s_pre[lo];
-        if (o < s_pcnt[lo]) {
-          row = s_pst[lo] + (int)o;
-          keep = true;
+        while (s_pre[cur + 1] <= e) ++cur;  // s_pre[np] = E > e bounds the walk
+        const int64_t o = e - s_pre[cur];
+        if (o < s_pcnt[cur]) {
+          rows[u] = s_pst[cur] + (int)o;
+          keep[u] = true;
         } else {
-          const int2 r = ix.rep[s_rst[lo] + (o - s_pcnt[lo])];
-          row = (int)((uint32_t)r.x & kRowMask);
+          const int2 r = ix.rep[s_rst[cur] + (o - s_pcnt[cur])];
+          const int row = (int)((uint32_t)r.x & kRowMask);
           const int rank = (int)((uint32_t)r.x >> kRankShift);
-          keep = !testbit(s_bits, r.y);
-          for (int i = 1; i < rank && keep; ++i)
-            keep = !testbit(s_bits, ix.assign_rows[(size_t)row * ix.R + i]);
+          bool k = !testbit(s_bits, r.y);
+          for (int i = 1; i < rank && k; ++i)
+            k = !testbit(s_bits, ix.assign_rows[(size_t)row * ix.R + i]);
+          rows[u] = row;
+          keep[u] = k;
         }
       }
-      float acc = 0.f;
-      if (keep) acc = adc_row<W>(ix.codes + (size_t)row * ix.row_bytes, s_lut, M);
-      scanned += keep ? 1 : 0;
+    }
+    // all code-row loads of the round in flight together
+    uint32_t cw[kScanRT][W];
+#pragma unroll
+    for (int u = 0; u < kScanRT; ++u) {
+      if (keep[u]) {
+        load_row<W>(ix.codes + (size_t)rows[u] * ix.row_bytes, cw[u]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < W; ++i) cw[u][i] = 0u;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kScanRT; ++u) {
+      const float acc = adc_words<W>(cw[u], s_lut, M);
+      scanned += keep[u] ? 1 : 0;
       if constexpr (TRACE) {
-        const uint64_t m = __ballot(keep);
+        const uint64_t m = __ballot(keep[u]);
         if (m) {
           unsigned long long bpos = 0;
           if (lane == 0) bpos = atomicAdd(&t_count[q], (unsigned long long)__popcll(m));
           bpos = __shfl(bpos, 0, 64);
-          if (keep) {
+          if (keep[u]) {
             const unsigned long long pos = bpos + __popcll(m & lanemask);
             if ((int64_t)pos < t_capacity) {
-              t_ids[(size_t)q * t_capacity + pos] = ix.row2ext[row];
+              t_ids[(size_t)q * t_capacity + pos] = ix.row2ext[rows[u]];
               t_adc[(size_t)q * t_capacity + pos] = acc;
             }
           }
@@ -530,10 +752,10 @@ __global__ __launch_bounds__(kBlock) void k_scan(
       } else {
         bool pass = false;
         uint64_t key = 0;
-        if (keep) {
+        if (keep[u]) {
           const uint32_t h = ord32(acc);
           if (h <= thr_hi) {
-            key = ((uint64_t)h << 32) | (uint32_t)ix.row2ext[row];
+            key = ((uint64_t)h << 32) | (uint32_t)ix.row2ext[rows[u]];
             pass = key < thr;
           }
         }
@@ -548,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(
     }
     __syncthreads();
     if constexpr (!TRACE) {
-      if (mc->count > cap - kBlock * round_steps) scan_compact(s_buf, s_tmp, ss, mc, n);
+      if (mc->count > n) scan_compact(s_buf, s_wsum, ss, mc, n);
     }
   }
   // candidates scored by this item
@@ -560,10 +782,10 @@ __global__ __launch_bounds__(kBlock) void k_scan(
   }
   __syncthreads();
   if constexpr (!TRACE) {
-    scan_compact(s_buf, s_tmp, ss, mc, n);
+    scan_compact(s_buf, s_wsum, ss, mc, n);
     const int cnt = min(mc->count, n);
     uint64_t* dst = pkeys + ((size_t)q * smax + j) * n;
-    for (int i = tid; i < cnt; i += kBlock) dst[i] = s_buf[i];
+    for (int i = tid; i < cnt; i += kScanBlock) dst[i] = s_buf[i];
     if (tid == 0) {
       pcount[(size_t)q * smax + j] = cnt;
       pscan[(size_t)q * smax + j] = mc->scanned;
@@ -605,21 +827,110 @@ __device__ __forceinline__ float exact_row(const DevIndex& ix, const float* __re
   return (float)acc;
 }
 
+// Integer rows of 16*G bytes: G lanes per candidate, one 16-byte chunk per
+// lane, 4 candidates per lane group in flight.  Exact integer sums.
+template <int G>
+__device__ void rerank_int16(const DevIndex& ix, const float* s_q, const uint64_t* s_top, int nn,
+                             uint64_t* s_key2, int P) {
+  const int lg = threadIdx.x % G, grp = threadIdx.x / G, ngrp = blockDim.x / G;
+  int qv[16];
+#pragma unroll
+  for (int b = 0; b < 16; ++b) qv[b] = (int)s_q[lg * 16 + b];
+  const bool u8 = ix.dtype == U8;
+  constexpr int U = 4;
+  for (int i0 = 0; i0 < P; i0 += ngrp * U) {
+    uint4 v[U];
+    uint32_t id[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * ngrp + grp;
+      ok[u] = i < nn;
+      id[u] = ok[u] ? (uint32_t)s_top[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = make_uint4(0u, 0u, 0u, 0u);
+      if (ok[u])
+        v[u] = *reinterpret_cast<const uint4*>(static_cast<const uint8_t*>(ix.vecs) +
+                                               (size_t)ix.ext2row[id[u]] * ix.dim + lg * 16);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t w4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+      int acc = 0;
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        const uint32_t byte = (w4[b >> 2] >> (8 * (b & 3))) & 255u;
+        const int xv = u8 ? (int)byte : (int)(int8_t)(uint8_t)byte;
+        const int d = qv[b] - xv;
+        acc += d * d;
+      }
+#pragma unroll
+      for (int d = 1; d < G; d <<= 1) acc += __shfl_xor(acc, d, 64);
+      const int i = i0 + u * ngrp + grp;
+      if (lg == 0 && i < P)
+        s_key2[i] = ok[u] ? (((uint64_t)ord32((float)acc) << 32) | id[u]) : ~0ull;
+    }
+  }
+}
+
 // Re-rank s_top[0..nn) (keys of (adc, id)) by exact distance and write top-k.
 __device__ void rerank_write(const DevIndex& ix, const float* s_q, const uint64_t* s_top, int nn,
                              uint64_t* s_key2, int P, int k, int64_t* out_ids, float* out_d) {
-  for (int i = threadIdx.x; i < P; i += kBlock) {
-    uint64_t key = ~0ull;
-    if (i < nn) {
-      const uint32_t id = (uint32_t)s_top[i];
-      const float e = exact_row(ix, s_q, ix.ext2row[id]);
-      key = ((uint64_t)ord32(e) << 32) | id;
+  const int g16 = ix.dim % 16 == 0 ? ix.dim / 16 : 0;
+  if (ix.dtype != F32 && (g16 == 1 || g16 == 2 || g16 == 4 || g16 == 8 || g16 == 16)) {
+    switch (g16) {
+      case 1: rerank_int16<1>(ix, s_q, s_top, nn, s_key2, P); break;
+      case 2: rerank_int16<2>(ix, s_q, s_top, nn, s_key2, P); break;
+      case 4: rerank_int16<4>(ix, s_q, s_top, nn, s_key2, P); break;
+      case 8: rerank_int16<8>(ix, s_q, s_top, nn, s_key2, P); break;
+      default: rerank_int16<16>(ix, s_q, s_top, nn, s_key2, P); break;
     }
-    s_key2[i] = key;
+  } else if (ix.dtype != F32 && ix.dim % 4 == 0) {
+    // integer data: 8 lanes per candidate, each summing every 8th dword of
+    // the row (exact integers, so the summation order is free)
+    const int g = threadIdx.x >> 3, jl = threadIdx.x & 7, ng = blockDim.x >> 3;
+    const int nd = ix.dim >> 2;
+    for (int i0 = 0; i0 < P; i0 += ng) {
+      const int i = i0 + g;
+      int acc = 0;
+      uint32_t id = 0;
+      if (i < nn) {
+        id = (uint32_t)s_top[i];
+        const uint32_t* x = reinterpret_cast<const uint32_t*>(
+            static_cast<const uint8_t*>(ix.vecs) + (size_t)ix.ext2row[id] * ix.dim);
+        for (int t = jl; t < nd; t += 8) {
+          const uint32_t v = x[t];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int xv = ix.dtype == U8 ? (int)((v >> (8 * b)) & 255u)
+                                          : (int)(int8_t)(uint8_t)((v >> (8 * b)) & 255u);
+            const int u = (int)s_q[4 * t + b] - xv;
+            acc += u * u;
+          }
+        }
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      acc += __shfl_xor(acc, 4, 64);
+      if (jl == 0 && i < P)
+        s_key2[i] = i < nn ? (((uint64_t)ord32((float)acc) << 32) | id) : ~0ull;
+    }
+  } else {
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+      uint64_t key = ~0ull;
+      if (i < nn) {
+        const uint32_t id = (uint32_t)s_top[i];
+        const float e = exact_row(ix, s_q, ix.ext2row[id]);
+        key = ((uint64_t)ord32(e) << 32) | id;
+      }
+      s_key2[i] = key;
+    }
   }
   __syncthreads();
   block_bitonic(s_key2, P);
-  for (int i = threadIdx.x; i < k; i += kBlock) {
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
     const bool v = i < nn;
     out_ids[i] = v ? (int64_t)(uint32_t)s_key2[i] : -1;
     out_d[i] = v ? unord32((uint32_t)(s_key2[i] >> 32)) : INFINITY;
@@ -634,9 +945,9 @@ __host__ __device__ inline MergeLayout merge_layout(int smax, int n, int dim) {
   MergeLayout L;
   const int P = pow2_at_least(n);
   size_t o = 0;
-  L.keys = o; o += (size_t)smax * n * 8;
+  // the re-rank keys reuse the partial-key area once the top-n is selected
+  L.keys = o; L.key2 = o; o += (size_t)std::max(smax * n, P) * 8;
   L.top = o; o += (size_t)P * 8;
-  L.key2 = o; o += (size_t)P * 8;
   L.q = o; o += (size_t)dim * 4; o = align_up(o, 16);
   L.sel = o; o += sizeof(SelScratch); o = align_up(o, 16);
   L.misc = o; o += 16 + 4 * 17;
@@ -697,16 +1008,18 @@ __global__ __launch_bounds__(kBlock) void k_merge(
     for (int i = tid; i < total; i += kBlock) s_top[i] = s_keys[i];
   }
   __syncthreads();
-  block_bitonic(s_top, P);
   if (topn_ids) {
+    block_bitonic(s_top, P);
     for (int i = tid; i < n; i += kBlock) {
       const bool v = i < nn;
       topn_ids[(size_t)q * n + i] = v ? (int32_t)(uint32_t)s_top[i] : -1;
       topn_adc[(size_t)q * n + i] = v ? unord32((uint32_t)(s_top[i] >> 32)) : INFINITY;
     }
   }
-  if (out_ids)
+  if (out_ids) {
+    __syncthreads();  // s_key2 aliases s_keys
     rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k, out_dists + (size_t)q * k);
+  }
 }
 
 // Step 8 for caller-provided candidates.
@@ -735,10 +1048,10 @@ __global__ __launch_bounds__(kBlock) void k_rerank_only(DevIndex ix, const float
 
 template <int W>
 hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t* np_eff,
-                         int np_max, int qc, const float* lut, const int32_t* sq, int smax, int n,
-                         int cap, int round_steps, uint64_t* pkeys, int32_t* pcount, int32_t* pscan,
-                         bool trace, int64_t t_capacity, int32_t* t_ids, float* t_adc,
-                         int64_t* t_count, hipStream_t st) {
+                         int np_max, int qc, const float* Q, const float* lut, const int32_t* sq,
+                         int smax, int n, int cap, uint64_t* pkeys, int32_t* pcount,
+                         int32_t* pscan, bool trace, int64_t t_capacity, int32_t* t_ids,
+                         float* t_adc, int64_t* t_count, hipStream_t st) {
   const ScanLayout L = scan_layout(ix.M, ix.nlist, ix.R, np_max, n, cap);
   const int qpad = (qc + 7) / 8 * 8;
   const dim3 grid((unsigned)((size_t)qpad * smax));
@@ -746,22 +1059,22 @@ hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t
     auto kern = k_scan<W, true>;
     if (L.total > 65536)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
-    hipLaunchKernelGGL(kern, grid, dim3(kBlock), L.total, st, ix, lists, np_eff, np_max, qc, lut,
-                       sq, smax, n, cap, round_steps, pkeys, pcount, pscan, t_capacity, t_ids,
-                       t_adc, reinterpret_cast<unsigned long long*>(t_count));
+    hipLaunchKernelGGL(kern, grid, dim3(kScanBlock), L.total, st, ix, lists, np_eff, np_max, qc,
+                       Q, lut, sq, smax, n, cap, pkeys, pcount, pscan, t_capacity, t_ids, t_adc,
+                       reinterpret_cast<unsigned long long*>(t_count));
   } else {
     auto kern = k_scan<W, false>;
     if (L.total > 65536)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
-    hipLaunchKernelGGL(kern, grid, dim3(kBlock), L.total, st, ix, lists, np_eff, np_max, qc, lut,
-                       sq, smax, n, cap, round_steps, pkeys, pcount, pscan, t_capacity, t_ids,
-                       t_adc, reinterpret_cast<unsigned long long*>(t_count));
+    hipLaunchKernelGGL(kern, grid, dim3(kScanBlock), L.total, st, ix, lists, np_eff, np_max, qc,
+                       Q, lut, sq, smax, n, cap, pkeys, pcount, pscan, t_capacity, t_ids, t_adc,
+                       reinterpret_cast<unsigned long long*>(t_count));
   }
   return hipGetLastError();
 }
 
 using ScanFn = hipError_t (*)(const DevIndex&, const int32_t*, const int32_t*, int, int,
-                              const float*, const int32_t*, int, int, int, int, uint64_t*,
+                              const float*, const float*, const int32_t*, int, int, int, uint64_t*,
                               int32_t*, int32_t*, bool, int64_t, int32_t*, float*, int64_t*,
                               hipStream_t);
 
@@ -783,8 +1096,8 @@ ScanFn scan_fn(int W) {
 
 int scan_smax(int n) { return std::max(1, std::min(16, 4096 / std::max(n, 1))); }
 
-size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n, int round_steps) {
-  return scan_layout(ix.M, ix.nlist, ix.R, np_max, n, n + kBlock * round_steps).total;
+size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n) {
+  return scan_layout(ix.M, ix.nlist, ix.R, np_max, n, n + kScanBlock * kScanRT).total;
 }
 
 static bool exact64(const DevIndex& ix) { return !ix.int_grid; }
@@ -793,13 +1106,22 @@ hipError_t launch_probe(const DevIndex& ix, const float* q, const int32_t* nprob
                         int qc, Work& w, float* out_dists_opt, int32_t* out_lists,
                         hipStream_t st) {
   if (qc <= 0) return hipSuccess;
-  const dim3 g1((ix.nlist + kBlock - 1) / kBlock, (qc + kProbeQT - 1) / kProbeQT);
-  const size_t lds1 = (size_t)kProbeQT * ix.dim * 4;
-  if (exact64(ix))
-    hipLaunchKernelGGL(k_probe_dist<true>, g1, dim3(kBlock), lds1, st, ix, q, qc, w.dist);
-  else
-    hipLaunchKernelGGL(k_probe_dist<false>, g1, dim3(kBlock), lds1, st, ix, q, qc, w.dist);
-  const size_t lds2 = (size_t)pow2_at_least(np_max) * 8;
+  if (ix.cent8) {
+    const dim3 g((ix.nlist + kPN - 1) / kPN, (qc + kPM - 1) / kPM);
+    const size_t lds = (size_t)kPM * ix.dim_pad + kPM * 4;
+    hipLaunchKernelGGL(k_probe_mfma, g, dim3(kBlock), lds, st, ix, q, qc, w.dist);
+  } else {
+    const dim3 g1((ix.nlist + kBlock - 1) / kBlock, (qc + kProbeQT - 1) / kProbeQT);
+    const size_t lds1 = (size_t)kProbeQT * ix.dim * 4;
+    if (exact64(ix))
+      hipLaunchKernelGGL(k_probe_dist<true>, g1, dim3(kBlock), lds1, st, ix, q, qc, w.dist);
+    else
+      hipLaunchKernelGGL(k_probe_dist<false>, g1, dim3(kBlock), lds1, st, ix, q, qc, w.dist);
+  }
+  const size_t lds2 = (size_t)std::max(pow2_at_least(np_max), kSelCand) * 8;
+  if (lds2 > 65536)
+    (void)hipFuncSetAttribute((const void*)k_probe_select,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
   hipLaunchKernelGGL(k_probe_select, dim3(qc), dim3(kBlock), lds2, st, w.dist, ix.nlist, nprobe,
                      np_max, out_lists, out_dists_opt, w.np_eff);
   return hipGetLastError();
@@ -807,22 +1129,18 @@ hipError_t launch_probe(const DevIndex& ix, const float* q, const int32_t* nprob
 
 hipError_t launch_lut(const DevIndex& ix, const float* q, int qc, float* out_lut, hipStream_t st) {
   if (qc <= 0) return hipSuccess;
-  const dim3 g(ix.M, qc);
-  if (exact64(ix))
-    hipLaunchKernelGGL(k_lut<true>, g, dim3(kKsub), 0, st, ix, q, qc, out_lut);
-  else
-    hipLaunchKernelGGL(k_lut<false>, g, dim3(kKsub), 0, st, ix, q, qc, out_lut);
+  hipLaunchKernelGGL(k_lut, dim3(qc), dim3(kKsub), 0, st, ix, q, qc, out_lut);
   return hipGetLastError();
 }
 
 hipError_t launch_scan(const DevIndex& ix, const int32_t* lists, const int32_t* np_eff,
-                       const float* lut, const LaunchCfg& c, Work& w, hipStream_t st) {
+                       const float* q, const LaunchCfg& c, Work& w, hipStream_t st) {
   if (c.qc <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_plan, dim3((c.qc + 255) / 256), dim3(256), 0, st, ix, lists, np_eff,
                      c.np_max, c.qc, c.tile, c.smax, w.eq, w.sq);
   const int W = (ix.M + 3) / 4;
-  const int cap = c.n + kBlock * c.round_steps;
-  return scan_fn(W)(ix, lists, np_eff, c.np_max, c.qc, lut, w.sq, c.smax, c.n, cap, c.round_steps,
+  const int cap = c.n + kScanBlock * kScanRT;
+  return scan_fn(W)(ix, lists, np_eff, c.np_max, c.qc, q, nullptr, w.sq, c.smax, c.n, cap,
                     w.pkeys, w.pcount, w.pscan, false, 0, nullptr, nullptr, nullptr, st);
 }
 
@@ -837,8 +1155,8 @@ hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const flo
                      qc, tile, smax, w.eq, w.sq);
   hipLaunchKernelGGL(k_zero_i64, dim3((qc + 255) / 256), dim3(256), 0, st, out_count, qc);
   const int W = (ix.M + 3) / 4;
-  return scan_fn(W)(ix, lists, w.np_eff, np_max, qc, lut, w.sq, smax, 1, 1, 1, nullptr, nullptr,
-                    nullptr, true, capacity, out_ids, out_adc, out_count, st);
+  return scan_fn(W)(ix, lists, w.np_eff, np_max, qc, nullptr, lut, w.sq, smax, 1, 1, nullptr,
+                    nullptr, nullptr, true, capacity, out_ids, out_adc, out_count, st);
 }
 
 hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,

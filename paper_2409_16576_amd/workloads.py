@@ -41,6 +41,7 @@ class Workload:
     sub_centres: int = 1    # > 1: each centre spawns this many sub-centres
     sub_sigma: float = 0.0
     kmeans_iters: int = 10
+    rerank_n_op: int = 0    # smallest swept rerank_n with oracle recall@10 >= 0.9 (0: rerank_n)
 
     def describe(self) -> dict:
         return {"workload": self.name, "n": self.n, "dim": self.dim, "dtype": self.kind,
@@ -51,10 +52,10 @@ class Workload:
 
 # 100k x 128-d float32, 256 centres U[0,100], sigma 5; 1024 lists; PQ 16 x 256.
 IVF_F32_100K = Workload("ivf_f32_100k", 1, 100_000, 128, "f32", 256, 0.0, 100.0, 5.0,
-                        1024, 16, 1000, 32, 100)
+                        1024, 16, 1000, 32, 100, rerank_n_op=400)
 # 10M x 128-d uint8, 4096 centres; 16384 lists; PQ 32 x 256.
 IVF_U8_10M = Workload("ivf_u8_10m", 2, 10_000_000, 128, "u8", 4096, 0.0, 255.0, 10.0,
-                      16384, 32, 10_000, 64, 200)
+                      16384, 32, 10_000, 64, 200, rerank_n_op=1400)
 # 5M x 96-d unit-norm float32, 2048 centres x 4 sub-centres, Zipf(1.1) weights;
 # 8192 lists; PQ 24 x 256; per-query nprobe U{8..128}.
 ZIPF_F32_5M = Workload("zipf_f32_5m", 3, 5_000_000, 96, "f32", 2048, 0.0, 0.0, 0.3,

@@ -137,7 +137,7 @@ def test_gather_dedup_adc_bit_exact(name, indexes, gpu_index, orc):
 
 
 @pytest.mark.parametrize("name", KINDS)
-@pytest.mark.parametrize("n", [1, 10, 100, 257])
+@pytest.mark.parametrize("n", [1, 10, 100, 257, 1400, 4096])
 def test_topn_bit_exact(name, n, indexes, gpu_index, orc):
     ix, _, Q = indexes[name]
     g = gpu_index(name)
@@ -158,7 +158,7 @@ def test_search_bit_exact(name, indexes, gpu_index, orc):
     _say("search", name)
     rng = np.random.default_rng(9)
     npr = rng.integers(1, 20, size=len(Q)).astype(np.int32)
-    for k, n in ((10, 10), (10, 64), (7, 200), (1, 1000)):
+    for k, n in ((10, 10), (10, 64), (7, 200), (1, 1000), (10, 1400), (32, 4096)):
         ids, d = g.search(_cuda(Q), _cuda(npr), k, n)
         torch.cuda.synchronize()
         r = orc.search(ix, Q, npr, k, n)
@@ -247,3 +247,32 @@ def test_errors(indexes, gpu_index, ann):
         g.search(Q, 4, 10, 5000)       # rerank_n too large
     with pytest.raises(ann.AnnError):
         ann.Index("/nonexistent/file", 0)
+    with pytest.raises(ann.AnnError):
+        g.set_option(g.OPT_SCAN_TILE, 3)
+    with pytest.raises(ann.AnnError):
+        g.set_option(99, 1)
+
+
+@pytest.mark.parametrize("name", KINDS)
+@pytest.mark.parametrize("tile,split", [(64, 16), (700, 3), (5000, 2)])
+def test_work_split_does_not_change_results(name, tile, split, indexes, gpu_index, orc):
+    """Splitting a query's entries over several work items (then merging their
+    partial top-n) gives the same bits as the single-item scan."""
+    ix, _, Q = indexes[name]
+    g = gpu_index(name)
+    _say("split", name, tile, split)
+    g.set_option(g.OPT_SCAN_TILE, tile)
+    g.set_option(g.OPT_SCAN_SPLIT, split)
+    try:
+        assert g.get_option(g.OPT_SCAN_TILE) == tile
+        for n in (10, 100, 1400):
+            ids, adc, nc = g.search_topn(_cuda(Q), 13, n)
+            r = orc.search(ix, Q, 13, 10, n)
+            assert np.array_equal(ids.cpu().numpy(), r.topn_ids), n
+            assert np.array_equal(adc.cpu().numpy(), r.topn_adc), n
+            assert np.array_equal(nc.cpu().numpy(), r.ncand), n
+            ids, d = g.search(_cuda(Q), 13, 10, n)
+            assert np.array_equal(ids.cpu().numpy(), r.ids) and np.array_equal(d.cpu().numpy(), r.dists)
+    finally:
+        g.set_option(g.OPT_SCAN_TILE, 65536)
+        g.set_option(g.OPT_SCAN_SPLIT, 16)

@@ -189,6 +189,39 @@ enum { ANN_OPT_SCAN_TILE = 1, ANN_OPT_SCAN_SPLIT = 2 };
 ann_status ann_set_option(ann_index* ix, int option, int64_t value);
 ann_status ann_get_option(ann_index* ix, int option, int64_t* value);
 
+/*
+ * Differentiable PQ distance with fixed codes (codebook fine-tuning).
+ * Eq. 1 with dist = squared L2 of sub-vectors, as a function of the queries
+ * and the codebooks:  Dhat[b][c] = sum_m ||q_b,m - CB[m][code[c][m]]||^2.
+ *   d_queries   float32 [B, M*dsub]
+ *   d_codebooks float32 [M, 256, dsub]   (dsub <= 16, M*256*4 <= 64 KiB)
+ *   d_codes     uint8   [C, M]
+ *   d_out       float32 [B, C]
+ * Index-free: works on any caller tensors.  float32 arithmetic.
+ */
+ann_status ann_adc_forward(const float* d_queries, int64_t B, const float* d_codebooks, int32_t M,
+                           int32_t dsub, const uint8_t* d_codes, int64_t C, float* d_out,
+                           void* stream);
+
+/* Bytes of device workspace ann_adc_backward needs for these sizes. */
+size_t ann_adc_backward_workspace(int64_t B, int64_t C, int32_t M, int32_t dsub);
+
+/*
+ * Backward of ann_adc_forward given d_grad = dL/dDhat float32 [B, C]:
+ *   d_dq  float32 [B, M*dsub] (may be NULL):
+ *         dQ[b] = 2 (sum_c G[b][c]) q_b - 2 sum_c G[b][c] dec(c)
+ *   d_dcb float32 [M, 256, dsub] (may be NULL):
+ *         dCB[m][j] = -2 sum_{c: code[c][m]=j} sum_b G[b][c] (q_b,m - CB[m][j])
+ * Codewords no candidate uses get exactly zero gradient; results do not depend
+ * on thread timing (no floating-point atomics).  d_workspace: caller-owned
+ * device memory of at least ann_adc_backward_workspace(...) bytes (the call
+ * allocates nothing).
+ */
+ann_status ann_adc_backward(const float* d_queries, int64_t B, const float* d_codebooks,
+                            int32_t M, int32_t dsub, const uint8_t* d_codes, int64_t C,
+                            const float* d_grad, float* d_dq, float* d_dcb, void* d_workspace,
+                            size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

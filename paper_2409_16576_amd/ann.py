@@ -72,6 +72,12 @@ def lib():
         L.ann_get_profile.argtypes = [P, ctypes.POINTER(Profile), ctypes.c_int]
         L.ann_set_option.argtypes = [P, ctypes.c_int, i64]
         L.ann_get_option.argtypes = [P, ctypes.c_int, ctypes.POINTER(i64)]
+        L.ann_adc_forward.argtypes = [P, i64, P, i32, i32, P, i64, P, P]
+        L.ann_adc_forward.restype = ctypes.c_int
+        L.ann_adc_backward_workspace.argtypes = [i64, i64, i32, i32]
+        L.ann_adc_backward_workspace.restype = ctypes.c_size_t
+        L.ann_adc_backward.argtypes = [P, i64, P, i32, i32, P, i64, P, P, P, P, ctypes.c_size_t, P]
+        L.ann_adc_backward.restype = ctypes.c_int
         for f in ("ann_load_index", "ann_index_info", "ann_search", "ann_search_topn", "ann_probe",
                   "ann_lut", "ann_scan_trace", "ann_rerank", "ann_set_profiling",
                   "ann_get_profile", "ann_set_option", "ann_get_option"):
@@ -217,3 +223,55 @@ class Index:
         v = ctypes.c_int64()
         _check(lib().ann_get_option(self._h, int(option), ctypes.byref(v)))
         return v.value
+
+
+# -- differentiable PQ distance (ann_adc_forward / ann_adc_backward) ------------------
+
+def _adc_args(Q, CB, codes):
+    if not (Q.is_cuda and Q.dtype == torch.float32 and Q.dim() == 2):
+        raise ValueError("queries must be a float32 CUDA tensor [B, D]")
+    if not (CB.is_cuda and CB.dtype == torch.float32 and CB.dim() == 3 and CB.shape[1] == 256):
+        raise ValueError("codebooks must be a float32 CUDA tensor [M, 256, dsub]")
+    if not (codes.is_cuda and codes.dtype == torch.uint8 and codes.dim() == 2
+            and codes.shape[1] == CB.shape[0]):
+        raise ValueError("codes must be a uint8 CUDA tensor [C, M]")
+    if Q.shape[1] != CB.shape[0] * CB.shape[2]:
+        raise ValueError("query dimension must equal M * dsub")
+    return Q.contiguous(), CB.contiguous(), codes.contiguous()
+
+
+class ADCDistance(torch.autograd.Function):
+    """Dhat[b, c] = sum_m ||Q[b, m-block] - CB[m, codes[c, m]]||^2 with codes fixed;
+    forward and backward run in the library's kernels."""
+
+    @staticmethod
+    def forward(ctx, Q, CB, codes):
+        Q, CB, codes = _adc_args(Q, CB, codes)
+        B, C = Q.shape[0], codes.shape[0]
+        M, dsub = CB.shape[0], CB.shape[2]
+        out = torch.empty((B, C), dtype=torch.float32, device=Q.device)
+        _check(lib().ann_adc_forward(_ptr(Q), B, _ptr(CB), M, dsub, _ptr(codes), C, _ptr(out),
+                                     _stream(Q.device, None)))
+        ctx.save_for_backward(Q, CB, codes)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad):
+        Q, CB, codes = ctx.saved_tensors
+        G = grad.contiguous().to(torch.float32)
+        B, C = Q.shape[0], codes.shape[0]
+        M, dsub = CB.shape[0], CB.shape[2]
+        nbytes = lib().ann_adc_backward_workspace(B, C, M, dsub)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=Q.device)
+        dQ = torch.empty_like(Q) if ctx.needs_input_grad[0] else None
+        dCB = torch.empty_like(CB) if ctx.needs_input_grad[1] else None
+        _check(lib().ann_adc_backward(_ptr(Q), B, _ptr(CB), M, dsub, _ptr(codes), C, _ptr(G),
+                                      _ptr(dQ), _ptr(dCB), _ptr(ws), nbytes,
+                                      _stream(Q.device, None)))
+        return dQ, dCB, None
+
+
+def adc_distance(Q, CB, codes):
+    """Differentiable PQ distance (see ADCDistance)."""
+    return ADCDistance.apply(Q, CB, codes)
+

@@ -33,6 +33,20 @@ ann_status fail(ann_status s, const char* fmt, ...) {
   return s;
 }
 
+}  // namespace
+
+int ann::set_error(int s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+namespace {
+
 #define HIP_TRY(expr)                                                                     \
   do {                                                                                    \
     hipError_t e_ = (expr);                                                               \
@@ -461,8 +475,27 @@ extern "C" ann_status ann_load_index(const char* path, int device, ann_index** o
     }
     if (nprim != pstart[l + 1] - pstart[l])
       return fail(ANN_EFORMAT, "list %d misses some of its first-list vectors", l);
+    // group this list's replica entries by their vector's first list (then row)
+    std::sort(rep.begin() + rstart[l], rep.end(), [](const int2& x, const int2& y) {
+      const uint32_t rx = (uint32_t)x.x & kRowMask, ry = (uint32_t)y.x & kRowMask;
+      return x.y < y.y || (x.y == y.y && rx < ry);
+    });
   }
   rstart[nlist] = (int32_t)rep.size();
+  std::vector<int32_t> lseg(nlist + 1, 0);
+  std::vector<int4> segs;
+  int max_segs = 0;
+  for (int l = 0; l < nlist; ++l) {
+    lseg[l] = (int32_t)segs.size();
+    for (int32_t r = rstart[l]; r < rstart[l + 1];) {
+      int32_t e = r;
+      while (e < rstart[l + 1] && rep[e].y == rep[r].y) ++e;
+      segs.push_back(make_int4(rep[r].y, r, e, 0));
+      r = e;
+    }
+    max_segs = std::max(max_segs, (int)(segs.size() - lseg[l]));
+  }
+  lseg[nlist] = (int32_t)segs.size();
 
   const int row_bytes = (M + 3) / 4 * 4;
   const int es = elem_size(dtype);
@@ -509,6 +542,11 @@ extern "C" ann_status ann_load_index(const char* path, int device, ann_index** o
   d.rep = prep;
   if ((s = dev_upload(ix.get(), asg_rows.data(), asg_rows.size(), &d.assign_rows)) != ANN_OK)
     return s;
+  const int4* pseg = nullptr;
+  if ((s = dev_upload(ix.get(), segs.data(), segs.size(), &pseg)) != ANN_OK) return s;
+  d.segs = pseg;
+  if ((s = dev_upload(ix.get(), lseg.data(), lseg.size(), &d.lseg)) != ANN_OK) return s;
+  d.max_segs = max_segs;
   // Integer-grid indexes probe on the int8 matrix cores: shifted, padded centroids.
   d.dim_pad = (dim + 63) / 64 * 64;
   d.shift8 = dtype == U8 ? 128 : 0;

@@ -41,6 +41,11 @@ struct DevIndex {
   const int32_t* cnorm8;      // [nlist] sum of squares of the shifted centroid
   int dim_pad;                // dim rounded up to 64
   int shift8;                 // 128 for uint8, 0 for int8
+  // replica entries of each list grouped by their vector's first list: group s
+  // of list l (s in [lseg[l], lseg[l+1])) is {first list, rep begin, rep end, 0}
+  const int4* segs;
+  const int32_t* lseg;        // [nlist + 1]
+  int max_segs;               // most groups of one list
 };
 
 // Per-call working buffers (one block of the memory pool).
@@ -82,6 +87,9 @@ hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, 
                         float* out_dists, hipStream_t st);
 hipError_t launch_rerank_only(const DevIndex& ix, const float* q, const int32_t* cand, int qc,
                               int n, int k, int64_t* out_ids, float* out_dists, hipStream_t st);
+
+// Records the thread's last error message (ann_last_error) and returns s.
+int set_error(int s, const char* fmt, ...);
 
 // Sizes of the dynamic LDS areas (bytes) for the scan kernel.
 size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n);

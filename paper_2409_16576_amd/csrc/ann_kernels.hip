@@ -3,10 +3,11 @@
 //   k_probe_dist   step 2: squared distances of each query to every list centroid
 //   k_probe_select step 2: the nprobe nearest lists, ascending by (distance, list)
 //   k_lut          step 1: per-query distance table, entry = ||q_m - c_{m,j}||^2 (Sec. 2.2)
-//   k_plan         splits each query's gathered entries into work items
-//   k_scan         steps 3, 5, 6, 7 fused: walk the probed lists, drop replica
-//                  entries owned by an earlier probed list (dedup), Eq. 1 by
-//                  table lookups from LDS, keep the n best (distance, id) keys
+//   k_scan         steps 1, 3, 5, 6, 7 fused: build the query's table in LDS,
+//                  walk the probed lists, drop replica entries owned by an
+//                  earlier probed list (dedup), Eq. 1 by table lookups, keep
+//                  the n best (distance, id) keys; splits long queries into
+//                  work items
 //   k_merge        step 7 across a query's work items, then step 8: exact
 //                  squared L2 of the n survivors, top-k
 //
@@ -455,48 +456,37 @@ __global__ __launch_bounds__(kBlock) void k_lut(DevIndex ix, const float* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Work planning: entries per query and number of work items.
-
-__global__ void k_plan(DevIndex ix, const int32_t* __restrict__ lists,
-                       const int32_t* __restrict__ np_eff, int np_max, int qc, int tile, int smax,
-                       int64_t* __restrict__ eq, int32_t* __restrict__ sq) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= qc) return;
-  int64_t e = 0;
-  const int np = np_eff[q];
-  for (int p = 0; p < np; ++p) {
-    const int l = lists[(size_t)q * np_max + p];
-    e += (int64_t)(ix.pstart[l + 1] - ix.pstart[l]) + (ix.rstart[l + 1] - ix.rstart[l]);
-  }
-  eq[q] = e;
-  const int64_t s = (e + tile - 1) / tile;
-  sq[q] = (int)max((int64_t)1, min((int64_t)smax, s));
-}
-
-// ---------------------------------------------------------------------------
 // Steps 3, 5, 6, 7: the fused scan.
 
+// A query's gathered entries are enumerated as "runs": per probed list, its
+// first-list rows (one contiguous row range) and its replica entries.  With
+// segmented replicas, a list's replica entries are grouped by their vector's
+// first list and only groups whose first list is NOT probed become runs (the
+// others are all duplicates of entries scanned from that first list).
 struct ScanLayout {
-  size_t lut, bits, list, pst, pcnt, rst, pre, buf, tmp, sel, misc, total;
+  size_t lut, bits, list, rstart, pre, buf, tmp, sel, misc, total;
 };
 
-__host__ __device__ inline ScanLayout scan_layout(int M, int nlist, int R, int np_max, int n,
-                                                  int cap) {
+// Most runs a query can have: per probed list, one row run plus one run per
+// replica group (segmented) or one replica run (not segmented).
+__host__ __device__ inline int scan_max_runs(int np_max, int max_segs, bool segmented) {
+  return np_max * (1 + (segmented ? max_segs : 1));
+}
+
+__host__ __device__ inline ScanLayout scan_layout(int M, int nlist, int R, int np_max,
+                                                  int max_runs, int cap) {
   ScanLayout L;
   size_t o = 0;
   L.lut = o; o += (size_t)M * kKsub * 4; o = align_up(o, 16);
   L.bits = o; o += (R > 1 ? (size_t)((nlist + 31) / 32) * 4 : 0); o = align_up(o, 16);
-  L.list = o; o += (size_t)np_max * 4;
-  L.pst = o; o += (size_t)np_max * 4;
-  L.pcnt = o; o += (size_t)np_max * 4;
-  L.rst = o; o += (size_t)np_max * 4; o = align_up(o, 16);
-  L.pre = o; o += (size_t)(np_max + 1) * 8; o = align_up(o, 16);
+  L.list = o; o += (size_t)np_max * 4; o = align_up(o, 16);
+  L.rstart = o; o += (size_t)max_runs * 4; o = align_up(o, 16);
+  L.pre = o; o += (size_t)(max_runs + 1) * 4; o = align_up(o, 16);
   L.buf = o; o += (size_t)cap * 8; o = align_up(o, 16);
-  L.tmp = o; o += (size_t)(kScanBlock / 64) * 4; o = align_up(o, 16);  // per-wave sums
+  L.tmp = o; o += (size_t)(kScanBlock / 64 + 1) * 4; o = align_up(o, 16);  // per-wave sums + total
   L.sel = o; o += sizeof(SelScratch); o = align_up(o, 16);
   L.misc = o; o += 32;
   L.total = align_up(o, 16);
-  (void)n;
   return L;
 }
 
@@ -607,11 +597,13 @@ __device__ void scan_compact(uint64_t* s_buf, int* s_wsum, SelScratch* ss, ScanM
 // kScanBlock), resolves them to code rows, issues all row loads, then scores
 // them; keys below the current threshold go to the LDS buffer, which is cut
 // back to the n best whenever it holds more than n.
+constexpr uint32_t kRunReplica = 0x80000000u;  // run start flag: replica-entry run
+
 template <int W, bool TRACE>
 __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_scan(
     DevIndex ix, const int32_t* __restrict__ lists, const int32_t* __restrict__ np_eff, int np_max,
     int qc, const float* __restrict__ Q, const float* __restrict__ lut,
-    const int32_t* __restrict__ sq, int smax, int n, int cap,
+    int32_t* __restrict__ sq, int smax, int tile, int segmented, int max_runs, int n, int cap,
     uint64_t* __restrict__ pkeys, int32_t* __restrict__ pcount, int32_t* __restrict__ pscan,
     int64_t t_capacity, int32_t* __restrict__ t_ids, float* __restrict__ t_adc,
     unsigned long long* __restrict__ t_count) {
@@ -622,24 +614,98 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   const int q = (slot / smax) * 8 + xcd;
   const int j = slot % smax;
   if (q >= qc) return;
-  const int S = sq[q];
-  if (j >= S) return;
   const int tid = threadIdx.x;
   const int M = ix.M;
 
   extern __shared__ __align__(16) unsigned char smem[];
-  const ScanLayout L = scan_layout(M, ix.nlist, ix.R, np_max, n, cap);
+  const ScanLayout L = scan_layout(M, ix.nlist, ix.R, np_max, max_runs, cap);
   float* s_lut = reinterpret_cast<float*>(smem + L.lut);
   uint32_t* s_bits = reinterpret_cast<uint32_t*>(smem + L.bits);
   int32_t* s_list = reinterpret_cast<int32_t*>(smem + L.list);
-  int32_t* s_pst = reinterpret_cast<int32_t*>(smem + L.pst);
-  int32_t* s_pcnt = reinterpret_cast<int32_t*>(smem + L.pcnt);
-  int32_t* s_rst = reinterpret_cast<int32_t*>(smem + L.rst);
-  int64_t* s_pre = reinterpret_cast<int64_t*>(smem + L.pre);
+  uint32_t* s_rstart = reinterpret_cast<uint32_t*>(smem + L.rstart);
+  int32_t* s_pre = reinterpret_cast<int32_t*>(smem + L.pre);
   uint64_t* s_buf = reinterpret_cast<uint64_t*>(smem + L.buf);
   int* s_wsum = reinterpret_cast<int*>(smem + L.tmp);
   SelScratch* ss = reinterpret_cast<SelScratch*>(smem + L.sel);
   ScanMisc* mc = reinterpret_cast<ScanMisc*>(smem + L.misc);
+
+  // Probed lists and the probe bitmap.
+  const int nwords = (ix.nlist + 31) / 32;
+  const bool use_bits = ix.R > 1;
+  if (use_bits)
+    for (int i = tid; i < nwords; i += kScanBlock) s_bits[i] = 0u;
+  const int np = np_eff[q];
+  for (int p = tid; p < np; p += kScanBlock) s_list[p] = lists[(size_t)q * np_max + p];
+  if (tid == 0) {
+    mc->thr = ~0ull;
+    mc->count = 0;
+    mc->scanned = 0;
+  }
+  __syncthreads();
+  if (use_bits)
+    for (int p = tid; p < np; p += kScanBlock) {
+      const int l = s_list[p];
+      atomicOr(&s_bits[l >> 5], 1u << (l & 31));
+    }
+  __syncthreads();
+
+  // Runs of every probed list (slot order), then their entry prefix sums.
+  int nruns = 0;
+  for (int p0 = 0; p0 < np; p0 += kScanBlock) {  // uniform trip count
+    const int p = p0 + tid;
+    int cnt = 0, l = 0;
+    if (p < np) {
+      l = s_list[p];
+      cnt = 1;
+      if (segmented) {
+        for (int s = ix.lseg[l]; s < ix.lseg[l + 1]; ++s) cnt += testbit(s_bits, ix.segs[s].x) ? 0 : 1;
+      } else {
+        cnt += ix.rstart[l + 1] > ix.rstart[l] ? 1 : 0;
+      }
+    }
+    const int off = nruns + block_excl_scan(cnt, s_wsum);
+    if (p < np) {
+      s_rstart[off] = (uint32_t)ix.pstart[l];
+      s_pre[off] = ix.pstart[l + 1] - ix.pstart[l];  // entry count, turned into offsets below
+      int r = off + 1;
+      if (segmented) {
+        for (int s = ix.lseg[l]; s < ix.lseg[l + 1]; ++s) {
+          const int4 g = ix.segs[s];
+          if (!testbit(s_bits, g.x)) {
+            s_rstart[r] = (uint32_t)g.y | kRunReplica;
+            s_pre[r] = g.z - g.y;
+            ++r;
+          }
+        }
+      } else if (cnt > 1) {
+        s_rstart[r] = (uint32_t)ix.rstart[l] | kRunReplica;
+        s_pre[r] = ix.rstart[l + 1] - ix.rstart[l];
+      }
+    }
+    if (tid == kScanBlock - 1) s_wsum[kScanBlock / 64] = off + cnt;  // running total
+    __syncthreads();
+    nruns = s_wsum[kScanBlock / 64];
+    __syncthreads();
+  }
+  // entry counts -> exclusive offsets (runs are at most a few thousand)
+  int total = 0;
+  for (int r0 = 0; r0 < nruns; r0 += kScanBlock) {
+    const int r = r0 + tid;
+    const int c = r < nruns ? s_pre[r] : 0;
+    const int off = total + block_excl_scan(c, s_wsum);
+    if (tid == kScanBlock - 1) s_wsum[kScanBlock / 64] = off + c;
+    __syncthreads();
+    if (r < nruns) s_pre[r] = off;
+    total = s_wsum[kScanBlock / 64];
+    __syncthreads();
+  }
+  if (tid == 0) s_pre[nruns] = total;
+
+  // Work items of this query: ceil(E / tile), at most smax.
+  const int E = total;
+  const int S = (int)max(1, min(smax, (E + tile - 1) / tile));
+  if (j == 0 && tid == 0) sq[q] = S;
+  if (j >= S) return;
 
   // Distance table of this query into LDS: computed here (step 1 fused into
   // the scan) unless the caller passed one in.
@@ -651,47 +717,15 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     const float* qrow = Q + (size_t)q * ix.dim;
     for (int i = tid; i < M * kKsub; i += kScanBlock) s_lut[i] = lut_entry(ix, qrow, i >> 8, i & 255);
   }
-  const int nwords = (ix.nlist + 31) / 32;
-  if (ix.R > 1)
-    for (int i = tid; i < nwords; i += kScanBlock) s_bits[i] = 0u;
-  const int np = np_eff[q];
-  for (int p = tid; p < np; p += kScanBlock) {
-    const int l = lists[(size_t)q * np_max + p];
-    const int a = ix.pstart[l];
-    s_list[p] = l;
-    s_pst[p] = a;
-    s_pcnt[p] = ix.pstart[l + 1] - a;
-    s_rst[p] = ix.rstart[l];
-  }
-  if (tid == 0) {
-    mc->thr = ~0ull;
-    mc->count = 0;
-    mc->scanned = 0;
-  }
-  __syncthreads();
-  if (ix.R > 1)
-    for (int p = tid; p < np; p += kScanBlock) {
-      const int l = s_list[p];
-      atomicOr(&s_bits[l >> 5], 1u << (l & 31));
-    }
-  if (tid == 0) {
-    int64_t acc = 0;
-    for (int p = 0; p < np; ++p) {
-      s_pre[p] = acc;
-      acc += (int64_t)s_pcnt[p] + (ix.rstart[s_list[p] + 1] - s_rst[p]);
-    }
-    s_pre[np] = acc;
-  }
   __syncthreads();
 
-  const int64_t E = s_pre[np];
-  const int64_t e0 = E * j / S, e1 = E * (j + 1) / S;
+  const int e0 = (int)((int64_t)E * j / S), e1 = (int)((int64_t)E * (j + 1) / S);
   const int lane = tid & 63;
   const uint64_t lanemask = (1ull << lane) - 1ull;
   int scanned = 0;
-  int cur = 0;  // list slot of this thread's current entry (entries only increase)
+  int cur = 0;  // run of this thread's current entry (entries only increase)
 
-  for (int64_t base = e0; base < e1; base += (int64_t)kScanBlock * kScanRT) {
+  for (int base = e0; base < e1; base += kScanBlock * kScanRT) {
     const uint64_t thr = mc->thr;
     const uint32_t thr_hi = (uint32_t)(thr >> 32);
     int rows[kScanRT];
@@ -699,17 +733,18 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     // resolve entries -> rows; replica entries owned by an earlier probed list are dropped
 #pragma unroll
     for (int u = 0; u < kScanRT; ++u) {
-      const int64_t e = base + (int64_t)u * kScanBlock + tid;
+      const int e = base + u * kScanBlock + tid;
       keep[u] = false;
       rows[u] = 0;
       if (e < e1) {
-        while (s_pre[cur + 1] <= e) ++cur;  // s_pre[np] = E > e bounds the walk
-        const int64_t o = e - s_pre[cur];
-        if (o < s_pcnt[cur]) {
-          rows[u] = s_pst[cur] + (int)o;
+        while (s_pre[cur + 1] <= e) ++cur;  // s_pre[nruns] = E > e bounds the walk
+        const int o = e - s_pre[cur];
+        const uint32_t rs = s_rstart[cur];
+        if (!(rs & kRunReplica)) {
+          rows[u] = (int)rs + o;
           keep[u] = true;
         } else {
-          const int2 r = ix.rep[s_rst[cur] + (o - s_pcnt[cur])];
+          const int2 r = ix.rep[(int)(rs & ~kRunReplica) + o];
           const int row = (int)((uint32_t)r.x & kRowMask);
           const int rank = (int)((uint32_t)r.x >> kRankShift);
           bool k = !testbit(s_bits, r.y);
@@ -1046,13 +1081,26 @@ __global__ __launch_bounds__(kBlock) void k_rerank_only(DevIndex ix, const float
   rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k, out_dists + (size_t)q * k);
 }
 
+// Segmented replica runs when their LDS bound stays small.
+constexpr int kMaxSegRuns = 1024;
+
+inline bool scan_segmented(const DevIndex& ix, int np_max) {
+  return ix.segs != nullptr && scan_max_runs(np_max, ix.max_segs, true) <= kMaxSegRuns;
+}
+
+inline int scan_runs(const DevIndex& ix, int np_max) {
+  return scan_max_runs(np_max, ix.max_segs, scan_segmented(ix, np_max));
+}
+
 template <int W>
 hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t* np_eff,
-                         int np_max, int qc, const float* Q, const float* lut, const int32_t* sq,
-                         int smax, int n, int cap, uint64_t* pkeys, int32_t* pcount,
+                         int np_max, int qc, const float* Q, const float* lut, int32_t* sq,
+                         int smax, int tile, int n, int cap, uint64_t* pkeys, int32_t* pcount,
                          int32_t* pscan, bool trace, int64_t t_capacity, int32_t* t_ids,
                          float* t_adc, int64_t* t_count, hipStream_t st) {
-  const ScanLayout L = scan_layout(ix.M, ix.nlist, ix.R, np_max, n, cap);
+  const int seg = scan_segmented(ix, np_max) ? 1 : 0;
+  const int max_runs = scan_runs(ix, np_max);
+  const ScanLayout L = scan_layout(ix.M, ix.nlist, ix.R, np_max, max_runs, cap);
   const int qpad = (qc + 7) / 8 * 8;
   const dim3 grid((unsigned)((size_t)qpad * smax));
   if (trace) {
@@ -1060,21 +1108,21 @@ hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t
     if (L.total > 65536)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
     hipLaunchKernelGGL(kern, grid, dim3(kScanBlock), L.total, st, ix, lists, np_eff, np_max, qc,
-                       Q, lut, sq, smax, n, cap, pkeys, pcount, pscan, t_capacity, t_ids, t_adc,
-                       reinterpret_cast<unsigned long long*>(t_count));
+                       Q, lut, sq, smax, tile, seg, max_runs, n, cap, pkeys, pcount, pscan,
+                       t_capacity, t_ids, t_adc, reinterpret_cast<unsigned long long*>(t_count));
   } else {
     auto kern = k_scan<W, false>;
     if (L.total > 65536)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
     hipLaunchKernelGGL(kern, grid, dim3(kScanBlock), L.total, st, ix, lists, np_eff, np_max, qc,
-                       Q, lut, sq, smax, n, cap, pkeys, pcount, pscan, t_capacity, t_ids, t_adc,
-                       reinterpret_cast<unsigned long long*>(t_count));
+                       Q, lut, sq, smax, tile, seg, max_runs, n, cap, pkeys, pcount, pscan,
+                       t_capacity, t_ids, t_adc, reinterpret_cast<unsigned long long*>(t_count));
   }
   return hipGetLastError();
 }
 
 using ScanFn = hipError_t (*)(const DevIndex&, const int32_t*, const int32_t*, int, int,
-                              const float*, const float*, const int32_t*, int, int, int, uint64_t*,
+                              const float*, const float*, int32_t*, int, int, int, int, uint64_t*,
                               int32_t*, int32_t*, bool, int64_t, int32_t*, float*, int64_t*,
                               hipStream_t);
 
@@ -1097,7 +1145,8 @@ ScanFn scan_fn(int W) {
 int scan_smax(int n) { return std::max(1, std::min(16, 4096 / std::max(n, 1))); }
 
 size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n) {
-  return scan_layout(ix.M, ix.nlist, ix.R, np_max, n, n + kScanBlock * kScanRT).total;
+  return scan_layout(ix.M, ix.nlist, ix.R, np_max, scan_runs(ix, np_max),
+                     n + kScanBlock * kScanRT).total;
 }
 
 static bool exact64(const DevIndex& ix) { return !ix.int_grid; }
@@ -1136,11 +1185,9 @@ hipError_t launch_lut(const DevIndex& ix, const float* q, int qc, float* out_lut
 hipError_t launch_scan(const DevIndex& ix, const int32_t* lists, const int32_t* np_eff,
                        const float* q, const LaunchCfg& c, Work& w, hipStream_t st) {
   if (c.qc <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plan, dim3((c.qc + 255) / 256), dim3(256), 0, st, ix, lists, np_eff,
-                     c.np_max, c.qc, c.tile, c.smax, w.eq, w.sq);
   const int W = (ix.M + 3) / 4;
   const int cap = c.n + kScanBlock * kScanRT;
-  return scan_fn(W)(ix, lists, np_eff, c.np_max, c.qc, q, nullptr, w.sq, c.smax, c.n, cap,
+  return scan_fn(W)(ix, lists, np_eff, c.np_max, c.qc, q, nullptr, w.sq, c.smax, c.tile, c.n, cap,
                     w.pkeys, w.pcount, w.pscan, false, 0, nullptr, nullptr, nullptr, st);
 }
 
@@ -1151,11 +1198,9 @@ hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const flo
   hipLaunchKernelGGL(k_count_lists, dim3((qc + 255) / 256), dim3(256), 0, st, lists, qc, np_max,
                      ix.nlist, w.np_eff);
   const int smax = 16, tile = 4096;
-  hipLaunchKernelGGL(k_plan, dim3((qc + 255) / 256), dim3(256), 0, st, ix, lists, w.np_eff, np_max,
-                     qc, tile, smax, w.eq, w.sq);
   hipLaunchKernelGGL(k_zero_i64, dim3((qc + 255) / 256), dim3(256), 0, st, out_count, qc);
   const int W = (ix.M + 3) / 4;
-  return scan_fn(W)(ix, lists, w.np_eff, np_max, qc, nullptr, lut, w.sq, smax, 1, 1, nullptr,
+  return scan_fn(W)(ix, lists, w.np_eff, np_max, qc, nullptr, lut, w.sq, smax, tile, 1, 1, nullptr,
                     nullptr, nullptr, true, capacity, out_ids, out_adc, out_count, st);
 }
 

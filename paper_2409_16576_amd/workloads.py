@@ -137,8 +137,15 @@ def cache_dir() -> str:
     return d
 
 
+_INDEX_FIELDS = ("wid", "n", "dim", "kind", "n_centres", "centre_low", "centre_high", "sigma",
+                 "nlist", "M", "R", "eps", "unit_norm", "zipf_s", "sub_centres", "sub_sigma",
+                 "kmeans_iters")
+
+
 def index_path(w: Workload) -> str:
-    h = hashlib.sha1(repr(w).encode()).hexdigest()[:16]
+    """Cache path keyed by the fields that determine the index file's bytes."""
+    key = repr(tuple(getattr(w, f) for f in _INDEX_FIELDS))
+    h = hashlib.sha1(key.encode()).hexdigest()[:16]
     safe = "".join(ch if ch.isalnum() or ch in "_-" else "_" for ch in w.name)[:60]
     return os.path.join(cache_dir(), f"{safe}-{h}.fidx")
 

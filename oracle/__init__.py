@@ -60,12 +60,14 @@ def _load():
         lib = ctypes.CDLL(LIB)
         P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         lib.orc_probe.argtypes = [P, P, i64, P, i32, P, P, ctypes.c_int]
-        lib.orc_lut.argtypes = [P, P, i64, P, P]
+        lib.orc_lut.argtypes = [P, P, i64, P, P, ctypes.c_int]
+        lib.orc_round_half.argtypes = [P, i64, P]
         lib.orc_gather_dedup.argtypes = [P, P, i32, P, P]
         lib.orc_gather_dedup.restype = i64
         lib.orc_adc.argtypes = [P, P, P, P, i64, P, P]
         lib.orc_exact.argtypes = [P, P, P, i64, P]
-        lib.orc_search.argtypes = [P, P, i64, P, i32, i32, P, P, P, P, P, P, ctypes.c_int]
+        lib.orc_search.argtypes = [P, P, i64, P, i32, i32, P, P, P, P, P, P, ctypes.c_int,
+                                   ctypes.c_int]
         lib.orc_bruteforce.argtypes = [P, P, i64, i32, P, P, ctypes.c_int]
         _lib = lib
     return _lib
@@ -161,14 +163,23 @@ def probe(ix: Index, Q, nprobe, threads: int = 0):
     return lists, d
 
 
-def lut(ix: Index, Q):
-    """Step 1: float32 table [nq, M, ksub] and the float64 table it is rounded from."""
+def lut(ix: Index, Q, f16: bool = False):
+    """Step 1: float32 table [nq, M, ksub] and the float64 table it is rounded from
+    (f16: the float32 entries rounded on to binary16, returned widened)."""
     Q = _q(Q)
     nq = Q.shape[0]
     l32 = np.empty((nq, ix.M, ix.ksub), dtype=np.float32)
     l64 = np.empty((nq, ix.M, ix.ksub), dtype=np.float64)
-    _load().orc_lut(ctypes.byref(ix.cstruct()), _p(Q), nq, _p(l32), _p(l64))
+    _load().orc_lut(ctypes.byref(ix.cstruct()), _p(Q), nq, _p(l32), _p(l64), 1 if f16 else 0)
     return l32, l64
+
+
+def round_half(x):
+    """Nearest binary16 values (ties to even) of float32 values, as float32."""
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1)
+    out = np.empty_like(x)
+    _load().orc_round_half(_p(x), len(x), _p(out))
+    return out
 
 
 def gather_dedup(ix: Index, lists):
@@ -214,8 +225,9 @@ class SearchResult:
     nentries: np.ndarray
 
 
-def search(ix: Index, Q, nprobe, k: int, rerank_n: int, threads: int = 0) -> SearchResult:
-    """Steps 1-8 for a batch of queries."""
+def search(ix: Index, Q, nprobe, k: int, rerank_n: int, threads: int = 0,
+           lut_f16: bool = False) -> SearchResult:
+    """Steps 1-8 for a batch of queries (lut_f16: half-precision table variant)."""
     Q = _q(Q)
     nq = Q.shape[0]
     npr = _np(nprobe, nq)
@@ -226,7 +238,8 @@ def search(ix: Index, Q, nprobe, k: int, rerank_n: int, threads: int = 0) -> Sea
     nc = np.empty(nq, dtype=np.int64)
     ne = np.empty(nq, dtype=np.int64)
     _load().orc_search(ctypes.byref(ix.cstruct()), _p(Q), nq, _p(npr), k, rerank_n, _p(ids),
-                       _p(dists), _p(tids), _p(tadc), _p(nc), _p(ne), threads)
+                       _p(dists), _p(tids), _p(tadc), _p(nc), _p(ne), threads,
+                       1 if lut_f16 else 0)
     return SearchResult(ids, dists, tids, tadc, nc, ne)
 
 

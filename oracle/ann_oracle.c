@@ -162,8 +162,30 @@ static int probe_one(const orc_index* ix, const double* q, int np, int32_t* out_
   return np;
 }
 
-/* Step 1: distance table L[m][j] = sum_t (q[m*dsub+t] - CB[m][j][t])^2. */
-static void lut_one(const orc_index* ix, const double* q, float* lut32, double* lut64) {
+/* The binary16 value nearest to x, ties to the even significand, as a float
+ * (exact: every binary16 value is a float).  binary16 has 10 fraction bits,
+ * normal magnitudes in [2^-14, 65504] and subnormal spacing 2^-24; magnitudes
+ * from 65520 (half-way to the first power of two it cannot hold) overflow to
+ * infinity.  Computed from that definition in float64: the spacing of x's
+ * binade divides x exactly, nearbyint rounds half to even. */
+static float round_to_half(float x) {
+  if (isnan(x)) return x;
+  const double a = fabs((double)x);
+  if (a >= 65520.0) return copysignf(INFINITY, x);
+  double quantum = 0x1p-24;
+  if (a >= 0x1p-14) {
+    int e;
+    (void)frexp(a, &e); /* a = f 2^e with f in [0.5, 1): the binade starts at 2^(e-1) */
+    quantum = ldexp(1.0, e - 1 - 10);
+  }
+  const double r = nearbyint(a / quantum) * quantum;
+  return copysignf((float)r, x);
+}
+
+/* Step 1: distance table L[m][j] = sum_t (q[m*dsub+t] - CB[m][j][t])^2.
+ * With f16 the float32 entry is then rounded to binary16 (the half-precision
+ * table variant) and kept widened back to float32. */
+static void lut_one(const orc_index* ix, const double* q, float* lut32, double* lut64, int f16) {
   for (int m = 0; m < ix->m; ++m) {
     for (int j = 0; j < ix->ksub; ++j) {
       const float* c = ix->codebooks + ((int64_t)m * ix->ksub + j) * ix->dsub;
@@ -173,7 +195,7 @@ static void lut_one(const orc_index* ix, const double* q, float* lut32, double* 
         double sq = u * u;
         acc = acc + sq;
       }
-      lut32[m * ix->ksub + j] = (float)acc;
+      lut32[m * ix->ksub + j] = f16 ? round_to_half((float)acc) : (float)acc;
       if (lut64) lut64[m * ix->ksub + j] = acc;
     }
   }
@@ -236,15 +258,22 @@ void orc_probe(const orc_index* ix, const float* Q, int64_t nq, const int32_t* n
   }
 }
 
-/* Step 1 for a batch.  lut32: nq x M x ksub; lut64 optional (same shape). */
-void orc_lut(const orc_index* ix, const float* Q, int64_t nq, float* lut32, double* lut64) {
+/* Step 1 for a batch.  lut32: nq x M x ksub; lut64 optional (same shape);
+ * f16: round the float32 entries to binary16. */
+void orc_lut(const orc_index* ix, const float* Q, int64_t nq, float* lut32, double* lut64,
+             int f16) {
   double* q = (double*)malloc(sizeof(double) * ix->dim);
   int64_t per = (int64_t)ix->m * ix->ksub;
   for (int64_t i = 0; i < nq; ++i) {
     convert_query(ix, Q + i * ix->dim, q);
-    lut_one(ix, q, lut32 + i * per, lut64 ? lut64 + i * per : NULL);
+    lut_one(ix, q, lut32 + i * per, lut64 ? lut64 + i * per : NULL, f16);
   }
   free(q);
+}
+
+/* binary16 rounding of explicit values (exposed for its pins). */
+void orc_round_half(const float* x, int64_t n, float* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = round_to_half(x[i]);
 }
 
 /* Steps 3+5 for one probe list: writes the distinct IDs (ascending) into
@@ -287,10 +316,12 @@ void orc_exact(const orc_index* ix, const float* q32, const int32_t* ids, int64_
  *   topn_ids, topn_adc   optional nq x rerank_n: the step-7 selection, ascending
  *   ncand                optional nq: distinct candidates scored by Eq. 1
  *   nentries             optional nq: list entries gathered (with duplicates)
+ *   lut_f16              1: the half-precision table variant (entries rounded
+ *                        to binary16, summed in float32 as in Eq. 1)
  */
 void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* nprobe,
                 int32_t k, int32_t rerank_n, int64_t* ids, float* dists, int32_t* topn_ids,
-                float* topn_adc, int64_t* ncand, int64_t* nentries, int nthreads) {
+                float* topn_adc, int64_t* ncand, int64_t* nentries, int nthreads, int lut_f16) {
   int64_t maxg = ix->offsets[ix->nlist];
   if (maxg < 1) maxg = 1;
 #ifdef _OPENMP
@@ -311,7 +342,7 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
     for (int64_t i = 0; i < nq; ++i) {
       convert_query(ix, Q + i * ix->dim, q);
       int_query(ix, q, qi);
-      lut_one(ix, q, lut, NULL);                                   /* step 1 */
+      lut_one(ix, q, lut, NULL, lut_f16);                          /* step 1 */
       int np = probe_one(ix, q, nprobe[i], probe, NULL, scratch);  /* step 2 */
       int64_t nu = 0;
       int64_t g = gather_dedup(ix, probe, np, buf, &nu);           /* steps 3, 5 */

@@ -253,3 +253,64 @@ def test_recall_rises_to_one_with_rerank_n(tmp_path, orc):
     rec = [orc.recall_at_k(orc.search(ix, Q, 128, 10, n).ids, bi, 10) for n in (10, 50, 200, 20000)]
     assert all(a <= b + 1e-12 for a, b in zip(rec, rec[1:]))
     assert rec[-1] == 1.0
+
+
+def test_binary16_rounding_matches_numpy(orc):
+    """The half-precision table variant rounds each float32 entry to the
+    nearest binary16 value, ties to even; numpy's float16 conversion is an
+    independent implementation of the same IEEE rounding.  Covers exact
+    half-way points (where truncation or ties-away would differ), the
+    subnormal range, the largest finite value and overflow."""
+    rng = np.random.default_rng(3)
+    x = np.concatenate([
+        rng.uniform(0, 70000, 20000), 10.0 ** rng.uniform(-9, 6, 20000),
+        rng.uniform(-100, 100, 2000),
+        [0.0, -0.0, 65504.0, 65519.99, 65520.0, 65535.0, 1e30, 2.0 ** -24, 2.0 ** -25,
+         3 * 2.0 ** -26, 2.0 ** -14, 2.0 ** -14 - 2.0 ** -25],
+    ]).astype(np.float32)
+    h = np.arange(0, 0x7C00, dtype=np.uint16).view(np.float16).astype(np.float32)
+    mids = ((h[:-1].astype(np.float64) + h[1:]) / 2).astype(np.float32)  # exact in float32
+    x = np.concatenate([x, mids, h])
+    want = x.astype(np.float16).astype(np.float32)
+    got = orc.round_half(x)
+    assert np.array_equal(np.isinf(got), np.isinf(want))
+    fin = ~np.isinf(want)
+    assert np.array_equal(got[fin].view(np.uint32), want[fin].view(np.uint32))
+
+
+def test_half_table_variant(tmp_path, orc):
+    """f16 table = binary16 rounding of the float32 table (numpy float16);
+    where every entry is exactly representable (small integers) the f16 search
+    is the float32 search bit for bit; otherwise its top-n is the valid
+    selection under the rounded table."""
+    path, _ = fx.lossless_u8(tmp_path, "h16", n=400, dim=8)
+    ix = orc.read_index(path)
+    rng = np.random.default_rng(8)
+    Q = rng.integers(0, 40, size=(12, 8)).astype(np.float32)  # entries (q - c)^2 <= 2048 for c <= 85
+    X = ix.vectors.astype(np.int64)
+    l32, _ = orc.lut(ix, Q)
+    l16, _ = orc.lut(ix, Q, f16=True)
+    assert np.array_equal(l16, l32.astype(np.float16).astype(np.float32))
+    small = (l32 <= 2048).all(axis=(1, 2))
+    r32 = orc.search(ix, Q, 4, 5, 30)
+    r16 = orc.search(ix, Q, 4, 5, 30, lut_f16=True)
+    for i in range(len(Q)):
+        if small[i]:
+            assert r16.topn_ids[i].tolist() == r32.topn_ids[i].tolist()
+    X = fx.mixture(21, 4000, 32, "f32", n_centres=8, hi=1.0, sigma=0.05)
+    path, _ = fx.built(tmp_path, "h16f", X, "f32", nlist=16, M=8)
+    ix = orc.read_index(path)
+    Q = fx.mixture(22, 6, 32, "f32", n_centres=8, hi=1.0, sigma=0.05).astype(np.float32)
+    n = 50
+    r = orc.search(ix, Q, 4, 10, n, lut_f16=True)
+    lists, _ = orc.probe(ix, Q, 4)
+    l32, _ = orc.lut(ix, Q)
+    t16 = l32.astype(np.float16).astype(np.float32)
+    for i in range(len(Q)):
+        cand = np.unique(np.concatenate([ix.entries[ix.offsets[l]:ix.offsets[l + 1]] for l in lists[i]]))
+        adc = np.zeros(len(cand), np.float32)
+        for m in range(ix.M):  # float32 sum in subspace order, as Eq. 1's reading
+            adc = (adc + t16[i, m, ix.codes[cand, m]]).astype(np.float32)
+        want = cand[np.lexsort((cand, adc))][:n]
+        assert r.topn_ids[i].tolist() == want.tolist()
+        assert r.topn_adc[i].tolist() == np.sort(adc)[:n].tolist()

@@ -9,8 +9,12 @@ queries, nprobe 64, rerank_n 200, k 10.  A step is one pass of the whole path
 over all queries, with the index and the queries already in HBM.
 
 Forms timed:
-  plain    one ann_search call per batch of 256 queries
-  batched  one ann_search call over all queries
+  plain    one ann_search call per batch of 256 queries (default work split)
+  batched  the whole batch as one HIP-graph launch (ann_graph_launch) with the
+           work split the autotuner picked; its per-stage times come from an
+           event-bracketed eager run of the same search ("batched_eager")
+  served   Poisson arrivals of requests of U{1..256} queries into the
+           continuous-batching server at several offered loads, then saturation
 The headline value is the batched form's queries/s.
 
 Also reported: candidates/s, recall@10 against exact kNN of a query sample,
@@ -67,16 +71,109 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="ivf_u8_10m")
     ap.add_argument("--plain-batch", type=int, default=256)
-    ap.add_argument("--cpu-queries", type=int, default=1024)
+    ap.add_argument("--cpu-queries", type=int, default=10000)
     ap.add_argument("--recall-queries", type=int, default=500)
     ap.add_argument("--rerank-n", type=int, default=0,
                     help="top-n re-ranked (default: the workload's recall>=0.9 operating point)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
-    ap.add_argument("--forms", default="plain,batched")
+    ap.add_argument("--forms", default="plain,batched,served")
+    ap.add_argument("--served-rates", default="0.25,0.5,1,1.5,2,3",
+                    help="offered loads of the served form, million queries/s")
+    ap.add_argument("--served-seconds", type=float, default=1.5,
+                    help="arrival window per offered load")
+    ap.add_argument("--lut16", action="store_true",
+                    help="half-precision distance table (binary16 entries, float32 sums)")
     ap.add_argument("--build-only", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
     return ap.parse_args()
+
+
+def run_served(ann, g, Qh, npq, w, k, n, args):
+    """Served form: Poisson request arrivals (sizes U{1..256}) at several
+    offered loads into a continuous-batching server; per load the achieved
+    queries/s and the p50/p99 request latency, then a saturation run (every
+    request waiting at once).  The form's qps is the best achieved rate whose
+    load was sustained (achieved >= 95% of offered) or the saturation rate,
+    whichever is higher."""
+    import queue
+    import threading
+
+    import numpy as np
+
+    nq = Qh.shape[0]
+    fixed_np = isinstance(w.nprobe, int)
+    np_all = np.full(nq, int(w.nprobe), np.int32) if fixed_np else npq.astype(np.int32)
+    srv = ann.Server(g, hbm_budget_bytes=4 << 30, max_slots=4, max_batch=1024,
+                     max_nprobe=int(np_all.max()), max_k=k, max_rerank_n=n)
+    rng = np.random.default_rng(1_000_003 * 2 + 7)
+
+    def play(arrivals, sizes):
+        tickets = queue.Queue()
+        done = {"q": 0, "t_end": 0.0}
+
+        def collect():
+            while True:
+                t = tickets.get()
+                if t is None:
+                    break
+                srv.poll(t, wait=True)
+            done["t_end"] = time.perf_counter()
+
+        th = threading.Thread(target=collect)
+        th.start()
+        pos = 0
+        t0 = time.perf_counter()
+        for a, sz in zip(arrivals, sizes):
+            while True:
+                dt = t0 + a - time.perf_counter()
+                if dt <= 0:
+                    break
+                if dt > 3e-4:
+                    time.sleep(dt - 2e-4)
+            rows = (np.arange(pos, pos + sz) % nq)
+            pos += sz
+            tickets.put(srv.submit(Qh[rows], np_all[rows], k, n))
+        tickets.put(None)
+        th.join()
+        return done["t_end"] - t0, pos
+
+    # warm-up (kernels, pinned pages)
+    play(np.zeros(8), [256] * 8)
+    srv.stats(reset=True)
+    loads = []
+    for rate_m in [float(x) for x in args.served_rates.split(",") if x]:
+        lam = rate_m * 1e6
+        nreq = max(8, int(lam * args.served_seconds / 128.5))
+        sizes = rng.integers(1, 257, size=nreq)
+        gaps = rng.exponential(1.0, size=nreq) * (sizes.mean() / lam)
+        arrivals = np.cumsum(gaps) - gaps[0]
+        el, nqs = play(arrivals, sizes)
+        st = srv.stats(reset=True)
+        ach = nqs / el
+        loads.append({"offered_qps": lam, "achieved_qps": round(ach, 1),
+                      "p50_ms": round(st["latency_p50_ms"], 3),
+                      "p99_ms": round(st["latency_p99_ms"], 3),
+                      "requests": int(st["requests_done"]), "launches": int(st["launches"]),
+                      "mean_launch_queries": round(st["queries_done"] / max(1, st["launches"]), 1),
+                      "max_in_flight": int(st["max_in_flight"]),
+                      "sustained": bool(ach >= 0.95 * lam)})
+        log(f"served @ {rate_m:g}M q/s offered: {ach:.0f} q/s, p50 {st['latency_p50_ms']:.2f} ms, "
+            f"p99 {st['latency_p99_ms']:.2f} ms, {st['launches']} launches")
+    # saturation: all requests waiting at once
+    sizes = rng.integers(1, 257, size=max(8, int(3 * nq / 128.5)))
+    el, nqs = play(np.zeros(len(sizes)), sizes)
+    st = srv.stats(reset=True)
+    sat = {"achieved_qps": round(nqs / el, 1), "p50_ms": round(st["latency_p50_ms"], 3),
+           "p99_ms": round(st["latency_p99_ms"], 3), "launches": int(st["launches"]),
+           "mean_launch_queries": round(st["queries_done"] / max(1, st["launches"]), 1),
+           "max_in_flight": int(st["max_in_flight"]), "queries": int(nqs)}
+    log(f"served saturation: {nqs / el:.0f} q/s over {nqs} queries, {st['launches']} launches")
+    srv.stop()
+    best = max([x["achieved_qps"] for x in loads if x["sustained"]] + [sat["achieved_qps"]])
+    return {"qps": best, "ms_per_step": nq / best * 1e3, "loads": loads, "saturation": sat,
+            "max_slots": 4, "max_batch": 1024, "request_sizes": "U{1..256}",
+            "arrivals": "Poisson"}
 
 
 def main():
@@ -113,6 +210,8 @@ def main():
     t0 = time.time()
     g = ann.Index(path, 0)
     log(f"index loaded to HBM in {time.time() - t0:.1f}s, {g.desc['hbm_bytes'] / 2**30:.2f} GiB")
+    if args.lut16:
+        g.set_option(g.OPT_LUT_F16, 1)
     Qh = workloads.queries(w)
     nq = Qh.shape[0]
     Q = torch.from_numpy(Qh).to(dev)
@@ -148,13 +247,32 @@ def main():
             g.search(Q[b0:b1], npb, k, n)
 
     out = {}
+    graph = None
+    tuned = None
 
-    def step_batched():
+    def step_eager():
         out["res"] = g.search(Q, nprobe_arg, k, n)
 
-    forms = {"plain": step_plain, "batched": step_batched}
+    def step_graph():
+        out["res"] = graph.launch(st)
+
+    forms = {"plain": step_plain, "batched": step_graph, "batched_eager": step_eager}
+    names = args.forms.split(",")
+    if "batched" in names:
+        # the batched form: work split picked by the autotuner for this batch,
+        # then the whole search captured once into a HIP graph; its stage
+        # times (and the scan roofline) come from an eager, event-bracketed run
+        # of the same search right after
+        tuned = ann.autotune(g, Q, nprobe_arg, k, n, reps=2)
+        log(f"autotune: tile {tuned['tile']}, split {tuned['split']} ({tuned['tried']} tried, "
+            f"{tuned['ms']:.3f} ms)")
+        graph = ann.Graph(g, Q, nprobe_arg, k, n)
+        names.insert(names.index("batched") + 1, "batched_eager")
     results = {}
-    for name in args.forms.split(","):
+    for name in names:
+        if name == "served":
+            results[name] = run_served(ann, g, Qh, npq, w, k, n, args)
+            continue
         fn = forms[name]
         for _ in range(args.warmup):
             fn()
@@ -174,6 +292,8 @@ def main():
         ms = ev0.elapsed_time(ev1) / args.steps
         prof = g.get_profile(reset=True)
         g.set_profiling(False)
+        if name == "batched":  # graph launches carry no stage events
+            prof = {s_: {"ms": 0.0, "launches": 0} for s_ in prof}
         results[name] = {"ms_per_step": ms, "qps": nq / (ms / 1e3),
                          "candidates_per_s": cand_per_step / (ms / 1e3),
                          "wall_ms_per_step": wall * 1e3 / args.steps,
@@ -184,10 +304,11 @@ def main():
             f"{results[name]['candidates_per_s'] / 1e9:.2f} G cand/s, stages "
             + ", ".join(f"{s} {v['ms'] / args.steps:.3f}ms" for s, v in prof.items()))
 
-    head = "batched" if "batched" in results else list(results)[0]
+    head = "batched" if "batched" in results else [f for f in results if f != "served"][0]
     R = results[head]
-    scan_ms = R["stage_ms_per_step"]["scan"]
-    scan_launches = max(1, R["stage_launches_per_step"]["scan"])
+    RS = results["batched_eager"] if head == "batched" else R  # stage times (events)
+    scan_ms = RS["stage_ms_per_step"]["scan"]
+    scan_launches = max(1, RS["stage_launches_per_step"]["scan"])
     achieved = scan_alg_bytes / (scan_ms / 1e3) / 1e9
     tr = load_traffic(w.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -204,15 +325,20 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {**w.describe(), "rerank_n": n, "rerank_n_config": w.rerank_n,
-                   "data_dtype": w.kind, "form": head, "plain_batch": args.plain_batch},
+                   "data_dtype": w.kind, "form": head, "plain_batch": args.plain_batch,
+                   "lut": "f16" if args.lut16 else "f32"},
         "candidates_per_s": round(R["candidates_per_s"], 1),
         "candidates_per_query": round(cand_per_step / nq, 1),
         "forms": {k_: {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()}
                   for k_, r in results.items()},
         "roofline": roofline,
     }
+    if tuned:
+        line["config"]["tuned_split"] = {"tile": tuned["tile"], "split": tuned["split"]}
     if "plain" in results and "batched" in results:
         line["batched_over_plain"] = round(results["batched"]["qps"] / results["plain"]["qps"], 3)
+    if "plain" in results and "served" in results:
+        line["served_over_plain"] = round(results["served"]["qps"] / results["plain"]["qps"], 3)
 
     if not args.no_cpu:
         import oracle
@@ -223,7 +349,7 @@ def main():
         threads = os.cpu_count() or 1
         ns = min(args.cpu_queries, nq)
         t0 = time.perf_counter()
-        r = oracle.search(oix, Qh[:ns], npq[:ns], k, n, threads=threads)
+        r = oracle.search(oix, Qh[:ns], npq[:ns], k, n, threads=threads, lut_f16=args.lut16)
         cpu_s = time.perf_counter() - t0
         log(f"oracle: {ns} queries in {cpu_s:.2f}s on {threads} threads")
         ids_gpu, d_gpu = out["res"] if "res" in out else g.search(Q, nprobe_arg, k, n)

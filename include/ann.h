@@ -178,16 +178,135 @@ ann_status ann_set_profiling(ann_index* ix, int enable);
 ann_status ann_get_profile(ann_index* ix, ann_profile* out, int reset);
 
 /*
+ * Options of an index.
  * Tuning knobs of the scan work split (no effect on any result: the top-n of
- * a query is the same however its gathered entries are split into items).
+ * a query is the same however its gathered entries are split into items):
  *   ANN_OPT_SCAN_TILE   target entries per work item, in [64, 2^30] (default 65536)
  *   ANN_OPT_SCAN_SPLIT  most work items per query, in [1, 16] (default 16;
  *                       the kernel also caps it at max(1, 4096 / rerank_n))
+ * Numeric variant (changes results, deterministically):
+ *   ANN_OPT_LUT_F16     1: the distance table of Eq. 1 is held in binary16 --
+ *                       each float32 entry rounded to the nearest binary16,
+ *                       ties to even, widened exactly before the float32 sum
+ *                       over subspaces; 0 (default): float32 entries.  Meant
+ *                       for data whose table entries stay below 65504 (larger
+ *                       entries become +inf).  ann_search / ann_search_topn
+ *                       and the forms built on them; ann_lut and
+ *                       ann_scan_trace stay float32.
  * Errors: ANN_EINVAL for an unknown option or an out-of-range value.
  */
-enum { ANN_OPT_SCAN_TILE = 1, ANN_OPT_SCAN_SPLIT = 2 };
+enum { ANN_OPT_SCAN_TILE = 1, ANN_OPT_SCAN_SPLIT = 2, ANN_OPT_LUT_F16 = 3 };
 ann_status ann_set_option(ann_index* ix, int option, int64_t value);
 ann_status ann_get_option(ann_index* ix, int option, int64_t* value);
+
+/*
+ * Batched form: the search of one query batch captured into a HIP graph.
+ * ann_graph_create records ann_search(ix, d_queries, nq, d_nprobe, nprobe_max,
+ * k, rerank_n, d_out_ids, d_out_dists) -- probe, scan and merge of every
+ * chunk -- into a graph with its own working memory (allocated here, held
+ * until ann_graph_free).  Each ann_graph_launch replays the whole search with
+ * one launch call and allocates nothing; it reads whatever d_queries and
+ * d_nprobe hold when it runs (same shapes), and writes the same results
+ * ann_search would.  Launches of one graph are ordered after each other even
+ * on different streams (they share its working memory).  The scan's work
+ * split (ann_set_option) is fixed at capture time.  The buffers must stay
+ * valid while the graph exists.  Errors: as ann_search (nq >= 1 here).
+ */
+typedef struct ann_graph ann_graph; /* opaque */
+ann_status ann_graph_create(ann_index* ix, const float* d_queries, int64_t nq,
+                            const int32_t* d_nprobe, int32_t nprobe_max, int32_t k,
+                            int32_t rerank_n, int64_t* d_out_ids, float* d_out_dists,
+                            ann_graph** out);
+ann_status ann_graph_launch(ann_graph* g, void* stream);
+void ann_graph_free(ann_graph* g); /* waits for its last launch; NULL is a no-op */
+
+/*
+ * Autotuner of the scan's work split for a batch: runs ann_search on the
+ * given queries for each candidate (tile in {4096 .. 131072, 2^30}, split in
+ * {1, 2, 4, 8, 16}), `reps` timed runs each after one warm-up, keeps the
+ * split with the lowest median time and sets it on the index
+ * (ANN_OPT_SCAN_TILE / ANN_OPT_SCAN_SPLIT).  The split never changes results.
+ * Synchronous; allocates temporary outputs.  Errors: as ann_search, ANN_EINVAL
+ * for reps outside [1, 100].
+ */
+typedef struct {
+  int64_t tile;   /* chosen ANN_OPT_SCAN_TILE */
+  int32_t split;  /* chosen ANN_OPT_SCAN_SPLIT */
+  int32_t tried;  /* candidates timed */
+  double ms;      /* median search time of the chosen split */
+} ann_tune_result;
+ann_status ann_autotune(ann_index* ix, const float* d_queries, int64_t nq, const int32_t* d_nprobe,
+                        int32_t nprobe_max, int32_t k, int32_t rerank_n, int32_t reps,
+                        ann_tune_result* out);
+
+/*
+ * Served form: continuous batching of small search requests on one GPU.
+ *
+ * The paper serves concurrent queries with one CPU thread per query and gives
+ * each in-flight query its own block of working memory (Sec. 5).  Here a
+ * server owns an HBM arena of hbm_budget_bytes and max_slots streams.  Its
+ * scheduler thread coalesces consecutive waiting requests that share
+ * (k, rerank_n) into one launch of at most max_batch queries and starts it as
+ * soon as a stream is free and the launch's device footprint (queries,
+ * outputs, working buffers) fits in the arena's free bytes.  A finished launch
+ * frees its stream and bytes immediately, so requests that arrive while others
+ * run are admitted without waiting for a batch boundary, and launches on
+ * different streams overlap on the device.  No device memory is allocated
+ * while serving.  Every query is searched exactly as by ann_search with the
+ * same nprobe, k and rerank_n, so results do not depend on the mix.
+ */
+typedef struct ann_server ann_server; /* opaque */
+
+typedef struct {
+  int64_t hbm_budget_bytes; /* device bytes for in-flight launches (0: 2 GiB); must hold
+                               one launch of max_batch queries at the max_* limits */
+  int32_t max_slots;        /* launches in flight at once, 1..16 (0: 4) */
+  int32_t max_batch;        /* most queries per launch and per request (0: 1024) */
+  int32_t max_nprobe;       /* largest nprobe_max accepted, 1..4096 (0: 256) */
+  int32_t max_k;            /* largest k accepted (0: 64) */
+  int32_t max_rerank_n;     /* largest rerank_n accepted (0: max_rerank_n of the index) */
+} ann_server_cfg;
+
+typedef struct {
+  int64_t requests_done;    /* requests completed (since start or the last reset) */
+  int64_t queries_done;
+  int64_t launches;         /* device launches started */
+  int64_t max_in_flight;    /* most launches on the device at once */
+  int64_t peak_bytes;       /* most arena bytes held by in-flight launches */
+  int64_t budget_bytes;
+  double latency_p50_ms;    /* submit -> results available, per request */
+  double latency_p99_ms;
+  double latency_max_ms;
+} ann_server_stats;
+
+/* Start a server on a loaded index (cfg NULL: all defaults).  The index must
+ * outlive the server.  Errors: ANN_EINVAL (limits, budget too small),
+ * ANN_ENOMEM, ANN_EDEVICE. */
+ann_status ann_server_start(ann_index* ix, const ann_server_cfg* cfg, ann_server** out);
+
+/* Queue a request of nq (1..max_batch) float32 queries in HOST memory
+ * (copied; the caller may reuse the buffer at once).  nprobe: host int32 [nq]
+ * or NULL (every query probes nprobe_max lists); same limits as ann_search.
+ * *ticket identifies the request for ann_server_poll.  Thread-safe.
+ * Errors: ANN_EINVAL (limits, server stopping), or the status of an earlier
+ * failed launch. */
+ann_status ann_server_submit(ann_server* s, const float* queries, int32_t nq,
+                             const int32_t* nprobe, int32_t nprobe_max, int32_t k,
+                             int32_t rerank_n, uint64_t* ticket);
+
+/* *done = 1 once the request has finished; then its results are copied to
+ * ids (host int64 [nq, k]) and dists (host float32 [nq, k]) when non-NULL and
+ * the ticket is forgotten (a later poll of it fails with ANN_EINVAL).  wait != 0
+ * blocks until the request has finished.  Thread-safe. */
+ann_status ann_server_poll(ann_server* s, uint64_t ticket, int64_t* ids, float* dists,
+                           int32_t* done, int32_t wait);
+
+/* Counters and latency percentiles; reset != 0 clears them afterwards. */
+ann_status ann_server_get_stats(ann_server* s, ann_server_stats* out, int reset);
+
+/* Finish every submitted request, stop the scheduler and free the server's
+ * resources.  No other call on `s` may run concurrently or follow. */
+ann_status ann_server_stop(ann_server* s);
 
 /*
  * Differentiable PQ distance with fixed codes (codebook fine-tuning).

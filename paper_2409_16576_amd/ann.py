@@ -43,6 +43,28 @@ class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int64), ("split", ctypes.c_int32), ("tried", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("max_nprobe", ctypes.c_int32),
+                ("max_k", ctypes.c_int32), ("max_rerank_n", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("requests_done", ctypes.c_int64), ("queries_done", ctypes.c_int64),
+                ("launches", ctypes.c_int64), ("max_in_flight", ctypes.c_int64),
+                ("peak_bytes", ctypes.c_int64), ("budget_bytes", ctypes.c_int64),
+                ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+                ("latency_max_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 STAGES = ("probe", "lut", "scan", "merge_rerank")
 
 _lib = None
@@ -78,9 +100,22 @@ def lib():
         L.ann_adc_backward_workspace.restype = ctypes.c_size_t
         L.ann_adc_backward.argtypes = [P, i64, P, i32, i32, P, i64, P, P, P, P, ctypes.c_size_t, P]
         L.ann_adc_backward.restype = ctypes.c_int
+        L.ann_graph_create.argtypes = [P, P, i64, P, i32, i32, i32, P, P, ctypes.POINTER(P)]
+        L.ann_graph_launch.argtypes = [P, P]
+        L.ann_graph_free.argtypes = [P]
+        L.ann_graph_free.restype = None
+        L.ann_autotune.argtypes = [P, P, i64, P, i32, i32, i32, i32, ctypes.POINTER(TuneResult)]
+        L.ann_server_start.argtypes = [P, ctypes.POINTER(ServerCfg), ctypes.POINTER(P)]
+        L.ann_server_submit.argtypes = [P, P, i32, P, i32, i32, i32,
+                                        ctypes.POINTER(ctypes.c_uint64)]
+        L.ann_server_poll.argtypes = [P, ctypes.c_uint64, P, P, ctypes.POINTER(i32), i32]
+        L.ann_server_get_stats.argtypes = [P, ctypes.POINTER(ServerStats), ctypes.c_int]
+        L.ann_server_stop.argtypes = [P]
         for f in ("ann_load_index", "ann_index_info", "ann_search", "ann_search_topn", "ann_probe",
                   "ann_lut", "ann_scan_trace", "ann_rerank", "ann_set_profiling",
-                  "ann_get_profile", "ann_set_option", "ann_get_option"):
+                  "ann_get_profile", "ann_set_option", "ann_get_option", "ann_server_start",
+                  "ann_server_submit", "ann_server_poll", "ann_server_get_stats",
+                  "ann_server_stop", "ann_graph_create", "ann_graph_launch", "ann_autotune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -215,6 +250,7 @@ class Index:
     # -- tuning --------------------------------------------------------------------
     OPT_SCAN_TILE = 1
     OPT_SCAN_SPLIT = 2
+    OPT_LUT_F16 = 3
 
     def set_option(self, option: int, value: int):
         _check(lib().ann_set_option(self._h, int(option), int(value)))
@@ -223,6 +259,124 @@ class Index:
         v = ctypes.c_int64()
         _check(lib().ann_get_option(self._h, int(option), ctypes.byref(v)))
         return v.value
+
+
+# -- batched form (ann_graph_*, ann_autotune) -------------------------------------------
+
+def _nprobe_args(index, Q, nprobe):
+    if isinstance(nprobe, int):
+        return None, int(nprobe)
+    t = nprobe.to(device=index.device, dtype=torch.int32).contiguous()
+    return t, int(t.max().item()) if t.numel() else 1
+
+
+class Graph:
+    """A batch search captured into a HIP graph (see ann_graph_create).  Holds the
+    query/nprobe/output tensors; launch() replays the search on them."""
+
+    def __init__(self, index, Q, nprobe, k: int, rerank_n: int):
+        self.index = index
+        self.Q = Q.contiguous()
+        self.np_t, self.np_max = _nprobe_args(index, Q, nprobe)
+        nq = self.Q.shape[0]
+        self.ids = torch.empty((nq, k), dtype=torch.int64, device=index.device)
+        self.dists = torch.empty((nq, k), dtype=torch.float32, device=index.device)
+        h = ctypes.c_void_p()
+        _check(lib().ann_graph_create(index._h, _ptr(self.Q), nq, _ptr(self.np_t), self.np_max,
+                                      int(k), int(rerank_n), _ptr(self.ids), _ptr(self.dists),
+                                      ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().ann_graph_launch(self._h, _stream(self.index.device, stream)))
+        return self.ids, self.dists
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ann_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(index, Q, nprobe, k: int, rerank_n: int, reps: int = 3) -> dict:
+    """Pick and set the scan work split for this batch (ann_autotune)."""
+    Q = Q.contiguous()
+    np_t, np_max = _nprobe_args(index, Q, nprobe)
+    r = TuneResult()
+    _check(lib().ann_autotune(index._h, _ptr(Q), Q.shape[0], _ptr(np_t), np_max, int(k),
+                              int(rerank_n), int(reps), ctypes.byref(r)))
+    return {"tile": r.tile, "split": r.split, "tried": r.tried, "ms": r.ms}
+
+
+# -- served form (ann_server_*) ---------------------------------------------------------
+
+class Server:
+    """Continuous-batching server over a loaded Index (see ann_server_start).
+    Requests are numpy arrays in host memory; results come back as numpy."""
+
+    def __init__(self, index: Index, hbm_budget_bytes: int = 0, max_slots: int = 0,
+                 max_batch: int = 0, max_nprobe: int = 0, max_k: int = 0, max_rerank_n: int = 0):
+        import numpy as np  # noqa: F401  (results are numpy arrays)
+        cfg = ServerCfg(int(hbm_budget_bytes), int(max_slots), int(max_batch), int(max_nprobe),
+                        int(max_k), int(max_rerank_n))
+        h = ctypes.c_void_p()
+        _check(lib().ann_server_start(index._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.index = index
+        self._k = {}
+
+    def submit(self, queries, nprobe, k: int, rerank_n: int) -> int:
+        """queries: float32 [nq, dim] numpy; nprobe: int or int32 [nq] numpy."""
+        import numpy as np
+        q = np.ascontiguousarray(queries, dtype=np.float32)
+        if isinstance(nprobe, (int, np.integer)):
+            npp, npmax = None, int(nprobe)
+        else:
+            npp = np.ascontiguousarray(nprobe, dtype=np.int32)
+            npmax = int(npp.max()) if npp.size else 1
+        t = ctypes.c_uint64()
+        _check(lib().ann_server_submit(self._h, q.ctypes.data_as(ctypes.c_void_p), q.shape[0],
+                                       None if npp is None else npp.ctypes.data_as(ctypes.c_void_p),
+                                       npmax, int(k), int(rerank_n), ctypes.byref(t)))
+        self._k[t.value] = (q.shape[0], int(k))
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True):
+        """(ids int64 [nq, k], dists float32 [nq, k]) once done, else None."""
+        import numpy as np
+        nq, k = self._k[ticket]
+        ids = np.empty((nq, k), dtype=np.int64)
+        d = np.empty((nq, k), dtype=np.float32)
+        done = ctypes.c_int32()
+        _check(lib().ann_server_poll(self._h, ctypes.c_uint64(ticket),
+                                     ids.ctypes.data_as(ctypes.c_void_p),
+                                     d.ctypes.data_as(ctypes.c_void_p), ctypes.byref(done),
+                                     1 if wait else 0))
+        if not done.value:
+            return None
+        del self._k[ticket]
+        return ids, d
+
+    def stats(self, reset: bool = False) -> dict:
+        s = ServerStats()
+        _check(lib().ann_server_get_stats(self._h, ctypes.byref(s), 1 if reset else 0))
+        return s.as_dict()
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _check(lib().ann_server_stop(h))
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
 
 
 # -- differentiable PQ distance (ann_adc_forward / ann_adc_backward) ------------------

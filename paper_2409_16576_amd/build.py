@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBANN = os.path.join(HERE, "libann.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["ann_kernels.hip", "ann_api.cpp", "ann_diff.hip"]
+SOURCES = ["ann_kernels.hip", "ann_api.cpp", "ann_diff.hip", "ann_server.cpp", "ann_batch.cpp"]
 
 # Packed FP32 instructions are disabled for all device code (they are not
 # needed here and some of their forms are unreliable on the test machines).
@@ -59,7 +59,7 @@ def build_libann(jobs: int = 4) -> str:
         if noise:
             sys.stderr.write("\n".join(noise) + "\n")
     tmp = LIBANN + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lz"])
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lz", "-lpthread"])
     os.replace(tmp, LIBANN)
     for o in objs:
         os.remove(o)

@@ -100,6 +100,7 @@ struct ann_index {
   // tuning (ann_set_option); never changes results
   int64_t opt_tile = 65536;
   int64_t opt_split = 16;
+  int64_t opt_lut16 = 0;
   // stage timing
   bool profiling = false;
   std::mutex prof_mu;
@@ -218,6 +219,9 @@ struct WsGuard {
   }
 };
 
+// Set while a search is captured into a HIP graph: no stage events then.
+thread_local bool g_capturing = false;
+
 // Brackets one kernel stage with an event pair when profiling is enabled.
 struct StageMark {
   ann_index* ix;
@@ -237,7 +241,7 @@ struct StageMark {
     return e;
   }
   StageMark(ann_index* ix_, int stage_, hipStream_t st_) : ix(ix_), stage(stage_), st(st_) {
-    if (!ix->profiling) return;
+    if (!ix->profiling || g_capturing) return;
     a = take(ix);
     b = take(ix);
     if (a) (void)hipEventRecord(a, st);
@@ -277,6 +281,8 @@ T rd(const std::vector<uint8_t>& b, size_t off) {
 }
 
 int elem_size(int dtype) { return dtype == F32 ? 4 : 1; }
+
+size_t align_up_sz(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 ann_status validate_args(ann_index* ix, const void* q, int64_t nq, int32_t np_max) {
   if (!ix) return fail(ANN_EINVAL, "index is NULL");
@@ -325,7 +331,7 @@ ann_status check_lds(ann_index* ix, int np_max, int n) {
   if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) !=
       hipSuccess)
     return fail(ANN_EDEVICE, "hipDeviceGetAttribute failed");
-  const size_t need = scan_lds_bytes(ix->d, np_max, n);
+  const size_t need = scan_lds_bytes(ix->d, np_max, n, ix->opt_lut16 != 0);
   if ((int64_t)need > (int64_t)max_lds)
     return fail(ANN_EUNSUPPORTED, "scan needs %zu bytes of LDS per block, device allows %d", need,
                 max_lds);
@@ -585,6 +591,29 @@ extern "C" void ann_free_index(ann_index* ix) { delete ix; }
 
 namespace {
 
+// Steps 1-8 (or 1-7 with topn_ids) for qc <= chunk_queries(...) queries, on
+// the given working buffers.
+ann_status run_chunk(ann_index* ix, Work& w, const float* q, int qc, const int32_t* nprobe,
+                     int32_t np_max, int32_t k, int32_t n, int64_t* out_ids, float* out_d,
+                     int32_t* topn_ids, float* topn_adc, int64_t* ncand, hipStream_t st) {
+  const DevIndex& d = ix->d;
+  LaunchCfg c = cfg_for(qc, np_max, n, k, ix->opt_tile, ix->opt_split);
+  c.lut16 = ix->opt_lut16 != 0;
+  {
+    StageMark m(ix, 0, st);
+    HIP_TRY(launch_probe(d, q, nprobe, np_max, qc, w, nullptr, w.lists, st));
+  }
+  {
+    StageMark m(ix, 2, st);  // steps 1, 3, 5, 6, 7: the table is built inside the scan
+    HIP_TRY(launch_scan(d, w.lists, w.np_eff, q, c, w, st));
+  }
+  {
+    StageMark m(ix, 3, st);
+    HIP_TRY(launch_merge(d, q, c, w, topn_ids, topn_adc, ncand, out_ids, out_d, st));
+  }
+  return ANN_OK;
+}
+
 ann_status run_pipeline(ann_index* ix, const float* Q, int64_t nq, const int32_t* nprobe,
                         int32_t np_max, int32_t k, int32_t n, int64_t* out_ids, float* out_d,
                         int32_t* topn_ids, float* topn_adc, int64_t* ncand, hipStream_t st) {
@@ -599,27 +628,74 @@ ann_status run_pipeline(ann_index* ix, const float* Q, int64_t nq, const int32_t
   WsGuard guard{ix, ws, st};
   for (int64_t q0 = 0; q0 < nq; q0 += qc_max) {
     const int qc = (int)std::min<int64_t>(qc_max, nq - q0);
-    const LaunchCfg c = cfg_for(qc, np_max, n, k, ix->opt_tile, ix->opt_split);
-    const float* q = Q + q0 * d.dim;
-    {
-      StageMark m(ix, 0, st);
-      HIP_TRY(launch_probe(d, q, nprobe ? nprobe + q0 : nullptr, np_max, qc, ws->w, nullptr,
-                           ws->w.lists, st));
-    }
-    {
-      StageMark m(ix, 2, st);  // steps 1, 3, 5, 6, 7: the table is built inside the scan
-      HIP_TRY(launch_scan(d, ws->w.lists, ws->w.np_eff, q, c, ws->w, st));
-    }
-    {
-      StageMark m(ix, 3, st);
-      HIP_TRY(launch_merge(d, q, c, ws->w, topn_ids ? topn_ids + q0 * n : nullptr,
-                           topn_adc ? topn_adc + q0 * n : nullptr, ncand ? ncand + q0 : nullptr,
-                           out_ids ? out_ids + q0 * k : nullptr, out_d ? out_d + q0 * k : nullptr,
-                           st));
-    }
+    s = run_chunk(ix, ws->w, Q + q0 * d.dim, qc, nprobe ? nprobe + q0 : nullptr, np_max, k, n,
+                  out_ids ? out_ids + q0 * k : nullptr, out_d ? out_d + q0 * k : nullptr,
+                  topn_ids ? topn_ids + q0 * n : nullptr, topn_adc ? topn_adc + q0 * n : nullptr,
+                  ncand ? ncand + q0 : nullptr, st);
+    if (s != ANN_OK) return s;
   }
   return ANN_OK;
 }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Helpers for the serving loop (ann_server.cpp).
+
+const DevIndex& ann::index_dev(const ann_index* ix) { return ix->d; }
+int ann::index_device(const ann_index* ix) { return ix->device; }
+
+size_t ann::work_bytes(const DevIndex& d, int qc, int np_max, int n) {
+  const int smax = cfg_for(qc, np_max, n, 1, 65536, 16).smax;
+  const Need g = need_for(d, qc, np_max, n, smax);
+  auto a = [](size_t b) { return align_up_sz(std::max<size_t>(b, 16), 256); };
+  return a(g.qc * g.nlist * 4) + a(g.qc * g.np * 4) + a(g.qc * 4) + a(g.qc * 8) + a(g.qc * 4) +
+         a(g.keys * 8) + a(g.items * 4) + a(g.items * 4);
+}
+
+Work ann::work_carve(const DevIndex& d, int qc, int np_max, int n, void* base) {
+  const int smax = cfg_for(qc, np_max, n, 1, 65536, 16).smax;
+  const Need g = need_for(d, qc, np_max, n, smax);
+  char* p = static_cast<char*>(base);
+  auto take = [&](size_t b) {
+    void* r = p;
+    p += align_up_sz(std::max<size_t>(b, 16), 256);
+    return r;
+  };
+  Work w;
+  w.dist = static_cast<float*>(take(g.qc * g.nlist * 4));
+  w.lists = static_cast<int32_t*>(take(g.qc * g.np * 4));
+  w.np_eff = static_cast<int32_t*>(take(g.qc * 4));
+  w.eq = static_cast<int64_t*>(take(g.qc * 8));
+  w.sq = static_cast<int32_t*>(take(g.qc * 4));
+  w.pkeys = static_cast<uint64_t*>(take(g.keys * 8));
+  w.pcount = static_cast<int32_t*>(take(g.items * 4));
+  w.pscan = static_cast<int32_t*>(take(g.items * 4));
+  return w;
+}
+
+int ann::search_on(ann_index* ix, Work& w, const float* d_q, int qc, const int32_t* d_nprobe,
+                   int np_max, int k, int n, int64_t* d_ids, float* d_dists, hipStream_t st) {
+  ann_status s = check_lds(ix, np_max, n);
+  if (s != ANN_OK) return s;
+  return run_chunk(ix, w, d_q, qc, d_nprobe, np_max, k, n, d_ids, d_dists, nullptr, nullptr,
+                   nullptr, st);
+}
+
+int ann::max_chunk(const DevIndex& d) { return chunk_queries(d, INT32_MAX); }
+
+void ann::set_capturing(bool on) { g_capturing = on; }
+
+int ann::get_opt(const ann_index* ix, int option, int64_t* v) {
+  switch (option) {
+    case ANN_OPT_SCAN_TILE: *v = ix->opt_tile; return ANN_OK;
+    case ANN_OPT_SCAN_SPLIT: *v = ix->opt_split; return ANN_OK;
+    case ANN_OPT_LUT_F16: *v = ix->opt_lut16; return ANN_OK;
+    default: return ANN_EINVAL;
+  }
+}
+
+namespace {
 
 }  // namespace
 
@@ -770,6 +846,10 @@ extern "C" ann_status ann_set_option(ann_index* ix, int option, int64_t value) {
       if (value < 1 || value > 16) return fail(ANN_EINVAL, "split must be in [1, 16]");
       ix->opt_split = value;
       return ANN_OK;
+    case ANN_OPT_LUT_F16:
+      if (value != 0 && value != 1) return fail(ANN_EINVAL, "lut_f16 must be 0 or 1");
+      ix->opt_lut16 = value;
+      return ANN_OK;
     default:
       return fail(ANN_EINVAL, "unknown option %d", option);
   }
@@ -780,6 +860,7 @@ extern "C" ann_status ann_get_option(ann_index* ix, int option, int64_t* value) 
   switch (option) {
     case ANN_OPT_SCAN_TILE: *value = ix->opt_tile; return ANN_OK;
     case ANN_OPT_SCAN_SPLIT: *value = ix->opt_split; return ANN_OK;
+    case ANN_OPT_LUT_F16: *value = ix->opt_lut16; return ANN_OK;
     default: return fail(ANN_EINVAL, "unknown option %d", option);
   }
 }

@@ -1,0 +1,208 @@
+// Batched form: a whole query batch's search captured once into a HIP graph
+// (one graph launch replays probe, scan and merge for every chunk), and an
+// autotuner that picks the scan's work split for a batch by timing it.
+//
+// The graph owns its working memory, so a launch neither allocates nor takes
+// a block from the index's pool; successive launches of one graph are ordered
+// by an event (they share that memory).  Results are those of ann_search on
+// the same buffers: the captured kernels are the same launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <memory>
+#include <vector>
+
+#include "ann.h"
+#include "ann_internal.h"
+
+using namespace ann;
+
+struct ann_graph {
+  ann_index* ix = nullptr;
+  void* work = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t last = nullptr;
+  bool launched = false;
+
+  ~ann_graph() {
+    if (last) {
+      if (launched) (void)hipEventSynchronize(last);
+      (void)hipEventDestroy(last);
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (work) (void)hipFree(work);
+  }
+};
+
+namespace {
+
+ann_status err(ann_status s, const char* what, hipError_t e) {
+  return (ann_status)set_error(s, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Enqueue the search of nq queries on st with the given working memory
+// (chunks of at most max_chunk queries share it in stream order).
+ann_status enqueue_search(ann_index* ix, void* work, const float* q, int64_t nq,
+                          const int32_t* nprobe, int np_max, int k, int n, int64_t* ids,
+                          float* dists, hipStream_t st) {
+  const DevIndex& d = index_dev(ix);
+  const int chunk = max_chunk(d);
+  for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
+    const int qc = (int)std::min<int64_t>(chunk, nq - q0);
+    Work w = work_carve(d, qc, np_max, n, work);
+    const int s = search_on(ix, w, q + q0 * d.dim, qc, nprobe ? nprobe + q0 : nullptr, np_max, k,
+                            n, ids + q0 * k, dists + q0 * k, st);
+    if (s != ANN_OK) return (ann_status)s;
+  }
+  return ANN_OK;
+}
+
+ann_status check_search_args(ann_index* ix, const float* q, int64_t nq, int32_t np_max, int32_t k,
+                             int32_t n, const void* ids, const void* dists) {
+  if (!ix) return (ann_status)set_error(ANN_EINVAL, "index is NULL");
+  if (nq < 1) return (ann_status)set_error(ANN_EINVAL, "nq must be >= 1");
+  if (!q || !ids || !dists) return (ann_status)set_error(ANN_EINVAL, "NULL pointer");
+  if (np_max < 1 || np_max > 4096)
+    return (ann_status)set_error(ANN_EINVAL, "nprobe_max must be in [1, 4096]");
+  if (k < 1) return (ann_status)set_error(ANN_EINVAL, "k must be >= 1");
+  if (n < k || n > kMaxRerank)
+    return (ann_status)set_error(ANN_EINVAL, "rerank_n must be in [k, %d]", kMaxRerank);
+  return ANN_OK;
+}
+
+}  // namespace
+
+extern "C" ann_status ann_graph_create(ann_index* ix, const float* d_queries, int64_t nq,
+                                       const int32_t* d_nprobe, int32_t nprobe_max, int32_t k,
+                                       int32_t rerank_n, int64_t* d_out_ids, float* d_out_dists,
+                                       ann_graph** out) {
+  if (!out) return (ann_status)set_error(ANN_EINVAL, "NULL argument");
+  *out = nullptr;
+  ann_status s = check_search_args(ix, d_queries, nq, nprobe_max, k, rerank_n, d_out_ids,
+                                   d_out_dists);
+  if (s != ANN_OK) return s;
+  hipError_t e = hipSetDevice(index_device(ix));
+  if (e != hipSuccess) return err(ANN_EDEVICE, "hipSetDevice", e);
+  const DevIndex& d = index_dev(ix);
+  const int chunk = (int)std::min<int64_t>(nq, max_chunk(d));
+  std::unique_ptr<ann_graph> g(new ann_graph());
+  g->ix = ix;
+  if ((e = hipMalloc(&g->work, work_bytes(d, chunk, nprobe_max, rerank_n))) != hipSuccess)
+    return err(ANN_ENOMEM, "graph working memory", e);
+  if ((e = hipEventCreateWithFlags(&g->last, hipEventDisableTiming)) != hipSuccess)
+    return err(ANN_EDEVICE, "hipEventCreate", e);
+  hipStream_t cs = nullptr;
+  if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess)
+    return err(ANN_EDEVICE, "hipStreamCreate", e);
+  if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return err(ANN_EDEVICE, "hipStreamBeginCapture", e);
+  }
+  set_capturing(true);
+  s = enqueue_search(ix, g->work, d_queries, nq, d_nprobe, nprobe_max, k, rerank_n, d_out_ids,
+                     d_out_dists, cs);
+  set_capturing(false);
+  e = hipStreamEndCapture(cs, &g->graph);
+  (void)hipStreamDestroy(cs);
+  if (s != ANN_OK) return s;
+  if (e != hipSuccess) return err(ANN_EDEVICE, "hipStreamEndCapture", e);
+  if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess)
+    return err(ANN_EDEVICE, "hipGraphInstantiate", e);
+  *out = g.release();
+  return ANN_OK;
+}
+
+extern "C" ann_status ann_graph_launch(ann_graph* g, void* stream) {
+  if (!g) return (ann_status)set_error(ANN_EINVAL, "graph is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSetDevice(index_device(g->ix));
+  if (e != hipSuccess) return err(ANN_EDEVICE, "hipSetDevice", e);
+  if (g->launched && (e = hipStreamWaitEvent(st, g->last, 0)) != hipSuccess)
+    return err(ANN_EDEVICE, "hipStreamWaitEvent", e);
+  if ((e = hipGraphLaunch(g->exec, st)) != hipSuccess) return err(ANN_EDEVICE, "hipGraphLaunch", e);
+  if ((e = hipEventRecord(g->last, st)) != hipSuccess) return err(ANN_EDEVICE, "hipEventRecord", e);
+  g->launched = true;
+  return ANN_OK;
+}
+
+extern "C" void ann_graph_free(ann_graph* g) { delete g; }
+
+extern "C" ann_status ann_autotune(ann_index* ix, const float* d_queries, int64_t nq,
+                                   const int32_t* d_nprobe, int32_t nprobe_max, int32_t k,
+                                   int32_t rerank_n, int32_t reps, ann_tune_result* out) {
+  if (!out) return (ann_status)set_error(ANN_EINVAL, "NULL argument");
+  if (reps < 1 || reps > 100) return (ann_status)set_error(ANN_EINVAL, "reps must be in [1, 100]");
+  int64_t* ids = nullptr;
+  float* dists = nullptr;
+  ann_status s = check_search_args(ix, d_queries, nq, nprobe_max, k, rerank_n, d_queries,
+                                   d_queries);
+  if (s != ANN_OK) return s;
+  hipError_t e = hipSetDevice(index_device(ix));
+  if (e != hipSuccess) return err(ANN_EDEVICE, "hipSetDevice", e);
+  int64_t tile0 = 0, split0 = 0;
+  get_opt(ix, ANN_OPT_SCAN_TILE, &tile0);
+  get_opt(ix, ANN_OPT_SCAN_SPLIT, &split0);
+  hipStream_t st = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  std::vector<std::pair<int64_t, int>> cand;
+  for (int64_t tile : {4096LL, 8192LL, 16384LL, 32768LL, 65536LL, 131072LL, 1LL << 30})
+    for (int split : {1, 2, 4, 8, 16}) {
+      if (tile == (1LL << 30) && split > 1) continue;  // one item per query whatever the split
+      cand.push_back({tile, split});
+    }
+  ann_tune_result best{};
+  best.ms = -1.0;
+  int tried = 0;
+  auto cleanup = [&]() {
+    if (st) (void)hipStreamSynchronize(st);
+    if (ids) (void)hipFree(ids);
+    if (dists) (void)hipFree(dists);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (st) (void)hipStreamDestroy(st);
+  };
+  if ((e = hipMalloc(&ids, (size_t)nq * k * 8)) != hipSuccess ||
+      (e = hipMalloc(&dists, (size_t)nq * k * 4)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
+    cleanup();
+    return err(ANN_ENOMEM, "autotune buffers", e);
+  }
+  for (auto [tile, split] : cand) {
+    ann_set_option(ix, ANN_OPT_SCAN_TILE, tile);
+    ann_set_option(ix, ANN_OPT_SCAN_SPLIT, split);
+    std::vector<float> t;
+    for (int r = 0; r <= reps && s == ANN_OK; ++r) {  // r = 0: warm-up
+      (void)hipEventRecord(a, st);
+      s = ann_search(ix, d_queries, nq, d_nprobe, nprobe_max, k, rerank_n, ids, dists, st);
+      (void)hipEventRecord(b, st);
+      if ((e = hipEventSynchronize(b)) != hipSuccess) s = err(ANN_EDEVICE, "autotune run", e);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      if (r > 0) t.push_back(ms);
+    }
+    if (s != ANN_OK) break;
+    std::sort(t.begin(), t.end());
+    const double med = t[t.size() / 2];
+    ++tried;
+    if (best.ms < 0 || med < best.ms) {
+      best.tile = tile;
+      best.split = split;
+      best.ms = med;
+    }
+  }
+  cleanup();
+  if (s != ANN_OK) {
+    ann_set_option(ix, ANN_OPT_SCAN_TILE, tile0);
+    ann_set_option(ix, ANN_OPT_SCAN_SPLIT, split0);
+    return s;
+  }
+  ann_set_option(ix, ANN_OPT_SCAN_TILE, best.tile);
+  ann_set_option(ix, ANN_OPT_SCAN_SPLIT, best.split);
+  best.tried = tried;
+  *out = best;
+  return ANN_OK;
+}

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+struct ann_index;
+
 namespace ann {
 
 enum DType : int { F32 = 0, U8 = 1, I8 = 2 };
@@ -69,6 +71,7 @@ struct LaunchCfg {
   int k;
   int smax;        // work items per query (max)
   int tile;        // target entries per work item
+  bool lut16 = false;  // half-precision distance table in the scan
 };
 
 // Kernel launchers (ann_kernels.hip).  All enqueue on `st` and return hipError_t.
@@ -88,11 +91,23 @@ hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, 
 hipError_t launch_rerank_only(const DevIndex& ix, const float* q, const int32_t* cand, int qc,
                               int n, int k, int64_t* out_ids, float* out_dists, hipStream_t st);
 
+// Serving-loop helpers (ann_api.cpp): the pipeline of ann_search for one
+// chunk of queries on caller-carved working buffers (no allocation).
+const DevIndex& index_dev(const ann_index* ix);
+int index_device(const ann_index* ix);
+size_t work_bytes(const DevIndex& d, int qc, int np_max, int n);  // 256-aligned total
+Work work_carve(const DevIndex& d, int qc, int np_max, int n, void* base);
+int search_on(ann_index* ix, Work& w, const float* d_q, int qc, const int32_t* d_nprobe,
+              int np_max, int k, int n, int64_t* d_ids, float* d_dists, hipStream_t st);
+int max_chunk(const DevIndex& d);  // most queries one search_on call may take
+void set_capturing(bool on);       // this thread is capturing a graph: no stage events
+int get_opt(const ann_index* ix, int option, int64_t* v);
+
 // Records the thread's last error message (ann_last_error) and returns s.
 int set_error(int s, const char* fmt, ...);
 
 // Sizes of the dynamic LDS areas (bytes) for the scan kernel.
-size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n);
+size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n, bool lut16);
 int scan_smax(int n);
 
 }  // namespace ann

@@ -22,7 +22,10 @@
 // lower id.
 #pragma clang fp contract(off)
 
+#include <hip/hip_fp16.h>
+
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "ann_internal.h"
@@ -474,10 +477,10 @@ __host__ __device__ inline int scan_max_runs(int np_max, int max_segs, bool segm
 }
 
 __host__ __device__ inline ScanLayout scan_layout(int M, int nlist, int R, int np_max,
-                                                  int max_runs, int cap) {
+                                                  int max_runs, int cap, int lut_elem) {
   ScanLayout L;
   size_t o = 0;
-  L.lut = o; o += (size_t)M * kKsub * 4; o = align_up(o, 16);
+  L.lut = o; o += (size_t)M * kKsub * lut_elem; o = align_up(o, 16);
   L.bits = o; o += (R > 1 ? (size_t)((nlist + 31) / 32) * 4 : 0); o = align_up(o, 16);
   L.list = o; o += (size_t)np_max * 4; o = align_up(o, 16);
   L.rstart = o; o += (size_t)max_runs * 4; o = align_up(o, 16);
@@ -541,9 +544,14 @@ __device__ __forceinline__ void load_row(const uint8_t* __restrict__ rowp, uint3
   }
 }
 
-// Eq. 1 for one code row: float32 sum over m = 0..M-1 in order.
-template <int W>
-__device__ __forceinline__ float adc_words(const uint32_t (&w)[W], const float* __restrict__ s_lut,
+__device__ __forceinline__ float lut_val(float v) { return v; }
+__device__ __forceinline__ float lut_val(__half v) { return __half2float(v); }  // exact
+
+// Eq. 1 for one code row: float32 sum over m = 0..M-1 in order.  The table
+// holds float32 entries, or binary16 entries (the half-precision variant,
+// widened exactly before the float32 sum).
+template <int W, class T>
+__device__ __forceinline__ float adc_words(const uint32_t (&w)[W], const T* __restrict__ s_lut,
                                            int M) {
   float acc = 0.f;
 #pragma unroll
@@ -551,7 +559,7 @@ __device__ __forceinline__ float adc_words(const uint32_t (&w)[W], const float* 
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int m = 4 * i + b;
-      if (i < W - 1 || m < M) acc = acc + s_lut[m * kKsub + ((w[i] >> (8 * b)) & 255u)];
+      if (i < W - 1 || m < M) acc = acc + lut_val(s_lut[m * kKsub + ((w[i] >> (8 * b)) & 255u)]);
     }
   }
   return acc;
@@ -599,7 +607,7 @@ __device__ void scan_compact(uint64_t* s_buf, int* s_wsum, SelScratch* ss, ScanM
 // back to the n best whenever it holds more than n.
 constexpr uint32_t kRunReplica = 0x80000000u;  // run start flag: replica-entry run
 
-template <int W, bool TRACE>
+template <int W, bool TRACE, bool H>
 __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_scan(
     DevIndex ix, const int32_t* __restrict__ lists, const int32_t* __restrict__ np_eff, int np_max,
     int qc, const float* __restrict__ Q, const float* __restrict__ lut,
@@ -618,8 +626,9 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   const int M = ix.M;
 
   extern __shared__ __align__(16) unsigned char smem[];
-  const ScanLayout L = scan_layout(M, ix.nlist, ix.R, np_max, max_runs, cap);
-  float* s_lut = reinterpret_cast<float*>(smem + L.lut);
+  using LutT = std::conditional_t<H, __half, float>;
+  const ScanLayout L = scan_layout(M, ix.nlist, ix.R, np_max, max_runs, cap, sizeof(LutT));
+  LutT* s_lut = reinterpret_cast<LutT*>(smem + L.lut);
   uint32_t* s_bits = reinterpret_cast<uint32_t*>(smem + L.bits);
   int32_t* s_list = reinterpret_cast<int32_t*>(smem + L.list);
   uint32_t* s_rstart = reinterpret_cast<uint32_t*>(smem + L.rstart);
@@ -709,13 +718,21 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
 
   // Distance table of this query into LDS: computed here (step 1 fused into
   // the scan) unless the caller passed one in.
-  if (lut) {
-    const float4* src = reinterpret_cast<const float4*>(lut + (size_t)q * M * kKsub);
-    float4* dst = reinterpret_cast<float4*>(s_lut);
-    for (int i = tid; i < M * (kKsub / 4); i += kScanBlock) dst[i] = src[i];
+  if constexpr (!H) {
+    if (lut) {
+      const float4* src = reinterpret_cast<const float4*>(lut + (size_t)q * M * kKsub);
+      float4* dst = reinterpret_cast<float4*>(s_lut);
+      for (int i = tid; i < M * (kKsub / 4); i += kScanBlock) dst[i] = src[i];
+    } else {
+      const float* qrow = Q + (size_t)q * ix.dim;
+      for (int i = tid; i < M * kKsub; i += kScanBlock)
+        s_lut[i] = lut_entry(ix, qrow, i >> 8, i & 255);
+    }
   } else {
+    // half-precision variant: nearest binary16 of the float32 entry, ties to even
     const float* qrow = Q + (size_t)q * ix.dim;
-    for (int i = tid; i < M * kKsub; i += kScanBlock) s_lut[i] = lut_entry(ix, qrow, i >> 8, i & 255);
+    for (int i = tid; i < M * kKsub; i += kScanBlock)
+      s_lut[i] = __float2half_rn(lut_entry(ix, qrow, i >> 8, i & 255));
   }
   __syncthreads();
 
@@ -768,7 +785,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     }
 #pragma unroll
     for (int u = 0; u < kScanRT; ++u) {
-      const float acc = adc_words<W>(cw[u], s_lut, M);
+      const float acc = adc_words<W, LutT>(cw[u], s_lut, M);
       scanned += keep[u] ? 1 : 0;
       if constexpr (TRACE) {
         const uint64_t m = __ballot(keep[u]);
@@ -805,7 +822,8 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     }
     __syncthreads();
     if constexpr (!TRACE) {
-      if (mc->count > n) scan_compact(s_buf, s_wsum, ss, mc, n);
+      // cut back to the n best only when the next round might not fit
+      if (mc->count > cap - kScanBlock * kScanRT) scan_compact(s_buf, s_wsum, ss, mc, n);
     }
   }
   // candidates scored by this item
@@ -910,9 +928,12 @@ __device__ void rerank_int16(const DevIndex& ix, const float* s_q, const uint64_
   }
 }
 
-// Re-rank s_top[0..nn) (keys of (adc, id)) by exact distance and write top-k.
-__device__ void rerank_write(const DevIndex& ix, const float* s_q, const uint64_t* s_top, int nn,
-                             uint64_t* s_key2, int P, int k, int64_t* out_ids, float* out_d) {
+// Re-rank s_top[0..nn) (keys of (adc, id)) by exact distance and write the
+// top-k, sorted.  s_key2 holds P >= nn keys; s_top is reused for the result
+// (it needs pow2_at_least(min(k, nn)) slots).
+__device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_top, int nn,
+                             uint64_t* s_key2, int P, int k, int64_t* out_ids, float* out_d,
+                             SelScratch* ss, int* s_cnt) {
   const int g16 = ix.dim % 16 == 0 ? ix.dim / 16 : 0;
   if (ix.dtype != F32 && (g16 == 1 || g16 == 2 || g16 == 4 || g16 == 8 || g16 == 16)) {
     switch (g16) {
@@ -964,11 +985,28 @@ __device__ void rerank_write(const DevIndex& ix, const float* s_q, const uint64_
     }
   }
   __syncthreads();
-  block_bitonic(s_key2, P);
+  // the kk smallest keys: select the kk-th, collect, sort kk
+  const int kk = min(k, nn);
+  if (kk > 0) {
+    const int pk = pow2_at_least(kk);
+    const uint64_t K = kk == nn ? ~0ull : block_kth([&](int i) { return s_key2[i]; }, nn, kk, ss);
+    if (threadIdx.x == 0) *s_cnt = 0;
+    for (int i = threadIdx.x; i < pk; i += blockDim.x) s_top[i] = ~0ull;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+      const uint64_t key = s_key2[i];
+      if (key <= K) {
+        const int pos = atomicAdd(s_cnt, 1);
+        if (pos < pk) s_top[pos] = key;
+      }
+    }
+    __syncthreads();
+    block_bitonic(s_top, pk);
+  }
   for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    const bool v = i < nn;
-    out_ids[i] = v ? (int64_t)(uint32_t)s_key2[i] : -1;
-    out_d[i] = v ? unord32((uint32_t)(s_key2[i] >> 32)) : INFINITY;
+    const bool v = i < kk;
+    out_ids[i] = v ? (int64_t)(uint32_t)s_top[i] : -1;
+    out_d[i] = v ? unord32((uint32_t)(s_top[i] >> 32)) : INFINITY;
   }
 }
 
@@ -1053,7 +1091,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(
   }
   if (out_ids) {
     __syncthreads();  // s_key2 aliases s_keys
-    rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k, out_dists + (size_t)q * k);
+    rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k,
+                 out_dists + (size_t)q * k, ss, s_cnt);
   }
 }
 
@@ -1078,7 +1117,9 @@ __global__ __launch_bounds__(kBlock) void k_rerank_only(DevIndex ix, const float
   }
   __syncthreads();
   const int nn = *s_cnt;
-  rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k, out_dists + (size_t)q * k);
+  __shared__ SelScratch ss;
+  rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k, out_dists + (size_t)q * k,
+               &ss, s_cnt);
 }
 
 // Segmented replica runs when their LDS bound stays small.
@@ -1096,22 +1137,23 @@ template <int W>
 hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t* np_eff,
                          int np_max, int qc, const float* Q, const float* lut, int32_t* sq,
                          int smax, int tile, int n, int cap, uint64_t* pkeys, int32_t* pcount,
-                         int32_t* pscan, bool trace, int64_t t_capacity, int32_t* t_ids,
-                         float* t_adc, int64_t* t_count, hipStream_t st) {
+                         int32_t* pscan, bool trace, bool lut16, int64_t t_capacity,
+                         int32_t* t_ids, float* t_adc, int64_t* t_count, hipStream_t st) {
   const int seg = scan_segmented(ix, np_max) ? 1 : 0;
   const int max_runs = scan_runs(ix, np_max);
-  const ScanLayout L = scan_layout(ix.M, ix.nlist, ix.R, np_max, max_runs, cap);
+  const ScanLayout L =
+      scan_layout(ix.M, ix.nlist, ix.R, np_max, max_runs, cap, (!trace && lut16) ? 2 : 4);
   const int qpad = (qc + 7) / 8 * 8;
   const dim3 grid((unsigned)((size_t)qpad * smax));
   if (trace) {
-    auto kern = k_scan<W, true>;
+    auto kern = k_scan<W, true, false>;
     if (L.total > 65536)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
     hipLaunchKernelGGL(kern, grid, dim3(kScanBlock), L.total, st, ix, lists, np_eff, np_max, qc,
                        Q, lut, sq, smax, tile, seg, max_runs, n, cap, pkeys, pcount, pscan,
                        t_capacity, t_ids, t_adc, reinterpret_cast<unsigned long long*>(t_count));
   } else {
-    auto kern = k_scan<W, false>;
+    auto kern = lut16 ? k_scan<W, false, true> : k_scan<W, false, false>;
     if (L.total > 65536)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
     hipLaunchKernelGGL(kern, grid, dim3(kScanBlock), L.total, st, ix, lists, np_eff, np_max, qc,
@@ -1123,7 +1165,7 @@ hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t
 
 using ScanFn = hipError_t (*)(const DevIndex&, const int32_t*, const int32_t*, int, int,
                               const float*, const float*, int32_t*, int, int, int, int, uint64_t*,
-                              int32_t*, int32_t*, bool, int64_t, int32_t*, float*, int64_t*,
+                              int32_t*, int32_t*, bool, bool, int64_t, int32_t*, float*, int64_t*,
                               hipStream_t);
 
 template <int... Ws>
@@ -1144,9 +1186,23 @@ ScanFn scan_fn(int W) {
 
 int scan_smax(int n) { return std::max(1, std::min(16, 4096 / std::max(n, 1))); }
 
-size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n) {
+// Top-n buffer slots of a scan block: n + one round of entries at least;
+// more slack (fewer cut-backs) while the block still fits twice in a CU's LDS.
+int scan_cap(const DevIndex& ix, int np_max, int n, bool lut16) {
+  constexpr size_t kTwoPerCU = 80 * 1024;
+  constexpr int kRound = kScanBlock * kScanRT;
+  const int base = n + kRound;
+  const size_t fixed =
+      scan_layout(ix.M, ix.nlist, ix.R, np_max, scan_runs(ix, np_max), 0, lut16 ? 2 : 4).total;
+  int extra = 0;
+  if (fixed + (size_t)base * 8 + 64 < kTwoPerCU)
+    extra = (int)((kTwoPerCU - 64 - fixed - (size_t)base * 8) / 8) / 64 * 64;
+  return std::min(base + std::min(extra, 2 * kRound), kCompactChunk * kScanBlock);
+}
+
+size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n, bool lut16) {
   return scan_layout(ix.M, ix.nlist, ix.R, np_max, scan_runs(ix, np_max),
-                     n + kScanBlock * kScanRT).total;
+                     scan_cap(ix, np_max, n, lut16), lut16 ? 2 : 4).total;
 }
 
 static bool exact64(const DevIndex& ix) { return !ix.int_grid; }
@@ -1186,9 +1242,9 @@ hipError_t launch_scan(const DevIndex& ix, const int32_t* lists, const int32_t* 
                        const float* q, const LaunchCfg& c, Work& w, hipStream_t st) {
   if (c.qc <= 0) return hipSuccess;
   const int W = (ix.M + 3) / 4;
-  const int cap = c.n + kScanBlock * kScanRT;
+  const int cap = scan_cap(ix, c.np_max, c.n, c.lut16);
   return scan_fn(W)(ix, lists, np_eff, c.np_max, c.qc, q, nullptr, w.sq, c.smax, c.tile, c.n, cap,
-                    w.pkeys, w.pcount, w.pscan, false, 0, nullptr, nullptr, nullptr, st);
+                    w.pkeys, w.pcount, w.pscan, false, c.lut16, 0, nullptr, nullptr, nullptr, st);
 }
 
 hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const float* lut, int qc,
@@ -1201,7 +1257,7 @@ hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const flo
   hipLaunchKernelGGL(k_zero_i64, dim3((qc + 255) / 256), dim3(256), 0, st, out_count, qc);
   const int W = (ix.M + 3) / 4;
   return scan_fn(W)(ix, lists, w.np_eff, np_max, qc, nullptr, lut, w.sq, smax, tile, 1, 1, nullptr,
-                    nullptr, nullptr, true, capacity, out_ids, out_adc, out_count, st);
+                    nullptr, nullptr, true, false, capacity, out_ids, out_adc, out_count, st);
 }
 
 hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,

@@ -158,7 +158,7 @@ def test_search_bit_exact(name, indexes, gpu_index, orc):
     _say("search", name)
     rng = np.random.default_rng(9)
     npr = rng.integers(1, 20, size=len(Q)).astype(np.int32)
-    for k, n in ((10, 10), (10, 64), (7, 200), (1, 1000), (10, 1400), (32, 4096)):
+    for k, n in ((10, 10), (10, 64), (7, 200), (1, 1000), (10, 1400), (64, 2048), (32, 4096)):
         ids, d = g.search(_cuda(Q), _cuda(npr), k, n)
         torch.cuda.synchronize()
         r = orc.search(ix, Q, npr, k, n)
@@ -276,3 +276,24 @@ def test_work_split_does_not_change_results(name, tile, split, indexes, gpu_inde
     finally:
         g.set_option(g.OPT_SCAN_TILE, 65536)
         g.set_option(g.OPT_SCAN_SPLIT, 16)
+
+
+@pytest.mark.parametrize("name", KINDS)
+def test_half_table_variant_bit_exact(name, indexes, gpu_index, orc):
+    """ANN_OPT_LUT_F16: binary16 table entries (nearest, ties to even), float32
+    sum; top-n and final results equal the oracle's half-table variant."""
+    ix, _, Q = indexes[name]
+    g = gpu_index(name)
+    _say("lut f16", name)
+    g.set_option(g.OPT_LUT_F16, 1)
+    try:
+        assert g.get_option(g.OPT_LUT_F16) == 1
+        for k, n in ((10, 100), (10, 1400)):
+            r = orc.search(ix, Q, 13, k, n, lut_f16=True)
+            ids, adc, nc = g.search_topn(_cuda(Q), 13, n)
+            assert np.array_equal(ids.cpu().numpy(), r.topn_ids), n
+            assert np.array_equal(adc.cpu().numpy(), r.topn_adc), n
+            ids, d = g.search(_cuda(Q), 13, k, n)
+            assert np.array_equal(ids.cpu().numpy(), r.ids) and np.array_equal(d.cpu().numpy(), r.dists)
+    finally:
+        g.set_option(g.OPT_LUT_F16, 0)

@@ -349,10 +349,14 @@ class Server:
     def poll(self, ticket: int, wait: bool = True):
         """(ids int64 [nq, k], dists float32 [nq, k]) once done, else None."""
         import numpy as np
+        done = ctypes.c_int32()
+        if ticket not in self._k:  # not issued here, or already collected: the library says so
+            _check(lib().ann_server_poll(self._h, ctypes.c_uint64(ticket), None, None,
+                                         ctypes.byref(done), 1 if wait else 0))
+            return None
         nq, k = self._k[ticket]
         ids = np.empty((nq, k), dtype=np.int64)
         d = np.empty((nq, k), dtype=np.float32)
-        done = ctypes.c_int32()
         _check(lib().ann_server_poll(self._h, ctypes.c_uint64(ticket),
                                      ids.ctypes.data_as(ctypes.c_void_p),
                                      d.ctypes.data_as(ctypes.c_void_p), ctypes.byref(done),

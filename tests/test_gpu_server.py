@@ -158,7 +158,6 @@ def test_server_errors(ann, setup):
         assert srv.poll(t, wait=True) is not None
         with pytest.raises(ann.AnnError):
             srv.poll(t, wait=True)               # already collected
-        srv._k[12345] = (1, 10)
         with pytest.raises(ann.AnnError):
             srv.poll(12345, wait=False)          # never issued
     finally:

@@ -83,6 +83,9 @@ def parse():
                     help="arrival window per offered load")
     ap.add_argument("--lut16", action="store_true",
                     help="half-precision distance table (binary16 entries, float32 sums)")
+    ap.add_argument("--split", type=int, default=0,
+                    help="batched form: this work split instead of the autotuner's")
+    ap.add_argument("--tile", type=int, default=65536, help="with --split: entries per item")
     ap.add_argument("--build-only", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
@@ -254,26 +257,39 @@ def main():
         out["res"] = g.search(Q, nprobe_arg, k, n)
 
     def step_graph():
-        out["res"] = graph.launch(st)
+        out["graph_res"] = graph.launch(st)
 
     forms = {"plain": step_plain, "batched": step_graph, "batched_eager": step_eager}
     names = args.forms.split(",")
+    default_split = (g.get_option(g.OPT_SCAN_TILE), g.get_option(g.OPT_SCAN_SPLIT))
     if "batched" in names:
-        # the batched form: work split picked by the autotuner for this batch,
-        # then the whole search captured once into a HIP graph; its stage
-        # times (and the scan roofline) come from an eager, event-bracketed run
-        # of the same search right after
-        tuned = ann.autotune(g, Q, nprobe_arg, k, n, reps=2)
-        log(f"autotune: tile {tuned['tile']}, split {tuned['split']} ({tuned['tried']} tried, "
+        # the batched form: work split picked by the autotuner for this batch
+        # (or given), then the whole search captured once into a HIP graph; its
+        # stage times (and the scan roofline) come from an eager,
+        # event-bracketed run of the same search right after
+        if args.split:
+            g.set_option(g.OPT_SCAN_TILE, args.tile)
+            g.set_option(g.OPT_SCAN_SPLIT, args.split)
+            tuned = {"tile": args.tile, "split": args.split, "tried": 0, "ms": 0.0}
+        else:
+            tuned = ann.autotune(g, Q, nprobe_arg, k, n, reps=2)
+        log(f"work split: tile {tuned['tile']}, split {tuned['split']} ({tuned['tried']} tried, "
             f"{tuned['ms']:.3f} ms)")
         graph = ann.Graph(g, Q, nprobe_arg, k, n)
         names.insert(names.index("batched") + 1, "batched_eager")
+    batched_split = (g.get_option(g.OPT_SCAN_TILE), g.get_option(g.OPT_SCAN_SPLIT))
     results = {}
     for name in names:
         if name == "served":
+            g.set_option(g.OPT_SCAN_TILE, default_split[0])
+            g.set_option(g.OPT_SCAN_SPLIT, default_split[1])
             results[name] = run_served(ann, g, Qh, npq, w, k, n, args)
             continue
         fn = forms[name]
+        # plain (and served) run with the index's default work split
+        sp = batched_split if name.startswith("batched") else default_split
+        g.set_option(g.OPT_SCAN_TILE, sp[0])
+        g.set_option(g.OPT_SCAN_SPLIT, sp[1])
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
@@ -352,7 +368,8 @@ def main():
         r = oracle.search(oix, Qh[:ns], npq[:ns], k, n, threads=threads, lut_f16=args.lut16)
         cpu_s = time.perf_counter() - t0
         log(f"oracle: {ns} queries in {cpu_s:.2f}s on {threads} threads")
-        ids_gpu, d_gpu = out["res"] if "res" in out else g.search(Q, nprobe_arg, k, n)
+        # parity of the headline form's own output (the graph's), else an eager search
+        ids_gpu, d_gpu = out.get("graph_res") or out.get("res") or g.search(Q, nprobe_arg, k, n)
         ids_gpu = ids_gpu[:ns].cpu().numpy()
         d_gpu = d_gpu[:ns].cpu().numpy()
         line["parity_sample"] = {"queries": ns, "ids_equal": bool(np.array_equal(ids_gpu, r.ids)),

@@ -81,7 +81,7 @@ struct SelScratch {
 };
 
 template <class G>
-__device__ uint64_t block_kth(G get, int cnt, int want, SelScratch* s) {
+__device__ __forceinline__ uint64_t block_kth(G get, int cnt, int want, SelScratch* s) {
   const int tid = threadIdx.x;
   if (tid == 0) {
     s->want = want;
@@ -123,9 +123,31 @@ __device__ uint64_t block_kth(G get, int cnt, int want, SelScratch* s) {
     for (int i = tid; i < 256; i += blockDim.x) s->hist[i] = 0;
     __syncthreads();
     const uint64_t prefix = s->prefix;
-    for (int i = tid; i < cnt; i += blockDim.x) {
-      const uint64_t k = get(i);
-      if ((k & mask) == prefix) atomicAdd(&s->hist[(k >> shift) & 255u], 1u);
+    // Histogram of the digit.  Keys cluster on few digits (nearby distances
+    // share their high bits), so lanes holding the same digit first combine
+    // into one atomic per digit (a few rounds), the rest add one by one.
+    for (int i0 = 0; i0 < cnt; i0 += blockDim.x) {  // trip count uniform per wave
+      const int i = i0 + tid;
+      uint64_t k = 0;
+      bool act = false;
+      if (i < cnt) {
+        k = get(i);
+        act = (k & mask) == prefix;
+      }
+      const uint32_t dig = (uint32_t)(k >> shift) & 255u;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        if (act) {
+          const uint32_t d = __builtin_amdgcn_readfirstlane(dig);  // first active lane's digit
+          const uint64_t same = __ballot(dig == d);                  // active lanes only
+          if (dig == d) {
+            if ((tid & 63) == __ffsll((unsigned long long)same) - 1)
+              atomicAdd(&s->hist[d], (uint32_t)__popcll(same));
+            act = false;
+          }
+        }
+      }
+      if (act) atomicAdd(&s->hist[dig], 1u);
     }
     __syncthreads();
     const uint32_t w = (uint32_t)s->want;
@@ -450,6 +472,57 @@ __device__ __forceinline__ float lut_entry(const DevIndex& ix, const float* __re
   return acc;
 }
 
+// Entry [m][j] from the already converted subvector m of the query (qs),
+// same arithmetic and order as lut_entry.
+__device__ __forceinline__ float lut_entry_conv(const DevIndex& ix, const float* qs, int m, int j) {
+  const float* c = ix.codebooks + ((size_t)m * kKsub + j) * ix.dsub;
+  if (!ix.int_grid) {
+    double acc = 0.0;
+    for (int t = 0; t < ix.dsub; ++t) {
+      const double u = (double)qs[t] - (double)c[t];
+      const double sq = u * u;
+      acc = acc + sq;
+    }
+    return (float)acc;
+  }
+  float acc = 0.f;
+  for (int t = 0; t < ix.dsub; ++t) {
+    const float u = qs[t] - c[t];
+    acc = acc + u * u;
+  }
+  return acc;
+}
+
+// The same with dsub a multiple of 4: the codeword is read as float4 vectors.
+__device__ __forceinline__ float lut_entry_v4(const DevIndex& ix, const float* qs, int m, int j) {
+  const float4* c4 = reinterpret_cast<const float4*>(ix.codebooks + ((size_t)m * kKsub + j) * ix.dsub);
+  if (!ix.int_grid) {
+    double acc = 0.0;
+    auto add = [&](float qv, float cv) {
+      const double u = (double)qv - (double)cv;
+      const double sq = u * u;
+      acc = acc + sq;
+    };
+    for (int t4 = 0; t4 < ix.dsub / 4; ++t4) {
+      const float4 c = c4[t4];
+      const float* qq = qs + 4 * t4;
+      add(qq[0], c.x); add(qq[1], c.y); add(qq[2], c.z); add(qq[3], c.w);
+    }
+    return (float)acc;
+  }
+  float acc = 0.f;
+  auto add = [&](float qv, float cv) {
+    const float u = qv - cv;
+    acc = acc + u * u;
+  };
+  for (int t4 = 0; t4 < ix.dsub / 4; ++t4) {
+    const float4 c = c4[t4];
+    const float* qq = qs + 4 * t4;
+    add(qq[0], c.x); add(qq[1], c.y); add(qq[2], c.z); add(qq[3], c.w);
+  }
+  return acc;
+}
+
 // One block per query, thread = codeword, loop over subspaces.
 __global__ __launch_bounds__(kBlock) void k_lut(DevIndex ix, const float* __restrict__ Q, int qc,
                                                  float* __restrict__ lut) {
@@ -571,7 +644,7 @@ __device__ __forceinline__ float adc_words(const uint32_t (&w)[W], const T* __re
 // moves to a position no later than its own (all reads precede all writes).
 constexpr int kCompactChunk = 8;  // cap <= kCompactChunk * kScanBlock
 
-__device__ void scan_compact(uint64_t* s_buf, int* s_wsum, SelScratch* ss, ScanMisc* mc, int n) {
+__device__ __forceinline__ void scan_compact(uint64_t* s_buf, int* s_wsum, SelScratch* ss, ScanMisc* mc, int n) {
   const int cnt = mc->count;
   if (cnt <= n) return;
   const uint64_t K = block_kth([&](int i) { return s_buf[i]; }, cnt, n, ss);
@@ -717,22 +790,27 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   if (j >= S) return;
 
   // Distance table of this query into LDS: computed here (step 1 fused into
-  // the scan) unless the caller passed one in.
-  if constexpr (!H) {
-    if (lut) {
-      const float4* src = reinterpret_cast<const float4*>(lut + (size_t)q * M * kKsub);
-      float4* dst = reinterpret_cast<float4*>(s_lut);
-      for (int i = tid; i < M * (kKsub / 4); i += kScanBlock) dst[i] = src[i];
-    } else {
-      const float* qrow = Q + (size_t)q * ix.dim;
-      for (int i = tid; i < M * kKsub; i += kScanBlock)
-        s_lut[i] = lut_entry(ix, qrow, i >> 8, i & 255);
-    }
+  // the scan) unless the caller passed one in.  The converted query is staged
+  // in the (still unused) top-n buffer so every entry reads it from LDS.
+  if (!H && lut) {
+    const float4* src = reinterpret_cast<const float4*>(lut + (size_t)q * M * kKsub);
+    float4* dst = reinterpret_cast<float4*>(s_lut);
+    for (int i = tid; i < M * (kKsub / 4); i += kScanBlock) dst[i] = src[i];
   } else {
-    // half-precision variant: nearest binary16 of the float32 entry, ties to even
-    const float* qrow = Q + (size_t)q * ix.dim;
-    for (int i = tid; i < M * kKsub; i += kScanBlock)
-      s_lut[i] = __float2half_rn(lut_entry(ix, qrow, i >> 8, i & 255));
+    float* s_qv = reinterpret_cast<float*>(s_buf);  // dim floats <= cap keys
+    for (int t = tid; t < ix.dim; t += kScanBlock)
+      s_qv[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
+    __syncthreads();
+    const bool v4 = ix.dsub % 4 == 0;
+    for (int i = tid; i < M * kKsub; i += kScanBlock) {
+      const int m = i >> 8, jj = i & 255;
+      const float* qs = s_qv + m * ix.dsub;
+      const float e = v4 ? lut_entry_v4(ix, qs, m, jj) : lut_entry_conv(ix, qs, m, jj);
+      if constexpr (H)
+        s_lut[i] = __float2half_rn(e);  // half-precision variant: nearest binary16, ties to even
+      else
+        s_lut[i] = e;
+    }
   }
   __syncthreads();
 

@@ -280,13 +280,13 @@ def main():
     batched_split = (g.get_option(g.OPT_SCAN_TILE), g.get_option(g.OPT_SCAN_SPLIT))
     results = {}
     for name in names:
-        if name == "served":
-            g.set_option(g.OPT_SCAN_TILE, default_split[0])
-            g.set_option(g.OPT_SCAN_SPLIT, default_split[1])
+        if name == "served":  # the server launches with the tuned work split
+            g.set_option(g.OPT_SCAN_TILE, batched_split[0])
+            g.set_option(g.OPT_SCAN_SPLIT, batched_split[1])
             results[name] = run_served(ann, g, Qh, npq, w, k, n, args)
             continue
         fn = forms[name]
-        # plain (and served) run with the index's default work split
+        # plain runs with the index's default work split
         sp = batched_split if name.startswith("batched") else default_split
         g.set_option(g.OPT_SCAN_TILE, sp[0])
         g.set_option(g.OPT_SCAN_SPLIT, sp[1])

@@ -251,6 +251,7 @@ class Index:
     OPT_SCAN_TILE = 1
     OPT_SCAN_SPLIT = 2
     OPT_LUT_F16 = 3
+    OPT_SCAN_ORDER = 4
 
     def set_option(self, option: int, value: int):
         _check(lib().ann_set_option(self._h, int(option), int(value)))

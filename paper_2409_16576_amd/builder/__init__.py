@@ -190,11 +190,13 @@ def train_ivf(X: np.ndarray, kind: str, p: BuildParams):
     return _grid(Csub, kind), (_grid(Ctop, kind) if kind != "f32" else Ctop.astype(np.float32), off)
 
 
-def assign_lists(X: np.ndarray, C: np.ndarray, hier, p: BuildParams) -> np.ndarray:
+def assign_lists(X: np.ndarray, C: np.ndarray, hier, p: BuildParams, progress=None) -> np.ndarray:
     lib = _load()
     n, d = X.shape
     A = np.empty((n, p.R), dtype=np.int32)
     for r0 in range(0, n, ROW_CHUNK):
+        if progress and r0 and r0 % (16 * ROW_CHUNK) == 0:
+            progress(f"assigned {r0} of {n} vectors")
         r1 = min(n, r0 + ROW_CHUNK)
         Xc = _rows_f32(X, r0, r1)
         out = np.empty((r1 - r0, p.R), dtype=np.int32)
@@ -265,15 +267,21 @@ class IndexArrays:
     int_grid: bool
 
 
-def build_arrays(X: np.ndarray, kind: str, p: BuildParams) -> IndexArrays:
+def build_arrays(X: np.ndarray, kind: str, p: BuildParams, progress=None) -> IndexArrays:
+    """progress: optional callable taking a message per finished stage."""
     assert X.dtype == NP_DTYPE[kind] and X.ndim == 2
     n, d = X.shape
     if d % p.M:
         raise ValueError(f"D={d} is not a multiple of M={p.M}")
+    say = progress or (lambda _m: None)
     C, hier = train_ivf(X, kind, p)
-    A = assign_lists(X, C, hier, p)
+    say("list centroids trained")
+    A = assign_lists(X, C, hier, p, progress)
+    say("vectors assigned to lists")
     CB = train_pq(X, kind, p)
+    say("PQ codebooks trained")
     codes = encode_pq(X, CB)
+    say("vectors encoded")
     offsets, entries = lists_from_assignment(A, p.nlist)
     return IndexArrays(kind, C, CB, codes, X, offsets, entries, A, p.eps, kind != "f32")
 
@@ -315,8 +323,8 @@ def write_index(path: str, ix: IndexArrays) -> None:
     os.replace(tmp, path)
 
 
-def build_index(path: str, X: np.ndarray, kind: str, p: BuildParams) -> IndexArrays:
-    ix = build_arrays(X, kind, p)
+def build_index(path: str, X: np.ndarray, kind: str, p: BuildParams, progress=None) -> IndexArrays:
+    ix = build_arrays(X, kind, p, progress)
     write_index(path, ix)
     return ix
 

@@ -101,6 +101,7 @@ struct ann_index {
   int64_t opt_tile = 65536;
   int64_t opt_split = 16;
   int64_t opt_lut16 = 0;
+  int64_t opt_order = 0;
   // stage timing
   bool profiling = false;
   std::mutex prof_mu;
@@ -164,7 +165,7 @@ ann_status ws_ensure(Workspace* ws, const Need& n) {
   WS(w.lists, g.qc * g.np * 4);
   WS(w.np_eff, g.qc * 4);
   WS(w.lut, g.lut * 4);
-  WS(w.eq, g.qc * 8);
+  WS(w.perm, g.qc * 4);
   WS(w.sq, g.qc * 4);
   WS(w.pkeys, g.keys * 8);
   WS(w.pcount, g.items * 4);
@@ -599,6 +600,7 @@ ann_status run_chunk(ann_index* ix, Work& w, const float* q, int qc, const int32
   const DevIndex& d = ix->d;
   LaunchCfg c = cfg_for(qc, np_max, n, k, ix->opt_tile, ix->opt_split);
   c.lut16 = ix->opt_lut16 != 0;
+  c.order = ix->opt_order != 0;
   {
     StageMark m(ix, 0, st);
     HIP_TRY(launch_probe(d, q, nprobe, np_max, qc, w, nullptr, w.lists, st));
@@ -666,7 +668,7 @@ Work ann::work_carve(const DevIndex& d, int qc, int np_max, int n, void* base) {
   w.dist = static_cast<float*>(take(g.qc * g.nlist * 4));
   w.lists = static_cast<int32_t*>(take(g.qc * g.np * 4));
   w.np_eff = static_cast<int32_t*>(take(g.qc * 4));
-  w.eq = static_cast<int64_t*>(take(g.qc * 8));
+  w.perm = static_cast<int32_t*>(take(g.qc * 4));
   w.sq = static_cast<int32_t*>(take(g.qc * 4));
   w.pkeys = static_cast<uint64_t*>(take(g.keys * 8));
   w.pcount = static_cast<int32_t*>(take(g.items * 4));
@@ -691,6 +693,7 @@ int ann::get_opt(const ann_index* ix, int option, int64_t* v) {
     case ANN_OPT_SCAN_TILE: *v = ix->opt_tile; return ANN_OK;
     case ANN_OPT_SCAN_SPLIT: *v = ix->opt_split; return ANN_OK;
     case ANN_OPT_LUT_F16: *v = ix->opt_lut16; return ANN_OK;
+    case ANN_OPT_SCAN_ORDER: *v = ix->opt_order; return ANN_OK;
     default: return ANN_EINVAL;
   }
 }
@@ -850,6 +853,10 @@ extern "C" ann_status ann_set_option(ann_index* ix, int option, int64_t value) {
       if (value != 0 && value != 1) return fail(ANN_EINVAL, "lut_f16 must be 0 or 1");
       ix->opt_lut16 = value;
       return ANN_OK;
+    case ANN_OPT_SCAN_ORDER:
+      if (value != 0 && value != 1) return fail(ANN_EINVAL, "scan order must be 0 or 1");
+      ix->opt_order = value;
+      return ANN_OK;
     default:
       return fail(ANN_EINVAL, "unknown option %d", option);
   }
@@ -861,6 +868,7 @@ extern "C" ann_status ann_get_option(ann_index* ix, int option, int64_t* value) 
     case ANN_OPT_SCAN_TILE: *value = ix->opt_tile; return ANN_OK;
     case ANN_OPT_SCAN_SPLIT: *value = ix->opt_split; return ANN_OK;
     case ANN_OPT_LUT_F16: *value = ix->opt_lut16; return ANN_OK;
+    case ANN_OPT_SCAN_ORDER: *value = ix->opt_order; return ANN_OK;
     default: return fail(ANN_EINVAL, "unknown option %d", option);
   }
 }

@@ -14,6 +14,7 @@ enum DType : int { F32 = 0, U8 = 1, I8 = 2 };
 constexpr int kKsub = 256;
 constexpr int kBlock = 256;           // threads per block (all kernels but the scan)
 constexpr int kScanBlock = 1024;      // threads per block of the scan kernel
+constexpr int kMergeBlock = 1024;     // threads per block of the merge / re-rank kernels
 constexpr int kScanRT = 2;            // entries per scan thread per round
 constexpr int kMaxRerank = 4096;      // largest rerank_n
 constexpr int kMaxM = 64;             // largest number of PQ subspaces
@@ -56,7 +57,7 @@ struct Work {
   int32_t* lists = nullptr;     // [qc, np_max]
   int32_t* np_eff = nullptr;    // [qc]
   float* lut = nullptr;         // [qc, M, 256]
-  int64_t* eq = nullptr;        // [qc] entries per query
+  int32_t* perm = nullptr;      // [qc] scan order of the queries (locality order)
   int32_t* sq = nullptr;        // [qc] work items per query
   uint64_t* pkeys = nullptr;    // [qc, smax, n] partial top-n keys
   int32_t* pcount = nullptr;    // [qc, smax]
@@ -72,6 +73,7 @@ struct LaunchCfg {
   int smax;        // work items per query (max)
   int tile;        // target entries per work item
   bool lut16 = false;  // half-precision distance table in the scan
+  bool order = false;  // scan queries in locality order (by nearest list)
 };
 
 // Kernel launchers (ann_kernels.hip).  All enqueue on `st` and return hipError_t.

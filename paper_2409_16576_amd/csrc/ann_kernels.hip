@@ -680,21 +680,87 @@ __device__ __forceinline__ void scan_compact(uint64_t* s_buf, int* s_wsum, SelSc
 // back to the n best whenever it holds more than n.
 constexpr uint32_t kRunReplica = 0x80000000u;  // run start flag: replica-entry run
 
+// Runs of up to 64 probed lists laid out by one wave (lane p: list p): run
+// starts in s_rstart, exclusive entry offsets in s_pre[0..nruns], and
+// s_pre[nruns] = the query's entries; *s_nruns = nruns.
+__device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_list, int np,
+                          const uint32_t* s_bits, int segmented, uint32_t* s_rstart,
+                          int32_t* s_pre, int* s_nruns) {
+  const int lane = threadIdx.x & 63;
+  int cnt = 0, l = 0, s0 = 0, s1 = 0;
+  if (lane < np) {
+    l = s_list[lane];
+    cnt = 1;
+    if (segmented) {
+      s0 = ix.lseg[l];
+      s1 = ix.lseg[l + 1];
+      for (int s = s0; s < s1; ++s) cnt += testbit(s_bits, ix.segs[s].x) ? 0 : 1;
+    } else {
+      cnt += ix.rstart[l + 1] > ix.rstart[l] ? 1 : 0;
+    }
+  }
+  const int incl = (int)wave_incl_scan((uint32_t)cnt);
+  const int nruns = __shfl(incl, 63, 64);
+  if (lane < np) {
+    const int off = incl - cnt;
+    s_rstart[off] = (uint32_t)ix.pstart[l];
+    s_pre[off] = ix.pstart[l + 1] - ix.pstart[l];  // entry counts first
+    int r = off + 1;
+    if (segmented) {
+      for (int s = s0; s < s1; ++s) {
+        const int4 g = ix.segs[s];
+        if (!testbit(s_bits, g.x)) {
+          s_rstart[r] = (uint32_t)g.y | kRunReplica;
+          s_pre[r] = g.z - g.y;
+          ++r;
+        }
+      }
+    } else if (cnt > 1) {
+      s_rstart[r] = (uint32_t)ix.rstart[l] | kRunReplica;
+      s_pre[r] = ix.rstart[l + 1] - ix.rstart[l];
+    }
+  }
+  __threadfence_block();  // other lanes read these counts below
+  int total = 0;
+  for (int r0 = 0; r0 < nruns; r0 += 64) {
+    const int r = r0 + lane;
+    const int c = r < nruns ? s_pre[r] : 0;
+    const int in = (int)wave_incl_scan((uint32_t)c);
+    if (r < nruns) s_pre[r] = total + in - c;
+    total += __shfl(in, 63, 64);
+  }
+  if (lane == 0) {
+    s_pre[nruns] = total;
+    *s_nruns = nruns;
+  }
+}
+
 template <int W, bool TRACE, bool H>
 __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_scan(
     DevIndex ix, const int32_t* __restrict__ lists, const int32_t* __restrict__ np_eff, int np_max,
     int qc, const float* __restrict__ Q, const float* __restrict__ lut,
     int32_t* __restrict__ sq, int smax, int tile, int segmented, int max_runs, int n, int cap,
     uint64_t* __restrict__ pkeys, int32_t* __restrict__ pcount, int32_t* __restrict__ pscan,
-    int64_t t_capacity, int32_t* __restrict__ t_ids, float* __restrict__ t_adc,
+    const int32_t* __restrict__ perm, int64_t t_capacity, int32_t* __restrict__ t_ids, float* __restrict__ t_adc,
     unsigned long long* __restrict__ t_count) {
-  // Block -> (query, item) with all items of one query on the same XCD:
-  // blocks are dispatched round-robin over the 8 XCDs.
+  // Block -> (query, item).  Blocks are dispatched round-robin over the 8
+  // XCDs (each with its own L2): block b runs on XCD b % 8.  With a locality
+  // order, XCD x takes the contiguous share x of the ordered queries, so the
+  // queries running side by side on one XCD probe overlapping lists; all
+  // items of a query stay on one XCD.
   const int b = blockIdx.x;
   const int xcd = b & 7, slot = b >> 3;
-  const int q = (slot / smax) * 8 + xcd;
   const int j = slot % smax;
-  if (q >= qc) return;
+  int q;
+  if (perm) {
+    const int per = (qc + 7) / 8;
+    const int pos = xcd * per + slot / smax;
+    if (slot / smax >= per || pos >= qc) return;
+    q = perm[pos];
+  } else {
+    q = (slot / smax) * 8 + xcd;
+    if (q >= qc) return;
+  }
   const int tid = threadIdx.x;
   const int M = ix.M;
 
@@ -723,6 +789,14 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     mc->count = 0;
     mc->scanned = 0;
   }
+  // The distance table is computed here (step 1 fused into the scan) unless
+  // the caller passed one in; the converted query is staged in the (still
+  // unused) top-n buffer so every table entry reads it from LDS.
+  const bool own_table = !TRACE;
+  float* s_qv = reinterpret_cast<float*>(s_buf);  // dim floats <= cap keys
+  if (own_table)
+    for (int t = tid; t < ix.dim; t += kScanBlock)
+      s_qv[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
   __syncthreads();
   if (use_bits)
     for (int p = tid; p < np; p += kScanBlock) {
@@ -731,9 +805,39 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     }
   __syncthreads();
 
+  // Table entry i of the query (or its copy from the caller's table).
+  auto table_entry = [&](int i) {
+    if constexpr (H) {
+      const int m = i >> 8;
+      const float* qs = s_qv + m * ix.dsub;
+      const float e = ix.dsub % 4 == 0 ? lut_entry_v4(ix, qs, m, i & 255)
+                                       : lut_entry_conv(ix, qs, m, i & 255);
+      s_lut[i] = __float2half_rn(e);  // half-precision variant: nearest binary16, ties to even
+    } else if (TRACE) {  // the trace form takes the caller's table
+      s_lut[i] = lut[(size_t)q * M * kKsub + i];
+    } else {
+      const int m = i >> 8;
+      const float* qs = s_qv + m * ix.dsub;
+      s_lut[i] = ix.dsub % 4 == 0 ? lut_entry_v4(ix, qs, m, i & 255)
+                                  : lut_entry_conv(ix, qs, m, i & 255);
+    }
+  };
+
   // Runs of every probed list (slot order), then their entry prefix sums.
+  // Up to 64 probed lists: wave 0 lays the runs out (one list per lane) while
+  // the other waves build the table; otherwise the whole block does both in turn.
   int nruns = 0;
-  for (int p0 = 0; p0 < np; p0 += kScanBlock) {  // uniform trip count
+  const bool wave_setup = np <= 64;
+  if (wave_setup) {
+    if (tid < 64) {
+      runs_wave(ix, s_list, np, s_bits, segmented, s_rstart, s_pre, &s_wsum[kScanBlock / 64]);
+    } else {
+      for (int i = tid - 64; i < M * kKsub; i += kScanBlock - 64) table_entry(i);
+    }
+    __syncthreads();
+    nruns = s_wsum[kScanBlock / 64];
+  }
+  for (int p0 = 0; !wave_setup && p0 < np; p0 += kScanBlock) {  // uniform trip count
     const int p = p0 + tid;
     int cnt = 0, l = 0;
     if (p < np) {
@@ -770,8 +874,8 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     __syncthreads();
   }
   // entry counts -> exclusive offsets (runs are at most a few thousand)
-  int total = 0;
-  for (int r0 = 0; r0 < nruns; r0 += kScanBlock) {
+  int total = wave_setup ? s_pre[nruns] : 0;
+  for (int r0 = 0; !wave_setup && r0 < nruns; r0 += kScanBlock) {
     const int r = r0 + tid;
     const int c = r < nruns ? s_pre[r] : 0;
     const int off = total + block_excl_scan(c, s_wsum);
@@ -781,7 +885,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     total = s_wsum[kScanBlock / 64];
     __syncthreads();
   }
-  if (tid == 0) s_pre[nruns] = total;
+  if (!wave_setup && tid == 0) s_pre[nruns] = total;
 
   // Work items of this query: ceil(E / tile), at most smax.
   const int E = total;
@@ -789,38 +893,23 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   if (j == 0 && tid == 0) sq[q] = S;
   if (j >= S) return;
 
-  // Distance table of this query into LDS: computed here (step 1 fused into
-  // the scan) unless the caller passed one in.  The converted query is staged
-  // in the (still unused) top-n buffer so every entry reads it from LDS.
-  if (!H && lut) {
-    const float4* src = reinterpret_cast<const float4*>(lut + (size_t)q * M * kKsub);
-    float4* dst = reinterpret_cast<float4*>(s_lut);
-    for (int i = tid; i < M * (kKsub / 4); i += kScanBlock) dst[i] = src[i];
-  } else {
-    float* s_qv = reinterpret_cast<float*>(s_buf);  // dim floats <= cap keys
-    for (int t = tid; t < ix.dim; t += kScanBlock)
-      s_qv[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
+  if (!wave_setup) {
+    for (int i = tid; i < M * kKsub; i += kScanBlock) table_entry(i);
     __syncthreads();
-    const bool v4 = ix.dsub % 4 == 0;
-    for (int i = tid; i < M * kKsub; i += kScanBlock) {
-      const int m = i >> 8, jj = i & 255;
-      const float* qs = s_qv + m * ix.dsub;
-      const float e = v4 ? lut_entry_v4(ix, qs, m, jj) : lut_entry_conv(ix, qs, m, jj);
-      if constexpr (H)
-        s_lut[i] = __float2half_rn(e);  // half-precision variant: nearest binary16, ties to even
-      else
-        s_lut[i] = e;
-    }
   }
-  __syncthreads();
 
   const int e0 = (int)((int64_t)E * j / S), e1 = (int)((int64_t)E * (j + 1) / S);
   const int lane = tid & 63;
   const uint64_t lanemask = (1ull << lane) - 1ull;
   int scanned = 0;
   int cur = 0;  // run of this thread's current entry (entries only increase)
+  // The block synchronises (and may cut its buffer back) every K rounds, K
+  // as large as the buffer's slack above n allows (at most 3).
+  constexpr int kRound = kScanBlock * kScanRT;
+  const int K = TRACE ? 1 : max(1, min(3, (cap - n) / kRound));
+  int rr = 0;
 
-  for (int base = e0; base < e1; base += kScanBlock * kScanRT) {
+  for (int base = e0; base < e1; base += kRound) {
     const uint64_t thr = mc->thr;
     const uint32_t thr_hi = (uint32_t)(thr >> 32);
     int rows[kScanRT];
@@ -898,10 +987,13 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
         }
       }
     }
-    __syncthreads();
-    if constexpr (!TRACE) {
-      // cut back to the n best only when the next round might not fit
-      if (mc->count > cap - kScanBlock * kScanRT) scan_compact(s_buf, s_wsum, ss, mc, n);
+    if (++rr == K || base + kRound >= e1) {  // uniform over the block
+      rr = 0;
+      __syncthreads();
+      if constexpr (!TRACE) {
+        // cut back to the n best only when the next K rounds might not fit
+        if (mc->count > cap - K * kRound) scan_compact(s_buf, s_wsum, ss, mc, n);
+      }
     }
   }
   // candidates scored by this item
@@ -959,15 +1051,27 @@ __device__ __forceinline__ float exact_row(const DevIndex& ix, const float* __re
 }
 
 // Integer rows of 16*G bytes: G lanes per candidate, one 16-byte chunk per
-// lane, 4 candidates per lane group in flight.  Exact integer sums.
+// lane, 4 candidates per lane group in flight.  Exact integer sums: per chunk
+// ||q - x||^2 = ||q||^2 + ||x||^2 - 2 q.x with the byte dot products done by
+// v_dot4 (unsigned bytes for uint8 data, signed for int8).
 template <int G>
 __device__ void rerank_int16(const DevIndex& ix, const float* s_q, const uint64_t* s_top, int nn,
                              uint64_t* s_key2, int P) {
   const int lg = threadIdx.x % G, grp = threadIdx.x / G, ngrp = blockDim.x / G;
-  int qv[16];
-#pragma unroll
-  for (int b = 0; b < 16; ++b) qv[b] = (int)s_q[lg * 16 + b];
   const bool u8 = ix.dtype == U8;
+  uint32_t qw[4];
+  int qq = 0;
+#pragma unroll
+  for (int b4 = 0; b4 < 4; ++b4) {
+    uint32_t wv = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int v = (int)s_q[lg * 16 + 4 * b4 + b];
+      qq += v * v;
+      wv |= ((uint32_t)v & 255u) << (8 * b);
+    }
+    qw[b4] = wv;
+  }
   constexpr int U = 4;
   for (int i0 = 0; i0 < P; i0 += ngrp * U) {
     uint4 v[U];
@@ -988,15 +1092,31 @@ __device__ void rerank_int16(const DevIndex& ix, const float* s_q, const uint64_
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t w4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-      int acc = 0;
-#pragma unroll
-      for (int b = 0; b < 16; ++b) {
-        const uint32_t byte = (w4[b >> 2] >> (8 * (b & 3))) & 255u;
-        const int xv = u8 ? (int)byte : (int)(int8_t)(uint8_t)byte;
-        const int d = qv[b] - xv;
-        acc += d * d;
+      int xx, qx;
+      if (u8) {
+        uint32_t a = __builtin_amdgcn_udot4(v[u].x, v[u].x, 0u, false);
+        a = __builtin_amdgcn_udot4(v[u].y, v[u].y, a, false);
+        a = __builtin_amdgcn_udot4(v[u].z, v[u].z, a, false);
+        a = __builtin_amdgcn_udot4(v[u].w, v[u].w, a, false);
+        uint32_t c = __builtin_amdgcn_udot4(qw[0], v[u].x, 0u, false);
+        c = __builtin_amdgcn_udot4(qw[1], v[u].y, c, false);
+        c = __builtin_amdgcn_udot4(qw[2], v[u].z, c, false);
+        c = __builtin_amdgcn_udot4(qw[3], v[u].w, c, false);
+        xx = (int)a;
+        qx = (int)c;
+      } else {
+        int a = __builtin_amdgcn_sdot4((int)v[u].x, (int)v[u].x, 0, false);
+        a = __builtin_amdgcn_sdot4((int)v[u].y, (int)v[u].y, a, false);
+        a = __builtin_amdgcn_sdot4((int)v[u].z, (int)v[u].z, a, false);
+        a = __builtin_amdgcn_sdot4((int)v[u].w, (int)v[u].w, a, false);
+        int c = __builtin_amdgcn_sdot4((int)qw[0], (int)v[u].x, 0, false);
+        c = __builtin_amdgcn_sdot4((int)qw[1], (int)v[u].y, c, false);
+        c = __builtin_amdgcn_sdot4((int)qw[2], (int)v[u].z, c, false);
+        c = __builtin_amdgcn_sdot4((int)qw[3], (int)v[u].w, c, false);
+        xx = a;
+        qx = c;
       }
+      int acc = qq + xx - 2 * qx;
 #pragma unroll
       for (int d = 1; d < G; d <<= 1) acc += __shfl_xor(acc, d, 64);
       const int i = i0 + u * ngrp + grp;
@@ -1006,12 +1126,60 @@ __device__ void rerank_int16(const DevIndex& ix, const float* s_q, const uint64_
   }
 }
 
+// The kk <= 64 smallest of the distinct keys s_key[0..nn), ascending, by
+// repeated wave minima: each wave extracts the kk smallest of its share into
+// s_cand (each lane caches the minimum of its strided keys and rescans only
+// when its key is taken), then wave 0 extracts the kk smallest of those.
+// Keys of s_key are consumed (overwritten with ~0).  Results: s_cand[0..kk).
+__device__ __forceinline__ void wave_take_min(uint64_t* s_key, int i0, int i1, int kk,
+                                                  uint64_t* out) {
+  const int lane = threadIdx.x & 63;
+  uint64_t mn = ~0ull;
+  int mi = -1;
+  auto rescan = [&]() {
+    mn = ~0ull;
+    mi = -1;
+    for (int i = i0 + lane; i < i1; i += 64) {
+      const uint64_t v = s_key[i];
+      if (v < mn) {
+        mn = v;
+        mi = i;
+      }
+    }
+  };
+  rescan();
+  for (int r = 0; r < kk; ++r) {
+    uint64_t m = mn;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      const uint64_t o = __shfl_xor(m, d, 64);
+      m = o < m ? o : m;
+    }
+    if (lane == 0) out[r] = m;
+    if (m != ~0ull && mn == m) {  // keys are distinct: exactly one lane holds it
+      s_key[mi] = ~0ull;
+      rescan();
+    }
+  }
+}
+
+__device__ void block_topk_small(uint64_t* s_key, int nn, int kk, uint64_t* s_cand) {
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int chunk = (nn + nw - 1) / nw;
+  const int i0 = min(nn, w * chunk), i1 = min(nn, i0 + chunk);
+  wave_take_min(s_key, i0, i1, kk, s_cand + kk * (w + 1));
+  __syncthreads();
+  if (w == 0) wave_take_min(s_cand + kk, 0, kk * nw, kk, s_cand);
+  __syncthreads();
+}
+
 // Re-rank s_top[0..nn) (keys of (adc, id)) by exact distance and write the
 // top-k, sorted.  s_key2 holds P >= nn keys; s_top is reused for the result
-// (it needs pow2_at_least(min(k, nn)) slots).
+// (it needs pow2_at_least(min(k, nn)) slots); s_cand holds
+// 64 * (blockDim / 64 + 1) keys.
 __device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_top, int nn,
                              uint64_t* s_key2, int P, int k, int64_t* out_ids, float* out_d,
-                             SelScratch* ss, int* s_cnt) {
+                             SelScratch* ss, int* s_cnt, uint64_t* s_cand) {
   const int g16 = ix.dim % 16 == 0 ? ix.dim / 16 : 0;
   if (ix.dtype != F32 && (g16 == 1 || g16 == 2 || g16 == 4 || g16 == 8 || g16 == 16)) {
     switch (g16) {
@@ -1063,9 +1231,13 @@ __device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_t
     }
   }
   __syncthreads();
-  // the kk smallest keys: select the kk-th, collect, sort kk
+  // the kk smallest keys, ascending
   const int kk = min(k, nn);
-  if (kk > 0) {
+  if (kk > 0 && kk <= 64) {
+    block_topk_small(s_key2, nn, kk, s_cand);
+    for (int i = threadIdx.x; i < kk; i += blockDim.x) s_top[i] = s_cand[i];
+    __syncthreads();
+  } else if (kk > 0) {  // select the kk-th, collect, sort kk
     const int pk = pow2_at_least(kk);
     const uint64_t K = kk == nn ? ~0ull : block_kth([&](int i) { return s_key2[i]; }, nn, kk, ss);
     if (threadIdx.x == 0) *s_cnt = 0;
@@ -1089,7 +1261,7 @@ __device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_t
 }
 
 struct MergeLayout {
-  size_t keys, top, key2, q, sel, misc, total;
+  size_t keys, top, key2, q, sel, cand, misc, total;
 };
 
 __host__ __device__ inline MergeLayout merge_layout(int smax, int n, int dim) {
@@ -1101,12 +1273,14 @@ __host__ __device__ inline MergeLayout merge_layout(int smax, int n, int dim) {
   L.top = o; o += (size_t)P * 8;
   L.q = o; o += (size_t)dim * 4; o = align_up(o, 16);
   L.sel = o; o += sizeof(SelScratch); o = align_up(o, 16);
+  L.cand = o; o += (size_t)64 * (kMergeBlock / 64 + 1) * 8;
   L.misc = o; o += 16 + 4 * 17;
   L.total = align_up(o, 16);
   return L;
 }
 
-__global__ __launch_bounds__(kBlock) void k_merge(
+template <int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_merge(
     DevIndex ix, const float* __restrict__ Q, int qc, const int32_t* __restrict__ sq, int smax,
     int n, int k, const uint64_t* __restrict__ pkeys, const int32_t* __restrict__ pcount,
     const int32_t* __restrict__ pscan, int32_t* __restrict__ topn_ids, float* __restrict__ topn_adc,
@@ -1118,12 +1292,13 @@ __global__ __launch_bounds__(kBlock) void k_merge(
   uint64_t* s_key2 = reinterpret_cast<uint64_t*>(smem + L.key2);
   float* s_q = reinterpret_cast<float*>(smem + L.q);
   SelScratch* ss = reinterpret_cast<SelScratch*>(smem + L.sel);
+  uint64_t* s_cand = reinterpret_cast<uint64_t*>(smem + L.cand);
   int* s_cnt = reinterpret_cast<int*>(smem + L.misc);
   int* s_off = s_cnt + 1;  // [smax + 1] (smax <= 16)
   const int q = blockIdx.x, tid = threadIdx.x;
   const int S = sq[q];
   const int P = pow2_at_least(n);
-  for (int t = tid; t < ix.dim; t += kBlock) s_q[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
+  for (int t = tid; t < ix.dim; t += BS) s_q[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
   if (tid == 0) {
     int acc = 0;
     int64_t sc = 0;
@@ -1141,14 +1316,14 @@ __global__ __launch_bounds__(kBlock) void k_merge(
   for (int j = 0; j < S; ++j) {
     const int c = s_off[j + 1] - s_off[j];
     const uint64_t* src = pkeys + ((size_t)q * smax + j) * n;
-    for (int i = tid; i < c; i += kBlock) s_keys[s_off[j] + i] = src[i];
+    for (int i = tid; i < c; i += BS) s_keys[s_off[j] + i] = src[i];
   }
   const int nn = min(n, total);
-  for (int i = nn + tid; i < P; i += kBlock) s_top[i] = ~0ull;
+  for (int i = nn + tid; i < P; i += BS) s_top[i] = ~0ull;
   __syncthreads();
   if (total > n) {
     const uint64_t K = block_kth([&](int i) { return s_keys[i]; }, total, n, ss);
-    for (int i = tid; i < total; i += kBlock) {
+    for (int i = tid; i < total; i += BS) {
       const uint64_t key = s_keys[i];
       if (key <= K) {
         const int pos = atomicAdd(s_cnt, 1);
@@ -1156,12 +1331,12 @@ __global__ __launch_bounds__(kBlock) void k_merge(
       }
     }
   } else {
-    for (int i = tid; i < total; i += kBlock) s_top[i] = s_keys[i];
+    for (int i = tid; i < total; i += BS) s_top[i] = s_keys[i];
   }
   __syncthreads();
   if (topn_ids) {
     block_bitonic(s_top, P);
-    for (int i = tid; i < n; i += kBlock) {
+    for (int i = tid; i < n; i += BS) {
       const bool v = i < nn;
       topn_ids[(size_t)q * n + i] = v ? (int32_t)(uint32_t)s_top[i] : -1;
       topn_adc[(size_t)q * n + i] = v ? unord32((uint32_t)(s_top[i] >> 32)) : INFINITY;
@@ -1170,12 +1345,13 @@ __global__ __launch_bounds__(kBlock) void k_merge(
   if (out_ids) {
     __syncthreads();  // s_key2 aliases s_keys
     rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k,
-                 out_dists + (size_t)q * k, ss, s_cnt);
+                 out_dists + (size_t)q * k, ss, s_cnt, s_cand);
   }
 }
 
 // Step 8 for caller-provided candidates.
-__global__ __launch_bounds__(kBlock) void k_rerank_only(DevIndex ix, const float* __restrict__ Q,
+template <int BS>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_rerank_only(DevIndex ix, const float* __restrict__ Q,
                                                          const int32_t* __restrict__ cand, int n,
                                                          int k, int64_t* __restrict__ out_ids,
                                                          float* __restrict__ out_dists) {
@@ -1183,13 +1359,14 @@ __global__ __launch_bounds__(kBlock) void k_rerank_only(DevIndex ix, const float
   const int P = pow2_at_least(n);
   uint64_t* s_top = reinterpret_cast<uint64_t*>(smem);
   uint64_t* s_key2 = s_top + P;
-  float* s_q = reinterpret_cast<float*>(s_key2 + P);
+  uint64_t* s_cand = s_key2 + P;  // 64 * (kMergeBlock / 64 + 1)
+  float* s_q = reinterpret_cast<float*>(s_cand + 64 * (kMergeBlock / 64 + 1));
   int* s_cnt = reinterpret_cast<int*>(s_q + ix.dim);
   const int q = blockIdx.x, tid = threadIdx.x;
-  for (int t = tid; t < ix.dim; t += kBlock) s_q[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
+  for (int t = tid; t < ix.dim; t += BS) s_q[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
   if (tid == 0) *s_cnt = 0;
   __syncthreads();
-  for (int i = tid; i < n; i += kBlock) {
+  for (int i = tid; i < n; i += BS) {
     const int id = cand[(size_t)q * n + i];
     if (id >= 0 && id < ix.n) s_top[atomicAdd(s_cnt, 1)] = (uint32_t)id;
   }
@@ -1197,7 +1374,30 @@ __global__ __launch_bounds__(kBlock) void k_rerank_only(DevIndex ix, const float
   const int nn = *s_cnt;
   __shared__ SelScratch ss;
   rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k, out_dists + (size_t)q * k,
-               &ss, s_cnt);
+               &ss, s_cnt, s_cand);
+}
+
+// Locality order of a chunk's queries: ascending (nearest probed list, query).
+// One block; bitonic sort of 64-bit keys in LDS (qc <= kOrderMax).
+constexpr int kOrderMax = 16384;
+
+__global__ __launch_bounds__(kScanBlock) void k_order(const int32_t* __restrict__ lists,
+                                                       const int32_t* __restrict__ np_eff,
+                                                       int np_max, int qc,
+                                                       int32_t* __restrict__ perm) {
+  extern __shared__ __align__(16) uint64_t s_key[];
+  const int P = pow2_at_least(qc);
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    uint64_t key = ~0ull;
+    if (i < qc) {
+      const uint32_t l = np_eff[i] > 0 ? (uint32_t)lists[(size_t)i * np_max] : 0xffffffffu;
+      key = ((uint64_t)l << 32) | (uint32_t)i;
+    }
+    s_key[i] = key;
+  }
+  __syncthreads();
+  block_bitonic(s_key, P);
+  for (int i = threadIdx.x; i < qc; i += blockDim.x) perm[i] = (int32_t)(uint32_t)s_key[i];
 }
 
 // Segmented replica runs when their LDS bound stays small.
@@ -1215,8 +1415,9 @@ template <int W>
 hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t* np_eff,
                          int np_max, int qc, const float* Q, const float* lut, int32_t* sq,
                          int smax, int tile, int n, int cap, uint64_t* pkeys, int32_t* pcount,
-                         int32_t* pscan, bool trace, bool lut16, int64_t t_capacity,
-                         int32_t* t_ids, float* t_adc, int64_t* t_count, hipStream_t st) {
+                         int32_t* pscan, const int32_t* perm, bool trace, bool lut16,
+                         int64_t t_capacity, int32_t* t_ids, float* t_adc, int64_t* t_count,
+                         hipStream_t st) {
   const int seg = scan_segmented(ix, np_max) ? 1 : 0;
   const int max_runs = scan_runs(ix, np_max);
   const ScanLayout L =
@@ -1229,22 +1430,24 @@ hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
     hipLaunchKernelGGL(kern, grid, dim3(kScanBlock), L.total, st, ix, lists, np_eff, np_max, qc,
                        Q, lut, sq, smax, tile, seg, max_runs, n, cap, pkeys, pcount, pscan,
-                       t_capacity, t_ids, t_adc, reinterpret_cast<unsigned long long*>(t_count));
+                       perm, t_capacity, t_ids, t_adc,
+                       reinterpret_cast<unsigned long long*>(t_count));
   } else {
     auto kern = lut16 ? k_scan<W, false, true> : k_scan<W, false, false>;
     if (L.total > 65536)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
     hipLaunchKernelGGL(kern, grid, dim3(kScanBlock), L.total, st, ix, lists, np_eff, np_max, qc,
                        Q, lut, sq, smax, tile, seg, max_runs, n, cap, pkeys, pcount, pscan,
-                       t_capacity, t_ids, t_adc, reinterpret_cast<unsigned long long*>(t_count));
+                       perm, t_capacity, t_ids, t_adc,
+                       reinterpret_cast<unsigned long long*>(t_count));
   }
   return hipGetLastError();
 }
 
 using ScanFn = hipError_t (*)(const DevIndex&, const int32_t*, const int32_t*, int, int,
                               const float*, const float*, int32_t*, int, int, int, int, uint64_t*,
-                              int32_t*, int32_t*, bool, bool, int64_t, int32_t*, float*, int64_t*,
-                              hipStream_t);
+                              int32_t*, int32_t*, const int32_t*, bool, bool, int64_t, int32_t*,
+                              float*, int64_t*, hipStream_t);
 
 template <int... Ws>
 constexpr ScanFn scan_table_entry(int w, std::integer_sequence<int, Ws...>) {
@@ -1321,8 +1524,20 @@ hipError_t launch_scan(const DevIndex& ix, const int32_t* lists, const int32_t* 
   if (c.qc <= 0) return hipSuccess;
   const int W = (ix.M + 3) / 4;
   const int cap = scan_cap(ix, c.np_max, c.n, c.lut16);
+  const int32_t* perm = nullptr;
+  if (c.order && c.qc > 8 && c.qc <= kOrderMax) {
+    const int P = pow2_at_least(c.qc);
+    const size_t lds = (size_t)P * 8;
+    if (lds > 65536)
+      (void)hipFuncSetAttribute((const void*)k_order, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+    hipLaunchKernelGGL(k_order, dim3(1), dim3(kScanBlock), lds, st, lists, np_eff, c.np_max, c.qc,
+                       w.perm);
+    perm = w.perm;
+  }
   return scan_fn(W)(ix, lists, np_eff, c.np_max, c.qc, q, nullptr, w.sq, c.smax, c.tile, c.n, cap,
-                    w.pkeys, w.pcount, w.pscan, false, c.lut16, 0, nullptr, nullptr, nullptr, st);
+                    w.pkeys, w.pcount, w.pscan, perm, false, c.lut16, 0, nullptr, nullptr, nullptr,
+                    st);
 }
 
 hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const float* lut, int qc,
@@ -1335,7 +1550,8 @@ hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const flo
   hipLaunchKernelGGL(k_zero_i64, dim3((qc + 255) / 256), dim3(256), 0, st, out_count, qc);
   const int W = (ix.M + 3) / 4;
   return scan_fn(W)(ix, lists, w.np_eff, np_max, qc, nullptr, lut, w.sq, smax, tile, 1, 1, nullptr,
-                    nullptr, nullptr, true, false, capacity, out_ids, out_adc, out_count, st);
+                    nullptr, nullptr, nullptr, true, false, capacity, out_ids, out_adc, out_count,
+                    st);
 }
 
 hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,
@@ -1343,9 +1559,12 @@ hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, 
                         float* out_dists, hipStream_t st) {
   if (c.qc <= 0) return hipSuccess;
   const MergeLayout L = merge_layout(c.smax, c.n, ix.dim);
+  // more threads only pay off when there are many candidates to re-rank
+  const bool big = c.n > 512;
+  auto kern = big ? k_merge<kMergeBlock> : k_merge<256>;
   if (L.total > 65536)
-    (void)hipFuncSetAttribute((const void*)k_merge, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
-  hipLaunchKernelGGL(k_merge, dim3(c.qc), dim3(kBlock), L.total, st, ix, q, c.qc, w.sq, c.smax,
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
+  hipLaunchKernelGGL(kern, dim3(c.qc), dim3(big ? kMergeBlock : 256), L.total, st, ix, q, c.qc, w.sq, c.smax,
                      c.n, c.k, w.pkeys, w.pcount, w.pscan, topn_ids, topn_adc, ncand, out_ids,
                      out_dists);
   return hipGetLastError();
@@ -1355,8 +1574,14 @@ hipError_t launch_rerank_only(const DevIndex& ix, const float* q, const int32_t*
                               int n, int k, int64_t* out_ids, float* out_dists, hipStream_t st) {
   if (qc <= 0) return hipSuccess;
   const int P = pow2_at_least(n);
-  const size_t lds = (size_t)P * 16 + (size_t)ix.dim * 4 + 16;
-  hipLaunchKernelGGL(k_rerank_only, dim3(qc), dim3(kBlock), lds, st, ix, q, cand, n, k, out_ids,
+  const size_t lds = (size_t)P * 16 + (size_t)64 * (kMergeBlock / 64 + 1) * 8 +
+                     (size_t)ix.dim * 4 + 16;
+  const bool big = n > 512;
+  auto kern = big ? k_rerank_only<kMergeBlock> : k_rerank_only<256>;
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  hipLaunchKernelGGL(kern, dim3(qc), dim3(big ? kMergeBlock : 256), lds, st, ix, q, cand, n, k, out_ids,
                      out_dists);
   return hipGetLastError();
 }

@@ -60,7 +60,7 @@ IVF_U8_10M = Workload("ivf_u8_10m", 2, 10_000_000, 128, "u8", 4096, 0.0, 255.0, 
 # 8192 lists; PQ 24 x 256; per-query nprobe U{8..128}.
 ZIPF_F32_5M = Workload("zipf_f32_5m", 3, 5_000_000, 96, "f32", 2048, 0.0, 0.0, 0.3,
                        8192, 24, 16_384, (8, 128), 100, unit_norm=True, zipf_s=1.1,
-                       sub_centres=4, sub_sigma=0.5, kmeans_iters=5)
+                       sub_centres=4, sub_sigma=0.5, kmeans_iters=5, rerank_n_op=2400)
 # 100M x 100-d int8, 8192 centres U[-128,127]; 65536 lists; PQ 50 x 256.
 SERVE_I8_100M = Workload("serve_i8_100m", 5, 100_000_000, 100, "i8", 8192, -128.0, 127.0,
                          10.0, 65536, 50, 10_000, 64, 100)
@@ -159,8 +159,13 @@ def ensure_index(w: Workload, verbose: bool = False) -> str:
         t0 = time.time()
         X = base_vectors(w)
         t1 = time.time()
-        build_index(path, X, w.kind, build_params(w))
+        import sys
+        say = None
+        if verbose:  # progress goes to stderr: stdout carries results only
+            say = lambda m: print(f"[index] {w.name}: {m} ({time.time() - t0:.0f}s)",  # noqa: E731
+                                  file=sys.stderr, flush=True)
+        build_index(path, X, w.kind, build_params(w), progress=say)
         if verbose:
             print(f"[index] {w.name}: data {t1 - t0:.1f}s build {time.time() - t1:.1f}s -> {path}",
-                  flush=True)
+                  file=sys.stderr, flush=True)
     return path

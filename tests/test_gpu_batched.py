@@ -124,3 +124,50 @@ def test_graph_errors(ann, setup):
         ann.Graph(g, Q[:0], 4, 10, 64)  # empty batch
     with pytest.raises(ann.AnnError):
         ann.autotune(g, Q, 4, 10, 64, reps=0)
+
+
+@pytest.fixture(scope="module")
+def zipf(orc, ann):
+    """A small copy of the skewed batched-form workload: unit-norm float32,
+    Zipf(1.1) list sizes (one list holds a large share of the vectors),
+    per-query nprobe drawn from U{8..128} (clamped to the 64 lists)."""
+    from paper_2409_16576_amd import workloads
+    w = workloads.scaled(workloads.ZIPF_F32_5M, n=40000, nlist=64, n_centres=16, nq=150)
+    path = workloads.ensure_index(w)
+    ix = orc.read_index(path)
+    g = ann.Index(path, 0)
+    yield ix, g, workloads.queries(w), workloads.nprobe_per_query(w)
+    g.close()
+
+
+@pytest.mark.parametrize("lut16", [0, 1])
+def test_skewed_lists_split_graph_and_tuning(ann, zipf, orc, lut16):
+    ix, g, Qh, npq = zipf
+    sizes = np.diff(ix.offsets)
+    assert sizes.max() > 8 * np.median(sizes)  # the skew the form is for
+    Q = torch.from_numpy(Qh).cuda()
+    NP = torch.from_numpy(npq).cuda()
+    k, n = 10, 400
+    r = orc.search(ix, Qh, npq, k, n, lut_f16=bool(lut16))
+    g.set_option(g.OPT_LUT_F16, lut16)
+    try:
+        for tile, split in ((512, 16), (4096, 4), (1 << 30, 1)):
+            _say("zipf", lut16, tile, split)
+            g.set_option(g.OPT_SCAN_TILE, tile)
+            g.set_option(g.OPT_SCAN_SPLIT, split)
+            ids, d = g.search(Q, NP, k, n)
+            assert np.array_equal(ids.cpu().numpy(), r.ids) and np.array_equal(d.cpu().numpy(), r.dists)
+        ann.autotune(g, Q, NP, k, n, reps=1)
+        gr = ann.Graph(g, Q, NP, k, n)
+        try:
+            for _ in range(3):
+                ids, d = gr.launch()
+                torch.cuda.synchronize()
+                assert np.array_equal(ids.cpu().numpy(), r.ids)
+                assert np.array_equal(d.cpu().numpy(), r.dists)
+        finally:
+            gr.close()
+    finally:
+        g.set_option(g.OPT_LUT_F16, 0)
+        g.set_option(g.OPT_SCAN_TILE, 65536)
+        g.set_option(g.OPT_SCAN_SPLIT, 16)

@@ -25,6 +25,7 @@
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 #include <utility>
 
@@ -1377,6 +1378,278 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
                &ss, s_cnt, s_cand);
 }
 
+// Step 2 on integer-grid indexes without materialising the distance matrix:
+// a block takes kFQ = 8 queries (one 16-row MFMA tile, rows 8..15 zero) through
+// every list tile of 256 lists (int8 MFMA, same exact arithmetic as
+// k_probe_mfma), keeps each query's keys
+// (ordered distance bits, list) below its running threshold in an LDS buffer,
+// and cuts a buffer back to its NP smallest keys when another tile might not
+// fit.  At the end the NP smallest of each query come out ascending.
+constexpr int kFQ = 8;
+constexpr int kFTile = 256;
+
+template <int NP>
+__host__ __device__ constexpr int fused_cap() { return NP + kFTile + 128; }
+
+// The want-th smallest (1-based) of the distinct keys s_key[0..c), found by
+// one wave: MSD radix over 8-bit digits below the bits all keys share, with a
+// private 256-bin histogram (hist), stopping once the digit bucket holds one
+// key.  LDS traffic of the wave is ordered with workgroup fences.
+__device__ uint64_t wave_kth(const uint64_t* s_key, int c, int want, uint32_t* hist) {
+  const int lane = threadIdx.x & 63;
+  uint64_t lo = ~0ull, hi = 0ull;
+  for (int i = lane; i < c; i += 64) {
+    const uint64_t k = s_key[i];
+    lo = k < lo ? k : lo;
+    hi = k > hi ? k : hi;
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    const uint64_t a = __shfl_xor(lo, d, 64), b = __shfl_xor(hi, d, 64);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+  }
+  const uint64_t diff = lo ^ hi;
+  if (diff == 0) return lo;
+  const int top = ((63 - __clzll((long long)diff)) / 8) * 8;
+  uint64_t mask = top >= 56 ? 0ull : ~((1ull << (top + 8)) - 1ull);
+  uint64_t prefix = lo & mask;
+  for (int shift = top; shift >= 0; shift -= 8) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) hist[4 * lane + b] = 0u;
+    __threadfence_block();
+    for (int i = lane; i < c; i += 64) {
+      const uint64_t k = s_key[i];
+      if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+    }
+    __threadfence_block();
+    const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1];
+    const uint32_t h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+    const uint32_t sum = h0 + h1 + h2 + h3;
+    const uint32_t incl = wave_incl_scan(sum);
+    const uint32_t excl = incl - sum;
+    const bool mine = excl < (uint32_t)want && (uint32_t)want <= incl;
+    uint32_t r = (uint32_t)want - excl, hb = h0;
+    int b = 4 * lane;
+    if (r > h0) {
+      r -= h0; b += 1; hb = h1;
+      if (r > h1) {
+        r -= h1; b += 1; hb = h2;
+        if (r > h2) { r -= h2; b += 1; hb = h3; }
+      }
+    }
+    const int owner = __ffsll((unsigned long long)__ballot(mine)) - 1;
+    want = __shfl((int)r, owner, 64);
+    b = __shfl(b, owner, 64);
+    hb = (uint32_t)__shfl((int)hb, owner, 64);
+    prefix |= (uint64_t)b << shift;
+    mask |= 255ull << shift;
+    if (hb == 1u) break;
+  }
+  uint64_t found = 0;
+  for (int i = lane; i < c; i += 64) {
+    const uint64_t k = s_key[i];
+    if ((k & mask) == prefix) found = k;
+  }
+  // one key matches: the largest over lanes is it (others hold 0)
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    const uint64_t o = __shfl_xor(found, d, 64);
+    found = o > found ? o : found;
+  }
+  return found;
+}
+
+// Keys of s_key[0..c) that are <= K, appended to out by one wave; returns
+// how many.
+__device__ int wave_collect_le(const uint64_t* s_key, int c, uint64_t K, uint64_t* out) {
+  const int lane = threadIdx.x & 63;
+  int n = 0;
+  for (int i0 = 0; i0 < c; i0 += 64) {
+    const int i = i0 + lane;
+    const uint64_t k = i < c ? s_key[i] : ~0ull;
+    const bool take = i < c && k <= K;
+    const uint64_t m = __ballot(take);
+    if (take) out[n + __popcll(m & ((1ull << lane) - 1ull))] = k;
+    n += __popcll(m);
+  }
+  __threadfence_block();
+  return n;
+}
+
+// Ascending bitonic sort of s[0..P) (P a power of two, <= 4096) by one wave.
+__device__ void wave_bitonic(uint64_t* s, int P) {
+  const int lane = threadIdx.x & 63;
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < P; i += 64) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = s[i], b = s[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            s[i] = b;
+            s[ixj] = a;
+          }
+        }
+      }
+      __threadfence_block();
+    }
+  }
+}
+
+template <int NP, int KS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_probe_fused(DevIndex ix, const float* __restrict__ Q,
+                                                         int qc, const int32_t* __restrict__ nprobe,
+                                                         int np_max, int32_t* __restrict__ lists,
+                                                         float* __restrict__ out_d,
+                                                         int32_t* __restrict__ np_eff) {
+  constexpr int CAP = fused_cap<NP>();
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* s_buf = reinterpret_cast<uint64_t*>(smem);        // [kFQ][CAP]
+  uint64_t* s_tmp = s_buf + kFQ * CAP;                         // [4 waves][NP]
+  uint64_t* s_thr = s_tmp + 4 * NP;                            // [kFQ]
+  uint32_t* s_hist = reinterpret_cast<uint32_t*>(s_thr + kFQ); // [4 waves][256]
+  int* s_cnt = reinterpret_cast<int*>(s_hist + 4 * 256);      // [kFQ]
+  int* s_qn = s_cnt + kFQ;                                     // [kFQ]
+  int8_t* s_q8 = reinterpret_cast<int8_t*>(s_qn + kFQ);       // [16][dim_pad]
+  const int Dp = ix.dim_pad, D = ix.dim;
+  const int q0 = blockIdx.x * kFQ;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = tid; i < 16 * Dp; i += kBlock) {
+    const int qi = i / Dp, qq = q0 + qi, t = i % Dp;
+    int v = 0;
+    if (qi < kFQ && qq < qc && t < D) v = (int)conv_query(Q[(size_t)qq * D + t], ix.dtype) - ix.shift8;
+    s_q8[i] = (int8_t)v;
+  }
+  if (tid < kFQ) {
+    s_thr[tid] = ~0ull;
+    s_cnt[tid] = 0;
+  }
+  __syncthreads();
+  if (tid < kFQ) {
+    int sum = 0;
+    for (int t = 0; t < Dp; ++t) {
+      const int v = s_q8[tid * Dp + t];
+      sum += v * v;
+    }
+    s_qn[tid] = sum;
+  }
+  __syncthreads();
+  const int r16 = lane & 15, g = lane >> 4;
+  int qn[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) qn[r] = 4 * g + r < kFQ ? s_qn[4 * g + r] : 0;
+  const bool rows = 4 * g < kFQ;  // this lane's output rows are real queries
+  // KS = dim_pad / 64 K-steps.  The query fragments stay in registers; the
+  // centroid fragments of the next list tile are loaded while this one is
+  // being filtered (software pipelining across tiles).
+  v4i_t fa[KS];
+#pragma unroll
+  for (int k = 0; k < KS; ++k)
+    fa[k] = *reinterpret_cast<const v4i_t*>(s_q8 + r16 * Dp + 64 * k + 16 * g);
+  v4i_t fn[KS][4];
+  auto load_tile = [&](int t0) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int l = t0 + w * 64 + b * 16 + r16;
+#pragma unroll
+      for (int k = 0; k < KS; ++k)
+        fn[k][b] = l < ix.nlist
+                       ? *reinterpret_cast<const v4i_t*>(ix.cent8 + (size_t)l * Dp + 64 * k + 16 * g)
+                       : v4i_t{0, 0, 0, 0};
+    }
+  };
+  load_tile(0);
+  for (int t0 = 0; t0 < ix.nlist; t0 += kFTile) {
+    const int l0 = t0 + w * 64;
+    v4i_t fb[KS][4];
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) fb[k][b] = fn[k][b];
+    if (t0 + kFTile < ix.nlist) load_tile(t0 + kFTile);
+    v4i_t acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = v4i_t{0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc[b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[k], fb[k][b], acc[b], 0, 0, 0);
+    // thresholds as (distance, list) integer pairs: the distances are exact
+    // non-negative integers, so comparing them as ints orders like the keys
+    int dT[4], lT[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint64_t t = rows ? s_thr[4 * g + r] : 0ull;
+      dT[r] = t == ~0ull ? INT_MAX : (int)unord32((uint32_t)(t >> 32));
+      lT[r] = t == ~0ull ? INT_MAX : (int)(uint32_t)t;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int l = l0 + b * 16 + r16;  // output column = lane % 16
+      if (!rows || l >= ix.nlist) continue;
+      const int cn = ix.cnorm8[l];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {  // output row = 4 * (lane / 16) + r
+        const int d = qn[r] + cn - 2 * acc[b][r];
+        if (d < dT[r] || (d == dT[r] && l < lT[r])) {
+          const int m = 4 * g + r;
+          s_buf[m * CAP + atomicAdd(&s_cnt[m], 1)] =
+              ((uint64_t)ord32((float)d) << 32) | (uint32_t)l;
+        }
+      }
+    }
+    __syncthreads();
+    // cut back the buffers that might not take another tile
+    for (int m = w; m < kFQ; m += 4) {
+      const int c = s_cnt[m];
+      if (c > CAP - kFTile) {
+        const uint64_t K = wave_kth(s_buf + m * CAP, c, NP, s_hist + w * 256);
+        wave_collect_le(s_buf + m * CAP, c, K, s_tmp + w * NP);  // exactly NP keys
+        for (int i = lane; i < NP; i += 64) s_buf[m * CAP + i] = s_tmp[w * NP + i];
+        if (lane == 0) {
+          s_cnt[m] = NP;
+          s_thr[m] = K;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // the np smallest of each query, ascending
+  for (int m = w; m < kFQ; m += 4) {
+    const int q = q0 + m;
+    if (q >= qc) continue;
+    int np = nprobe ? nprobe[q] : np_max;
+    np = max(0, min(np, min(np_max, ix.nlist)));
+    const int c = s_cnt[m];
+    const int kk = min(NP, c);
+    uint64_t* t = s_tmp + w * NP;
+    if (kk > 0) {
+      const uint64_t K = kk == c ? ~0ull : wave_kth(s_buf + m * CAP, c, kk, s_hist + w * 256);
+      const int got = wave_collect_le(s_buf + m * CAP, c, K, t);
+      const int P = pow2_at_least(got);
+      for (int i = got + lane; i < P; i += 64) t[i] = ~0ull;
+      __threadfence_block();
+      wave_bitonic(t, P);
+    }
+    for (int p = lane; p < np_max; p += 64) {
+      const bool v = p < np;
+      const uint64_t key = v ? s_tmp[w * NP + p] : ~0ull;
+      lists[(size_t)q * np_max + p] = v ? (int32_t)(uint32_t)key : -1;
+      if (out_d) out_d[(size_t)q * np_max + p] = v ? unord32((uint32_t)(key >> 32)) : INFINITY;
+    }
+    if (lane == 0) np_eff[q] = np;
+  }
+}
+
+template <int NP>
+size_t fused_lds(const DevIndex& ix) {
+  return (size_t)kFQ * fused_cap<NP>() * 8 + (size_t)4 * NP * 8 + kFQ * 8 + 4 * 256 * 4 +
+         kFQ * 8 + (size_t)16 * ix.dim_pad;
+}
+
 // Locality order of a chunk's queries: ascending (nearest probed list, query).
 // One block; bitonic sort of 64-bit keys in LDS (qc <= kOrderMax).
 constexpr int kOrderMax = 16384;
@@ -1492,6 +1765,19 @@ hipError_t launch_probe(const DevIndex& ix, const float* q, const int32_t* nprob
                         int qc, Work& w, float* out_dists_opt, int32_t* out_lists,
                         hipStream_t st) {
   if (qc <= 0) return hipSuccess;
+  if (ix.cent8 && np_max <= 128 && ix.dim_pad <= 128) {
+    // integer grid: fused distances + selection, no distance matrix in HBM
+    const dim3 g((qc + kFQ - 1) / kFQ);
+    auto kern = np_max <= 64 ? (ix.dim_pad == 64 ? k_probe_fused<64, 1> : k_probe_fused<64, 2>)
+                             : (ix.dim_pad == 64 ? k_probe_fused<128, 1> : k_probe_fused<128, 2>);
+    const size_t lds = np_max <= 64 ? fused_lds<64>(ix) : fused_lds<128>(ix);
+    if (lds > 65536)
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+    hipLaunchKernelGGL(kern, g, dim3(kBlock), lds, st, ix, q, qc, nprobe, np_max, out_lists,
+                       out_dists_opt, w.np_eff);
+    return hipGetLastError();
+  }
   if (ix.cent8) {
     const dim3 g((ix.nlist + kPN - 1) / kPN, (qc + kPM - 1) / kPM);
     const size_t lds = (size_t)kPM * ix.dim_pad + kPM * 4;

@@ -1387,6 +1387,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 // fit.  At the end the NP smallest of each query come out ascending.
 constexpr int kFQ = 8;
 constexpr int kFTile = 256;
+constexpr int kFusedMinQueries = 4096;
 
 template <int NP>
 __host__ __device__ constexpr int fused_cap() { return NP + kFTile + 128; }
@@ -1765,8 +1766,10 @@ hipError_t launch_probe(const DevIndex& ix, const float* q, const int32_t* nprob
                         int qc, Work& w, float* out_dists_opt, int32_t* out_lists,
                         hipStream_t st) {
   if (qc <= 0) return hipSuccess;
-  if (ix.cent8 && np_max <= 128 && ix.dim_pad <= 128) {
-    // integer grid: fused distances + selection, no distance matrix in HBM
+  if (ix.cent8 && np_max <= 128 && ix.dim_pad <= 128 && qc >= kFusedMinQueries) {
+    // integer grid, large batch: fused distances + selection, no distance
+    // matrix in HBM (a block walks all lists for its 8 queries, so small
+    // batches would leave most of the GPU idle: they take the two-kernel path)
     const dim3 g((qc + kFQ - 1) / kFQ);
     auto kern = np_max <= 64 ? (ix.dim_pad == 64 ? k_probe_fused<64, 1> : k_probe_fused<64, 2>)
                              : (ix.dim_pad == 64 ? k_probe_fused<128, 1> : k_probe_fused<128, 2>);

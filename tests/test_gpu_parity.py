@@ -104,6 +104,32 @@ def test_probe_bit_exact(name, indexes, gpu_index, orc):
     assert np.array_equal(lists.cpu().numpy(), ol)
 
 
+@pytest.mark.parametrize("name", ["u8", "i8"])
+@pytest.mark.parametrize("npmax", [40, 100])
+def test_probe_large_batch_bit_exact(name, npmax, indexes, gpu_index, orc):
+    """Batches of >= 4096 queries on integer-grid indexes take the fused
+    distance + selection kernel; lists and distances stay bit-exact."""
+    ix, _, Q = indexes[name]
+    g = gpu_index(name)
+    rng = np.random.default_rng(17)
+    lo, hi = (0, 255) if name == "u8" else (-128, 127)
+    Qb = np.clip(np.rint(np.tile(Q, (4500 // len(Q) + 1, 1))[:4500]
+                         + rng.normal(0, 20, size=(4500, Q.shape[1]))), lo, hi).astype(np.float32)
+    npr = rng.integers(0, npmax + 1, size=len(Qb)).astype(np.int32)
+    npr[:3] = (0, npmax, ix.nlist + 5)
+    _say("probe large batch", name, npmax)
+    lists, d = g.probe(_cuda(Qb), _cuda(np.minimum(npr, npmax)))
+    torch.cuda.synchronize()
+    ol, od = orc.probe(ix, Qb, np.minimum(npr, npmax))
+    w = ol.shape[1]
+    assert np.array_equal(lists.cpu().numpy()[:, :w], ol)
+    assert np.array_equal(d.cpu().numpy()[:, :w], od)
+    assert (lists.cpu().numpy()[:, w:] == -1).all()
+    ids, dd = g.search(_cuda(Qb), _cuda(np.minimum(npr, npmax)), 10, 100)
+    r = orc.search(ix, Qb, np.minimum(npr, npmax), 10, 100)
+    assert np.array_equal(ids.cpu().numpy(), r.ids) and np.array_equal(dd.cpu().numpy(), r.dists)
+
+
 @pytest.mark.parametrize("name", KINDS)
 def test_lut_bit_exact(name, indexes, gpu_index, orc):
     ix, _, Q = indexes[name]

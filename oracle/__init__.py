@@ -67,7 +67,7 @@ def _load():
         lib.orc_adc.argtypes = [P, P, P, P, i64, P, P]
         lib.orc_exact.argtypes = [P, P, P, i64, P]
         lib.orc_search.argtypes = [P, P, i64, P, i32, i32, P, P, P, P, P, P, ctypes.c_int,
-                                   ctypes.c_int]
+                                   ctypes.c_int, i32, ctypes.c_double, i32, P]
         lib.orc_bruteforce.argtypes = [P, P, i64, i32, P, P, ctypes.c_int]
         _lib = lib
     return _lib
@@ -223,11 +223,13 @@ class SearchResult:
     topn_adc: np.ndarray
     ncand: np.ndarray
     nentries: np.ndarray
+    reranked: np.ndarray = None
 
 
 def search(ix: Index, Q, nprobe, k: int, rerank_n: int, threads: int = 0,
-           lut_f16: bool = False) -> SearchResult:
-    """Steps 1-8 for a batch of queries (lut_f16: half-precision table variant)."""
+           lut_f16: bool = False, heuristic=None) -> SearchResult:
+    """Steps 1-8 for a batch of queries (lut_f16: half-precision table variant;
+    heuristic = (batch_size, eps, beta): step 8 by the heuristic re-ranking)."""
     Q = _q(Q)
     nq = Q.shape[0]
     npr = _np(nprobe, nq)
@@ -237,10 +239,12 @@ def search(ix: Index, Q, nprobe, k: int, rerank_n: int, threads: int = 0,
     tadc = np.empty((nq, rerank_n), dtype=np.float32)
     nc = np.empty(nq, dtype=np.int64)
     ne = np.empty(nq, dtype=np.int64)
+    hb, he, hbeta = heuristic if heuristic else (0, 0.0, 1)
+    rr = np.empty(nq, dtype=np.int64)
     _load().orc_search(ctypes.byref(ix.cstruct()), _p(Q), nq, _p(npr), k, rerank_n, _p(ids),
                        _p(dists), _p(tids), _p(tadc), _p(nc), _p(ne), threads,
-                       1 if lut_f16 else 0)
-    return SearchResult(ids, dists, tids, tadc, nc, ne)
+                       1 if lut_f16 else 0, int(hb), float(he), int(hbeta), _p(rr))
+    return SearchResult(ids, dists, tids, tadc, nc, ne, rr)
 
 
 def bruteforce(ix: Index, Q, k: int, threads: int = 0):

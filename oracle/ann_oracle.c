@@ -227,6 +227,80 @@ static float adc_one(const orc_index* ix, const float* lut32, int64_t v) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Step 8, heuristic form (Alg. 1 with the change rate of Eq. 3).            */
+/* A max-heap Q of at most k (distance, id) pairs; candidates are taken in   */
+/* ascending ADC order, in mini-batches of `batch`.  A candidate enters Q    */
+/* while Q holds fewer than k pairs, otherwise if it is smaller than Q's     */
+/* maximum (which it replaces).  After each mini-batch the change rate is    */
+/* the number of IDs in Q that were not in Q before the mini-batch, divided  */
+/* by k; the process stops once it has been <= eps for beta mini-batches in  */
+/* a row.  Returns the number of candidates re-ranked.                       */
+
+static void heap_sift_down(pair_t* h, int n, int i) {
+  for (;;) {
+    int l = 2 * i + 1, r = l + 1, m = i;
+    if (l < n && pair_cmp(&h[l], &h[m]) > 0) m = l;
+    if (r < n && pair_cmp(&h[r], &h[m]) > 0) m = r;
+    if (m == i) return;
+    pair_t t = h[i];
+    h[i] = h[m];
+    h[m] = t;
+    i = m;
+  }
+}
+
+static void heap_push(pair_t* h, int* n, pair_t p) {
+  int i = (*n)++;
+  h[i] = p;
+  while (i > 0) {
+    int up = (i - 1) / 2;
+    if (pair_cmp(&h[i], &h[up]) <= 0) break;
+    pair_t t = h[i];
+    h[i] = h[up];
+    h[up] = t;
+    i = up;
+  }
+}
+
+static int64_t heuristic_rerank(const orc_index* ix, const double* q, const int32_t* qi,
+                                const pair_t* tasks, int64_t ntask, int k, int batch, double eps,
+                                int beta, pair_t* heap, int32_t* prev_ids, int* out_n) {
+  int hn = 0, stable = 0;
+  int64_t done = 0;
+  for (int64_t i = 0; i < ntask; i += batch) {
+    int nprev = hn;
+    for (int t = 0; t < hn; ++t) prev_ids[t] = heap[t].id;          /* S_{n-1} */
+    for (int64_t j = i; j < i + batch && j < ntask; ++j) {
+      pair_t c;
+      c.id = tasks[j].id;
+      c.d = exact_dist(ix, q, qi, c.id);
+      if (hn < k) {
+        heap_push(heap, &hn, c);
+      } else if (pair_cmp(&c, &heap[0]) < 0) {
+        heap[0] = c;
+        heap_sift_down(heap, hn, 0);
+      }
+      done = j + 1;
+    }
+    int changed = 0;                                                 /* |S_n - S_n & S_{n-1}| */
+    for (int t = 0; t < hn; ++t) {
+      int seen = 0;
+      for (int u = 0; u < nprev && !seen; ++u) seen = prev_ids[u] == heap[t].id;
+      changed += !seen;
+    }
+    double delta = (double)changed / (double)k;                      /* Eq. 3 */
+    if (delta <= eps) {
+      if (++stable >= beta) break;
+    } else {
+      stable = 0;
+    }
+  }
+  qsort(heap, (size_t)hn, sizeof(pair_t), pair_cmp);
+  *out_n = hn;
+  return done;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Public entry points.  All arrays are host arrays owned by the caller.     */
 
 /* Step 2 for a batch.  probe/pdist: nq x nprobe_max, padded with -1/+inf. */
@@ -318,10 +392,15 @@ void orc_exact(const orc_index* ix, const float* q32, const int32_t* ids, int64_
  *   nentries             optional nq: list entries gathered (with duplicates)
  *   lut_f16              1: the half-precision table variant (entries rounded
  *                        to binary16, summed in float32 as in Eq. 1)
+ *   h_batch              > 0: step 8 is the heuristic re-ranking (Alg. 1) with
+ *                        mini-batches of h_batch, threshold h_eps, count h_beta;
+ *                        0: the fixed-n re-rank
+ *   reranked             optional nq: candidates whose exact distance was computed
  */
 void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* nprobe,
                 int32_t k, int32_t rerank_n, int64_t* ids, float* dists, int32_t* topn_ids,
-                float* topn_adc, int64_t* ncand, int64_t* nentries, int nthreads, int lut_f16) {
+                float* topn_adc, int64_t* ncand, int64_t* nentries, int nthreads, int lut_f16,
+                int32_t h_batch, double h_eps, int32_t h_beta, int64_t* reranked) {
   int64_t maxg = ix->offsets[ix->nlist];
   if (maxg < 1) maxg = 1;
 #ifdef _OPENMP
@@ -336,6 +415,7 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
     float* lut = (float*)malloc(sizeof(float) * ix->m * ix->ksub);
     int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * maxg);
     pair_t* rr = (pair_t*)malloc(sizeof(pair_t) * (rerank_n > 0 ? rerank_n : 1));
+    int32_t* prev = (int32_t*)malloc(sizeof(int32_t) * (k > 0 ? k : 1));
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 1)
 #endif
@@ -358,15 +438,23 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
           topn_adc[i * rerank_n + c] = c < nn ? scratch[c].d : INFINITY;
         }
       }
-      for (int64_t c = 0; c < nn; ++c) {                           /* step 8 */
-        rr[c].id = scratch[c].id;
-        rr[c].d = exact_dist(ix, q, qi, scratch[c].id);
+      int64_t nout = nn, nre = nn;
+      if (h_batch > 0) {                                           /* step 8, Alg. 1 */
+        int hn = 0;
+        nre = heuristic_rerank(ix, q, qi, scratch, nn, k, h_batch, h_eps, h_beta, rr, prev, &hn);
+        nout = hn;
+      } else {                                                     /* step 8, fixed n */
+        for (int64_t c = 0; c < nn; ++c) {
+          rr[c].id = scratch[c].id;
+          rr[c].d = exact_dist(ix, q, qi, scratch[c].id);
+        }
+        qsort(rr, (size_t)nn, sizeof(pair_t), pair_cmp);
       }
-      qsort(rr, (size_t)nn, sizeof(pair_t), pair_cmp);
       for (int c = 0; c < k; ++c) {
-        ids[i * k + c] = c < nn ? (int64_t)rr[c].id : -1;
-        dists[i * k + c] = c < nn ? rr[c].d : INFINITY;
+        ids[i * k + c] = c < nout ? (int64_t)rr[c].id : -1;
+        dists[i * k + c] = c < nout ? rr[c].d : INFINITY;
       }
+      if (reranked) reranked[i] = nre;
       if (ncand) ncand[i] = nu;
       if (nentries) nentries[i] = g;
     }
@@ -377,6 +465,7 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
     free(lut);
     free(buf);
     free(rr);
+    free(prev);
   }
 }
 

@@ -314,3 +314,49 @@ def test_half_table_variant(tmp_path, orc):
         want = cand[np.lexsort((cand, adc))][:n]
         assert r.topn_ids[i].tolist() == want.tolist()
         assert r.topn_adc[i].tolist() == np.sort(adc)[:n].tolist()
+
+
+def _prefix_topk(Q, X, cand, k):
+    """Exact top-k (distance, id) of each prefix length, by numpy (integers)."""
+    ex = ((Q[None, :].astype(np.int64) - X[cand].astype(np.int64)) ** 2).sum(1)
+    return ex
+
+
+def test_heuristic_rerank_reductions_and_rule(tmp_path, orc):
+    """Heuristic re-ranking (Alg. 1, change rate of Eq. 3), pinned three ways:
+    (a) beta larger than the number of mini-batches never stops early, so the
+        result is the fixed-n re-rank; (b) eps >= 1 with beta = 1 stops after
+        the first mini-batch, so the result is the exact top-k of the first
+        batch_size candidates; (c) for other settings the result is the exact
+        top-k of the first T candidates and T is where the stopping rule,
+        re-derived here with numpy sets of prefix top-k IDs, first fires."""
+    X = fx.mixture(23, 6000, 32, "u8", n_centres=8, hi=255)
+    path, _ = fx.built(tmp_path, "heur", X, "u8", nlist=16, M=8)
+    ix = orc.read_index(path)
+    Q = fx.mixture(24, 12, 32, "u8", n_centres=8, hi=255).astype(np.float32)
+    k, n = 10, 300
+    fixed = orc.search(ix, Q, 6, k, n)
+    never = orc.search(ix, Q, 6, k, n, heuristic=(32, 0.0, 10 ** 6))
+    assert np.array_equal(never.ids, fixed.ids) and np.array_equal(never.dists, fixed.dists)
+    assert (never.reranked == np.minimum(n, fixed.ncand)).all()
+    for B, eps, beta in ((40, 1.0, 1), (16, 0.0, 2), (8, 0.1, 3), (25, 0.2, 1)):
+        r = orc.search(ix, Q, 6, k, n, heuristic=(B, eps, beta))
+        for i in range(len(Q)):
+            cand = fixed.topn_ids[i][fixed.topn_ids[i] >= 0]
+            ex = _prefix_topk(Q[i], X, cand, k)
+            stop, stable, prev = len(cand), 0, set()
+            for b0 in range(0, len(cand), B):
+                t = min(len(cand), b0 + B)
+                cur = set(cand[np.lexsort((cand[:t], ex[:t]))][:k].tolist())
+                delta = len(cur - prev) / k
+                prev = cur
+                stable = stable + 1 if delta <= eps else 0
+                if stable >= beta:
+                    stop = t
+                    break
+            assert r.reranked[i] == stop, (B, eps, beta, i)
+            o = np.lexsort((cand[:stop], ex[:stop]))[:k]
+            assert r.ids[i][:len(o)].tolist() == cand[:stop][o].tolist()
+            assert r.dists[i][:len(o)].tolist() == ex[:stop][o].astype(np.float32).tolist()
+            if (B, eps, beta) == (40, 1.0, 1):
+                assert stop == min(40, len(cand))

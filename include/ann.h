@@ -110,6 +110,27 @@ ann_status ann_search(ann_index* ix, const float* d_queries, int64_t nq, const i
                       float* d_out_dists, void* stream);
 
 /*
+ * Steps 1-8 with step 8 by the heuristic re-ranking of Alg. 1 (change rate
+ * of Eq. 3) instead of a fixed number of exact distances.  The rerank_n
+ * candidates of step 7 are taken in ascending (ADC distance, id) order in
+ * mini-batches of batch_size.  After each mini-batch the current best k
+ * (exact distance, id) pairs are those of all candidates re-ranked so far;
+ * the change rate is the number of their IDs that were not among the best k
+ * before the mini-batch, divided by k.  Re-ranking stops once the change rate
+ * has been <= eps for beta consecutive mini-batches (or when the candidates
+ * run out).  The result is the exact top-k of the candidates re-ranked.
+ *   1 <= k <= 64, k <= rerank_n <= max_rerank_n, batch_size >= 1, beta >= 1,
+ *   eps >= 0
+ *   d_out_reranked optional int32 [nq]: candidates re-ranked per query
+ * Other arguments and errors as ann_search.
+ */
+ann_status ann_search_heuristic(ann_index* ix, const float* d_queries, int64_t nq,
+                                const int32_t* d_nprobe, int32_t nprobe_max, int32_t k,
+                                int32_t rerank_n, int32_t batch_size, double eps, int32_t beta,
+                                int64_t* d_out_ids, float* d_out_dists, int32_t* d_out_reranked,
+                                void* stream);
+
+/*
  * Steps 1-7: like ann_search but returns the rerank_n best approximate
  * candidates (ascending by (ADC distance, id)) instead of re-ranking them.
  *   d_out_ids int32 [nq, rerank_n] (-1 padded), d_out_adc float32 [nq, rerank_n]

@@ -100,6 +100,8 @@ def lib():
         L.ann_adc_backward_workspace.restype = ctypes.c_size_t
         L.ann_adc_backward.argtypes = [P, i64, P, i32, i32, P, i64, P, P, P, P, ctypes.c_size_t, P]
         L.ann_adc_backward.restype = ctypes.c_int
+        L.ann_search_heuristic.argtypes = [P, P, i64, P, i32, i32, i32, i32, ctypes.c_double, i32,
+                                           P, P, P, P]
         L.ann_graph_create.argtypes = [P, P, i64, P, i32, i32, i32, P, P, ctypes.POINTER(P)]
         L.ann_graph_launch.argtypes = [P, P]
         L.ann_graph_free.argtypes = [P]
@@ -115,7 +117,8 @@ def lib():
                   "ann_lut", "ann_scan_trace", "ann_rerank", "ann_set_profiling",
                   "ann_get_profile", "ann_set_option", "ann_get_option", "ann_server_start",
                   "ann_server_submit", "ann_server_poll", "ann_server_get_stats",
-                  "ann_server_stop", "ann_graph_create", "ann_graph_launch", "ann_autotune"):
+                  "ann_server_stop", "ann_graph_create", "ann_graph_launch", "ann_autotune",
+                  "ann_search_heuristic"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -186,6 +189,20 @@ class Index:
         _check(lib().ann_search(self._h, _ptr(q), nq, _ptr(npt), npmax, k, rerank_n, _ptr(ids),
                                 _ptr(d), _stream(self.device, stream)))
         return ids, d
+
+    def search_heuristic(self, queries, nprobe, k: int, rerank_n: int, batch_size: int,
+                         eps: float, beta: int, stream=None):
+        """Steps 1-8 with the heuristic re-ranking (Alg. 1): (ids, dists, re-ranked counts)."""
+        q = self._queries(queries)
+        nq = q.shape[0]
+        npt, npmax = self._nprobe(nprobe, nq)
+        ids = torch.empty((nq, k), dtype=torch.int64, device=self.device)
+        d = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        rr = torch.empty((nq,), dtype=torch.int32, device=self.device)
+        _check(lib().ann_search_heuristic(self._h, _ptr(q), nq, _ptr(npt), npmax, k, rerank_n,
+                                          int(batch_size), float(eps), int(beta), _ptr(ids),
+                                          _ptr(d), _ptr(rr), _stream(self.device, stream)))
+        return ids, d, rr
 
     def search_topn(self, queries, nprobe, rerank_n: int, stream=None):
         """Steps 1-7: (ids int32 [nq, n], ADC distances float32 [nq, n], candidates int64 [nq])."""

@@ -592,15 +592,27 @@ extern "C" void ann_free_index(ann_index* ix) { delete ix; }
 
 namespace {
 
+// Heuristic re-ranking parameters (Alg. 1); batch 0 = the fixed-n re-rank.
+struct Heur {
+  int batch = 0;
+  double eps = 0.0;
+  int beta = 1;
+  int32_t* reranked = nullptr;  // [nq] candidates re-ranked, or NULL
+};
+
 // Steps 1-8 (or 1-7 with topn_ids) for qc <= chunk_queries(...) queries, on
 // the given working buffers.
 ann_status run_chunk(ann_index* ix, Work& w, const float* q, int qc, const int32_t* nprobe,
                      int32_t np_max, int32_t k, int32_t n, int64_t* out_ids, float* out_d,
-                     int32_t* topn_ids, float* topn_adc, int64_t* ncand, hipStream_t st) {
+                     int32_t* topn_ids, float* topn_adc, int64_t* ncand, hipStream_t st,
+                     const Heur& h = Heur()) {
   const DevIndex& d = ix->d;
   LaunchCfg c = cfg_for(qc, np_max, n, k, ix->opt_tile, ix->opt_split);
   c.lut16 = ix->opt_lut16 != 0;
   c.order = ix->opt_order != 0;
+  c.hb = h.batch;
+  c.h_eps = h.eps;
+  c.h_beta = h.beta;
   {
     StageMark m(ix, 0, st);
     HIP_TRY(launch_probe(d, q, nprobe, np_max, qc, w, nullptr, w.lists, st));
@@ -611,14 +623,15 @@ ann_status run_chunk(ann_index* ix, Work& w, const float* q, int qc, const int32
   }
   {
     StageMark m(ix, 3, st);
-    HIP_TRY(launch_merge(d, q, c, w, topn_ids, topn_adc, ncand, out_ids, out_d, st));
+    HIP_TRY(launch_merge(d, q, c, w, topn_ids, topn_adc, ncand, out_ids, out_d, h.reranked, st));
   }
   return ANN_OK;
 }
 
 ann_status run_pipeline(ann_index* ix, const float* Q, int64_t nq, const int32_t* nprobe,
                         int32_t np_max, int32_t k, int32_t n, int64_t* out_ids, float* out_d,
-                        int32_t* topn_ids, float* topn_adc, int64_t* ncand, hipStream_t st) {
+                        int32_t* topn_ids, float* topn_adc, int64_t* ncand, hipStream_t st,
+                        const Heur& h = Heur()) {
   HIP_TRY(hipSetDevice(ix->device));
   ann_status s;
   if ((s = check_lds(ix, np_max, n)) != ANN_OK) return s;
@@ -633,7 +646,8 @@ ann_status run_pipeline(ann_index* ix, const float* Q, int64_t nq, const int32_t
     s = run_chunk(ix, ws->w, Q + q0 * d.dim, qc, nprobe ? nprobe + q0 : nullptr, np_max, k, n,
                   out_ids ? out_ids + q0 * k : nullptr, out_d ? out_d + q0 * k : nullptr,
                   topn_ids ? topn_ids + q0 * n : nullptr, topn_adc ? topn_adc + q0 * n : nullptr,
-                  ncand ? ncand + q0 : nullptr, st);
+                  ncand ? ncand + q0 : nullptr, st,
+                  Heur{h.batch, h.eps, h.beta, h.reranked ? h.reranked + q0 : nullptr});
     if (s != ANN_OK) return s;
   }
   return ANN_OK;
@@ -715,6 +729,30 @@ extern "C" ann_status ann_search(ann_index* ix, const float* d_queries, int64_t 
   if (nq == 0) return ANN_OK;
   return run_pipeline(ix, d_queries, nq, d_nprobe, nprobe_max, k, rerank_n, d_out_ids,
                       d_out_dists, nullptr, nullptr, nullptr, (hipStream_t)stream);
+}
+
+extern "C" ann_status ann_search_heuristic(ann_index* ix, const float* d_queries, int64_t nq,
+                                           const int32_t* d_nprobe, int32_t nprobe_max, int32_t k,
+                                           int32_t rerank_n, int32_t batch_size, double eps,
+                                           int32_t beta, int64_t* d_out_ids, float* d_out_dists,
+                                           int32_t* d_out_reranked, void* stream) {
+  ann_status s = validate_args(ix, d_queries, nq, nprobe_max);
+  if (s != ANN_OK) return s;
+  if (k < 1 || k > 64) return fail(ANN_EINVAL, "k must be in [1, 64] for the heuristic re-rank");
+  if (rerank_n < k || rerank_n > kMaxRerank)
+    return fail(ANN_EINVAL, "rerank_n must be in [k, %d]", kMaxRerank);
+  if (batch_size < 1) return fail(ANN_EINVAL, "batch_size must be >= 1");
+  if (beta < 1) return fail(ANN_EINVAL, "beta must be >= 1");
+  if (!(eps >= 0.0)) return fail(ANN_EINVAL, "eps must be >= 0");
+  if (nq > 0 && (!d_out_ids || !d_out_dists)) return fail(ANN_EINVAL, "output pointer is NULL");
+  if (nq == 0) return ANN_OK;
+  Heur h;
+  h.batch = batch_size;
+  h.eps = eps;
+  h.beta = beta;
+  h.reranked = d_out_reranked;
+  return run_pipeline(ix, d_queries, nq, d_nprobe, nprobe_max, k, rerank_n, d_out_ids,
+                      d_out_dists, nullptr, nullptr, nullptr, (hipStream_t)stream, h);
 }
 
 extern "C" ann_status ann_search_topn(ann_index* ix, const float* d_queries, int64_t nq,

@@ -74,6 +74,10 @@ struct LaunchCfg {
   int tile;        // target entries per work item
   bool lut16 = false;  // half-precision distance table in the scan
   bool order = false;  // scan queries in locality order (by nearest list)
+  // heuristic re-ranking (Alg. 1): mini-batch size (0: fixed-n re-rank), eps, beta
+  int hb = 0;
+  double h_eps = 0.0;
+  int h_beta = 1;
 };
 
 // Kernel launchers (ann_kernels.hip).  All enqueue on `st` and return hipError_t.
@@ -89,7 +93,7 @@ hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const flo
                              int64_t* out_count, Work& w, hipStream_t st);
 hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,
                         int32_t* topn_ids, float* topn_adc, int64_t* ncand, int64_t* out_ids,
-                        float* out_dists, hipStream_t st);
+                        float* out_dists, int32_t* reranked, hipStream_t st);
 hipError_t launch_rerank_only(const DevIndex& ix, const float* q, const int32_t* cand, int qc,
                               int n, int k, int64_t* out_ids, float* out_dists, hipStream_t st);
 

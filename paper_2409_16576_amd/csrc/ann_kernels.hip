@@ -1178,9 +1178,10 @@ __device__ void block_topk_small(uint64_t* s_key, int nn, int kk, uint64_t* s_ca
 // top-k, sorted.  s_key2 holds P >= nn keys; s_top is reused for the result
 // (it needs pow2_at_least(min(k, nn)) slots); s_cand holds
 // 64 * (blockDim / 64 + 1) keys.
-__device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_top, int nn,
-                             uint64_t* s_key2, int P, int k, int64_t* out_ids, float* out_d,
-                             SelScratch* ss, int* s_cnt, uint64_t* s_cand) {
+// Exact keys (squared distance, id) of the candidates s_top[0..nn) (keys of
+// (adc, id)) into s_key2[0..P), P >= nn, ~0 beyond nn.
+__device__ void exact_keys(const DevIndex& ix, const float* s_q, const uint64_t* s_top, int nn,
+                           uint64_t* s_key2, int P) {
   const int g16 = ix.dim % 16 == 0 ? ix.dim / 16 : 0;
   if (ix.dtype != F32 && (g16 == 1 || g16 == 2 || g16 == 4 || g16 == 8 || g16 == 16)) {
     switch (g16) {
@@ -1231,6 +1232,12 @@ __device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_t
       s_key2[i] = key;
     }
   }
+}
+
+__device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_top, int nn,
+                             uint64_t* s_key2, int P, int k, int64_t* out_ids, float* out_d,
+                             SelScratch* ss, int* s_cnt, uint64_t* s_cand) {
+  exact_keys(ix, s_q, s_top, nn, s_key2, P);
   __syncthreads();
   // the kk smallest keys, ascending
   const int kk = min(k, nn);
@@ -1261,8 +1268,60 @@ __device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_t
   }
 }
 
+// Step 8 by the heuristic re-ranking (Alg. 1, change rate of Eq. 3): the
+// candidates s_top[0..nn), sorted ascending by (adc, id), are re-ranked in
+// mini-batches of hb; after each mini-batch the k best (distance, id) pairs
+// so far are the k smallest of (previous best, this mini-batch), and the
+// change rate is the number of their IDs absent from the previous best,
+// divided by k.  The loop stops once the rate has been <= eps for beta
+// mini-batches in a row.  k <= 64.  s_key2 holds >= nn keys, s_best 64,
+// s_cand 64 * (blockDim / 64 + 1); *reranked = candidates re-ranked.
+__device__ void rerank_heuristic(const DevIndex& ix, const float* s_q, const uint64_t* s_top,
+                                 int nn, uint64_t* s_key2, uint64_t* s_best, uint64_t* s_cand,
+                                 int* s_misc, int k, int hb, double eps, int beta,
+                                 int64_t* out_ids, float* out_d, int32_t* reranked) {
+  int cur = 0, stable = 0, done = 0;
+  for (int i = 0; i < nn; i += hb) {
+    const int b = min(hb, nn - i);
+    exact_keys(ix, s_q, s_top + i, b, s_key2, b);
+    for (int t = threadIdx.x; t < cur; t += blockDim.x) s_key2[b + t] = s_best[t];  // b + cur <= nn
+    __syncthreads();
+    const int kk = min(k, b + cur);
+    block_topk_small(s_key2, b + cur, kk, s_cand);  // ascending in s_cand[0..kk)
+    if (threadIdx.x < 64) {  // IDs of the new best that the previous best lacked
+      const int lane = threadIdx.x;
+      bool fresh = false;
+      if (lane < kk) {
+        const uint32_t id = (uint32_t)s_cand[lane];
+        fresh = true;
+        for (int u = 0; u < cur; ++u) fresh = fresh && (uint32_t)s_best[u] != id;
+      }
+      const uint64_t m = __ballot(fresh);
+      if (lane == 0) *s_misc = __popcll(m);
+    }
+    __syncthreads();
+    const int changed = *s_misc;
+    for (int t = threadIdx.x; t < kk; t += blockDim.x) s_best[t] = s_cand[t];
+    cur = kk;
+    done = i + b;
+    __syncthreads();
+    const double delta = (double)changed / (double)k;  // Eq. 3
+    if (delta <= eps) {
+      if (++stable >= beta) break;
+    } else {
+      stable = 0;
+    }
+  }
+  for (int t = threadIdx.x; t < k; t += blockDim.x) {
+    const bool v = t < cur;
+    out_ids[t] = v ? (int64_t)(uint32_t)s_best[t] : -1;
+    out_d[t] = v ? unord32((uint32_t)(s_best[t] >> 32)) : INFINITY;
+  }
+  if (threadIdx.x == 0 && reranked) *reranked = done;
+}
+
 struct MergeLayout {
-  size_t keys, top, key2, q, sel, cand, misc, total;
+  size_t keys, top, key2, q, sel, cand, best, misc, total;
 };
 
 __host__ __device__ inline MergeLayout merge_layout(int smax, int n, int dim) {
@@ -1275,7 +1334,8 @@ __host__ __device__ inline MergeLayout merge_layout(int smax, int n, int dim) {
   L.q = o; o += (size_t)dim * 4; o = align_up(o, 16);
   L.sel = o; o += sizeof(SelScratch); o = align_up(o, 16);
   L.cand = o; o += (size_t)64 * (kMergeBlock / 64 + 1) * 8;
-  L.misc = o; o += 16 + 4 * 17;
+  L.best = o; o += 64 * 8;
+  L.misc = o; o += 16 + 4 * 18;
   L.total = align_up(o, 16);
   return L;
 }
@@ -1285,7 +1345,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     DevIndex ix, const float* __restrict__ Q, int qc, const int32_t* __restrict__ sq, int smax,
     int n, int k, const uint64_t* __restrict__ pkeys, const int32_t* __restrict__ pcount,
     const int32_t* __restrict__ pscan, int32_t* __restrict__ topn_ids, float* __restrict__ topn_adc,
-    int64_t* __restrict__ ncand, int64_t* __restrict__ out_ids, float* __restrict__ out_dists) {
+    int64_t* __restrict__ ncand, int64_t* __restrict__ out_ids, float* __restrict__ out_dists,
+    int hb, double h_eps, int h_beta, int32_t* __restrict__ reranked) {
   extern __shared__ __align__(16) unsigned char smem[];
   const MergeLayout L = merge_layout(smax, n, ix.dim);
   uint64_t* s_keys = reinterpret_cast<uint64_t*>(smem + L.keys);
@@ -1343,7 +1404,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
       topn_adc[(size_t)q * n + i] = v ? unord32((uint32_t)(s_top[i] >> 32)) : INFINITY;
     }
   }
-  if (out_ids) {
+  if (out_ids && hb > 0) {  // heuristic re-ranking: candidates in ascending ADC order
+    if (!topn_ids) block_bitonic(s_top, P);  // (already sorted when the top-n was written)
+    __syncthreads();  // s_key2 aliases s_keys
+    rerank_heuristic(ix, s_q, s_top, nn, s_key2, reinterpret_cast<uint64_t*>(smem + L.best),
+                     s_cand, s_cnt + 18, k, hb, h_eps, h_beta, out_ids + (size_t)q * k,
+                     out_dists + (size_t)q * k, reranked ? reranked + q : nullptr);
+  } else if (out_ids) {
     __syncthreads();  // s_key2 aliases s_keys
     rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k,
                  out_dists + (size_t)q * k, ss, s_cnt, s_cand);
@@ -1845,7 +1912,7 @@ hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const flo
 
 hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,
                         int32_t* topn_ids, float* topn_adc, int64_t* ncand, int64_t* out_ids,
-                        float* out_dists, hipStream_t st) {
+                        float* out_dists, int32_t* reranked, hipStream_t st) {
   if (c.qc <= 0) return hipSuccess;
   const MergeLayout L = merge_layout(c.smax, c.n, ix.dim);
   // more threads only pay off when there are many candidates to re-rank
@@ -1855,7 +1922,7 @@ hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, 
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
   hipLaunchKernelGGL(kern, dim3(c.qc), dim3(big ? kMergeBlock : 256), L.total, st, ix, q, c.qc, w.sq, c.smax,
                      c.n, c.k, w.pkeys, w.pcount, w.pscan, topn_ids, topn_adc, ncand, out_ids,
-                     out_dists);
+                     out_dists, c.hb, c.h_eps, c.h_beta, reranked);
   return hipGetLastError();
 }
 

@@ -323,3 +323,31 @@ def test_half_table_variant_bit_exact(name, indexes, gpu_index, orc):
             assert np.array_equal(ids.cpu().numpy(), r.ids) and np.array_equal(d.cpu().numpy(), r.dists)
     finally:
         g.set_option(g.OPT_LUT_F16, 0)
+
+
+@pytest.mark.parametrize("name", KINDS)
+def test_heuristic_rerank_bit_exact(name, indexes, gpu_index, orc):
+    """Step 8 by the heuristic re-ranking (Alg. 1 / Eq. 3): IDs, distances and
+    the number of candidates re-ranked equal the oracle's max-heap version."""
+    ix, _, Q = indexes[name]
+    g = gpu_index(name)
+    rng = np.random.default_rng(12)
+    npr = rng.integers(1, 20, size=len(Q)).astype(np.int32)
+    for k, n, hb, eps, beta in ((10, 400, 32, 0.0, 2), (10, 1400, 100, 0.1, 3), (5, 64, 7, 0.2, 1),
+                                (64, 2048, 256, 0.0, 1), (10, 300, 1000, 0.0, 1), (1, 10, 1, 0.0, 4)):
+        _say("heuristic", name, k, n, hb, eps, beta)
+        ids, d, rr = g.search_heuristic(_cuda(Q), _cuda(npr), k, n, hb, eps, beta)
+        torch.cuda.synchronize()
+        r = orc.search(ix, Q, npr, k, n, heuristic=(hb, eps, beta))
+        assert np.array_equal(ids.cpu().numpy(), r.ids), (k, n, hb, eps, beta)
+        assert np.array_equal(d.cpu().numpy(), r.dists), (k, n, hb, eps, beta)
+        assert np.array_equal(rr.cpu().numpy().astype(np.int64), r.reranked)
+
+
+def test_heuristic_rerank_errors(indexes, gpu_index, ann):
+    _, _, Q = indexes["u8"]
+    g = gpu_index("u8")
+    for args in ((65, 100, 10, 0.0, 1), (10, 100, 0, 0.0, 1), (10, 100, 10, -1.0, 1),
+                 (10, 100, 10, 0.0, 0), (10, 5, 10, 0.0, 1)):
+        with pytest.raises(ann.AnnError):
+            g.search_heuristic(_cuda(Q), 4, *args)

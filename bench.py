@@ -76,7 +76,9 @@ def parse():
     ap.add_argument("--rerank-n", type=int, default=0,
                     help="top-n re-ranked (default: the workload's recall>=0.9 operating point)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
-    ap.add_argument("--forms", default="plain,batched,served")
+    ap.add_argument("--forms", default="plain,batched,served,heuristic")
+    ap.add_argument("--heur", default="2000,200,0,2",
+                    help="heuristic form: rerank_n,batch_size,eps,beta (Alg. 1)")
     ap.add_argument("--served-rates", default="0.25,0.5,1,1.5,2,3",
                     help="offered loads of the served form, million queries/s")
     ap.add_argument("--served-seconds", type=float, default=1.5,
@@ -356,7 +358,14 @@ def main():
     def step_graph():
         out["graph_res"] = graph.launch(st)
 
-    forms = {"plain": step_plain, "batched": step_graph, "batched_eager": step_eager}
+    hn, hb, heps, hbeta = (float(x) for x in args.heur.split(","))
+    hn, hb, hbeta = int(hn), int(hb), int(hbeta)
+
+    def step_heur():
+        out["heur_res"] = g.search_heuristic(Q, nprobe_arg, k, hn, hb, heps, hbeta)
+
+    forms = {"plain": step_plain, "batched": step_graph, "batched_eager": step_eager,
+             "heuristic": step_heur}
     names = args.forms.split(",")
     default_split = (g.get_option(g.OPT_SCAN_TILE), g.get_option(g.OPT_SCAN_SPLIT))
     if "batched" in names:
@@ -384,7 +393,7 @@ def main():
             continue
         fn = forms[name]
         # plain runs with the index's default work split
-        sp = batched_split if name.startswith("batched") else default_split
+        sp = batched_split if name.startswith("batched") or name == "heuristic" else default_split
         g.set_option(g.OPT_SCAN_TILE, sp[0])
         g.set_option(g.OPT_SCAN_SPLIT, sp[1])
         for _ in range(args.warmup):
@@ -452,6 +461,13 @@ def main():
         line["batched_over_plain"] = round(results["batched"]["qps"] / results["plain"]["qps"], 3)
     if "plain" in results and "served" in results:
         line["served_over_plain"] = round(results["served"]["qps"] / results["plain"]["qps"], 3)
+    if "heuristic" in results:
+        rr = out["heur_res"][2].float()
+        results["heuristic"]["params"] = {"rerank_n": hn, "batch_size": hb, "eps": heps,
+                                          "beta": hbeta}
+        results["heuristic"]["mean_reranked"] = round(float(rr.mean()), 1)
+        line["forms"]["heuristic"] = {kk: (round(v, 4) if isinstance(v, float) else v)
+                                      for kk, v in results["heuristic"].items()}
 
     if not args.no_cpu:
         import oracle
@@ -481,6 +497,16 @@ def main():
         log(f"brute force of {nr} queries in {time.perf_counter() - t0:.1f}s")
         line["recall_at_10"] = round(oracle.recall_at_k(ids_gpu[:nr], gt, k), 4)
         line["recall_queries"] = nr
+        if "heur_res" in out:
+            hid = out["heur_res"][0][:nr].cpu().numpy()
+            line["forms"]["heuristic"]["recall_at_10"] = round(oracle.recall_at_k(hid, gt, k), 4)
+            rh = oracle.search(oix, Qh[:nr], npq[:nr], k, hn, threads=threads,
+                               lut_f16=args.lut16, heuristic=(hb, heps, hbeta))
+            line["forms"]["heuristic"]["parity_sample"] = {
+                "queries": nr, "ids_equal": bool(np.array_equal(hid, rh.ids)),
+                "dists_equal": bool(np.array_equal(out["heur_res"][1][:nr].cpu().numpy(), rh.dists)),
+                "reranked_equal": bool(np.array_equal(
+                    out["heur_res"][2][:nr].cpu().numpy().astype(np.int64), rh.reranked))}
     print(json.dumps(line), flush=True)
 
 

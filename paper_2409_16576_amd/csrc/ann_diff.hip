@@ -48,61 +48,41 @@ __global__ __launch_bounds__(kBlock) void k_adc_fwd(const float* __restrict__ Q,
   }
 }
 
-// Decoded candidates Dec [C, D].
-__global__ void k_decode(const float* __restrict__ CB, const uint8_t* __restrict__ codes, int C,
-                         int D, int M, int dsub, float* __restrict__ dec) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)C * D) return;
-  const int c = (int)(i / D), d = (int)(i % D);
-  const int m = d / dsub, t = d % dsub;
-  dec[i] = CB[((size_t)m * kKsub + codes[(size_t)c * M + m]) * dsub + t];
-}
 
-// Row sums and column sums of G [B, C].
-__global__ void k_rowsum(const float* __restrict__ G, int B, int C, float* __restrict__ rs) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  float acc = 0.f;
-  for (int c = 0; c < C; ++c) acc += G[(size_t)b * C + c];
-  rs[b] = acc;
-}
-
-__global__ void k_colsum(const float* __restrict__ G, int B, int C, float* __restrict__ cs) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C) return;
-  float acc = 0.f;
-  for (int b = 0; b < B; ++b) acc += G[(size_t)b * C + c];
-  cs[c] = acc;
-}
-
-// Out[i][j] = sum_k A(i, k) * Bm(k, j), fp32 MFMA 16x16x4.  A(i, k) =
-// A[i * lda_i + k * lda_k] (so a transposed operand is just other strides),
-// Bm(k, j) = Bm[k * ldb + j], Out row-major [rows, cols].  Block: 64 x 64
-// output tile, 4 waves of 32 x 32 (2 x 2 MFMA tiles); K staged 16 at a time.
+// Out[i][j] = sum over k in [k0, k1) of A(i, k) * Bm(k, j), fp32 MFMA
+// 16x16x4.  A(i, k) = A[i * lda_i + k * lda_k] (a transposed operand is
+// just other strides), Bm(k, j) = Bm[k * ldb + j], Out row-major [rows,
+// cols].  Block: 64 x 64 output tile, 4 waves of 32 x 32 (2 x 2 MFMA tiles);
+// K staged 16 at a time, loads coalesced along whichever index of A is
+// contiguous.  blockIdx.z picks the K slice [z * kslice, (z + 1) * kslice)
+// and the partial tile goes to out + z * rows * cols (split K; the slices are
+// summed afterwards in a fixed order, so results do not depend on timing).
 __global__ __launch_bounds__(kBlock) void k_gemm_f32(const float* __restrict__ A, int64_t lda_i,
                                                       int64_t lda_k, const float* __restrict__ Bm,
                                                       int64_t ldb, int rows, int cols, int K,
-                                                      float* __restrict__ out) {
+                                                      int kslice, float* __restrict__ out) {
   __shared__ float sA[64][17];
   __shared__ float sB[16][65];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int kb = blockIdx.z * kslice, ke = min(K, kb + kslice);
   const int wi = (w >> 1) * 32, wj = (w & 1) * 32;
+  const bool a_rows_contig = lda_i == 1;  // A(i, k) contiguous along i (a transposed operand)
   v4f_t acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int c = 0; c < 2; ++c) acc[a][c] = v4f_t{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     for (int e = tid; e < 64 * 16; e += kBlock) {
-      const int r = e / 16, kk = e % 16;
+      const int r = a_rows_contig ? e % 64 : e / 16, kk = a_rows_contig ? e / 64 : e % 16;
       const int gi = i0 + r, gk = k0 + kk;
-      sA[r][kk] = (gi < rows && gk < K) ? A[(int64_t)gi * lda_i + (int64_t)gk * lda_k] : 0.f;
+      sA[r][kk] = (gi < rows && gk < ke) ? A[(int64_t)gi * lda_i + (int64_t)gk * lda_k] : 0.f;
     }
     for (int e = tid; e < 16 * 64; e += kBlock) {
       const int kk = e / 64, c = e % 64;
       const int gk = k0 + kk, gj = j0 + c;
-      sB[kk][c] = (gk < K && gj < cols) ? Bm[(int64_t)gk * ldb + gj] : 0.f;
+      sB[kk][c] = (gk < ke && gj < cols) ? Bm[(int64_t)gk * ldb + gj] : 0.f;
     }
     __syncthreads();
 #pragma unroll
@@ -119,6 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_gemm_f32(const float* __restrict__ A
     }
     __syncthreads();
   }
+  float* o = out + (size_t)blockIdx.z * rows * cols;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -127,39 +108,92 @@ __global__ __launch_bounds__(kBlock) void k_gemm_f32(const float* __restrict__ A
       for (int r = 0; r < 4; ++r) {
         const int gi = i0 + wi + a * 16 + 4 * (lane >> 4) + r;
         const int gj = j0 + wj + c * 16 + (lane & 15);
-        if (gi < rows && gj < cols) out[(size_t)gi * cols + gj] = acc[a][c][r];
+        if (gi < rows && gj < cols) o[(size_t)gi * cols + gj] = acc[a][c][r];
       }
 }
 
-// dQ = 2 * (rowsum(G) * Q - GDec)
-__global__ void k_dq(const float* __restrict__ Q, const float* __restrict__ rs,
-                     const float* __restrict__ gdec, int B, int D, float* __restrict__ dq) {
+// out[i] = sum over s = 0..S-1, in that order, of part[s][i].
+__global__ void k_sum_slices(const float* __restrict__ part, int S, size_t n,
+                             float* __restrict__ out) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)B * D) return;
-  const int b = (int)(i / D);
-  dq[i] = 2.f * (rs[b] * Q[i] - gdec[i]);
+  if (i >= n) return;
+  float acc = part[i];
+  for (int s = 1; s < S; ++s) acc = acc + part[(size_t)s * n + i];
+  out[i] = acc;
 }
 
-// dCB[m][j][t] = -2 * (sum_{c in S_mj} T[c][m*dsub+t] - (sum_{c in S_mj} cs[c]) * CB[m][j][t])
-// One thread per (m, j); members added in increasing c.
-__global__ void k_dcb(const float* __restrict__ CB, const uint8_t* __restrict__ codes,
-                      const float* __restrict__ T, const float* __restrict__ cs, int C, int D,
-                      int M, int dsub, float* __restrict__ dcb) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= M * kKsub) return;
-  const int m = e >> 8, j = e & 255;
+// Q1 [B, D + 1] = [Q | 1]: the extra column makes G^T Q1 carry colsum(G).
+__global__ void k_ones_col(const float* __restrict__ Q, int B, int D, float* __restrict__ q1) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)B * (D + 1)) return;
+  const int b = (int)(i / (D + 1)), d = (int)(i % (D + 1));
+  q1[i] = d < D ? Q[(size_t)b * D + d] : 1.f;
+}
+
+// dQ = 2 * (rowsum(G) * Q - G Dec), both read from GD1 = G [Dec | 1].
+__global__ void k_dq(const float* __restrict__ Q, const float* __restrict__ gd1, int B, int D,
+                     float* __restrict__ dq) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)B * D) return;
+  const int b = (int)(i / D), d = (int)(i % D);
+  const float* row = gd1 + (size_t)b * (D + 1);
+  dq[i] = 2.f * (row[D] * Q[i] - row[d]);
+}
+
+// dCB[m][j][t] = -2 * (sum_{c in S_mj} T[c][m*dsub+t] - (sum_{c in S_mj} colsum_c) * CB[m][j][t])
+// with T1 = G^T [Q | 1] (its last column is colsum).  Block per subspace m,
+// thread per codeword j; the subspace's codes are staged in LDS in chunks and
+// every thread walks them in increasing c (broadcast reads), adding the rows
+// of its members in that order.
+constexpr int kDcbChunk = 16384;
+
+__global__ __launch_bounds__(kKsub) void k_dcb(const float* __restrict__ CB,
+                                                const uint8_t* __restrict__ codes,
+                                                const float* __restrict__ T1, int C, int D, int M,
+                                                int dsub, float* __restrict__ dcb) {
+  __shared__ uint8_t s_code[kDcbChunk];
+  const int m = blockIdx.x, j = threadIdx.x;
   float s_cs = 0.f;
   float s_t[16];
   for (int t = 0; t < 16; ++t) s_t[t] = 0.f;
-  for (int c = 0; c < C; ++c) {
-    if (codes[(size_t)c * M + m] != j) continue;
-    s_cs += cs[c];
-    for (int t = 0; t < dsub; ++t) s_t[t] += T[(size_t)c * D + m * dsub + t];
+  for (int c0 = 0; c0 < C; c0 += kDcbChunk) {
+    const int cn = min(kDcbChunk, C - c0);
+    __syncthreads();
+    for (int c = j; c < cn; c += kKsub) s_code[c] = codes[(size_t)(c0 + c) * M + m];
+    __syncthreads();
+    for (int c = 0; c < cn; ++c) {
+      if (s_code[c] != j) continue;
+      const float* row = T1 + (size_t)(c0 + c) * (D + 1);
+      s_cs += row[D];
+      for (int t = 0; t < dsub; ++t) s_t[t] += row[m * dsub + t];
+    }
   }
   for (int t = 0; t < dsub; ++t) {
     const float cb = CB[((size_t)m * kKsub + j) * dsub + t];
     dcb[((size_t)m * kKsub + j) * dsub + t] = -2.f * (s_t[t] - s_cs * cb);
   }
+}
+
+// Decoded candidates with a ones column: Dec1 [C, D + 1] = [Dec | 1].
+__global__ void k_decode1(const float* __restrict__ CB, const uint8_t* __restrict__ codes, int C,
+                          int D, int M, int dsub, float* __restrict__ dec1) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)C * (D + 1)) return;
+  const int c = (int)(i / (D + 1)), d = (int)(i % (D + 1));
+  if (d == D) {
+    dec1[i] = 1.f;
+    return;
+  }
+  const int m = d / dsub, t = d % dsub;
+  dec1[i] = CB[((size_t)m * kKsub + codes[(size_t)c * M + m]) * dsub + t];
+}
+
+// K slices for a GEMM with `tiles` output tiles: about 1024 blocks in all,
+// slices of at least 64.
+int kslices(int tiles, int K) {
+  int s = std::max(1, 1024 / std::max(1, tiles));
+  s = std::min(s, std::max(1, K / 64));
+  return std::min(s, 64);
 }
 
 ann_status diff_fail(ann_status s, const char* msg) { return (ann_status)set_error(s, "%s", msg); }
@@ -188,10 +222,12 @@ extern "C" ann_status ann_adc_forward(const float* d_queries, int64_t B, const f
 }
 
 extern "C" size_t ann_adc_backward_workspace(int64_t B, int64_t C, int32_t M, int32_t dsub) {
-  const size_t D = (size_t)M * dsub;
-  // Dec [C, D], GDec [B, D], T [C, D], rowsum [B], colsum [C]
-  return sizeof(float) * ((size_t)C * D + (size_t)B * D + (size_t)C * D + (size_t)B + (size_t)C) +
-         256;
+  const size_t D1 = (size_t)M * dsub + 1;
+  const int t1 = (int)(((D1 + 63) / 64) * ((B + 63) / 64)), t2 = (int)(((D1 + 63) / 64) * ((C + 63) / 64));
+  const size_t s1 = (size_t)kslices(t1, (int)C), s2 = (size_t)kslices(t2, (int)B);
+  // Dec1 [C, D1], Q1 [B, D1], GD1 [B, D1], T1 [C, D1], K-slice partials
+  return sizeof(float) * ((size_t)C * D1 + 2 * (size_t)B * D1 + (size_t)C * D1 +
+                          std::max(s1 * (size_t)B * D1, s2 * (size_t)C * D1)) + 256;
 }
 
 extern "C" ann_status ann_adc_backward(const float* d_queries, int64_t B, const float* d_codebooks,
@@ -205,36 +241,43 @@ extern "C" ann_status ann_adc_backward(const float* d_queries, int64_t B, const 
   if (!d_queries || !d_codebooks || !d_codes || !d_grad || !d_workspace)
     return diff_fail(ANN_EINVAL, "NULL pointer");
   hipStream_t st = (hipStream_t)stream;
+  const int D1 = D + 1;
   float* ws = static_cast<float*>(d_workspace);
-  float* dec = ws;
-  float* gdec = dec + (size_t)C * D;
-  float* T = gdec + (size_t)B * D;
-  float* rs = T + (size_t)C * D;
-  float* cs = rs + B;
+  float* dec1 = ws;                          // [C, D1]
+  float* q1 = dec1 + (size_t)C * D1;         // [B, D1]
+  float* gd1 = q1 + (size_t)B * D1;          // [B, D1] = G [Dec | 1]
+  float* t1 = gd1 + (size_t)B * D1;          // [C, D1] = G^T [Q | 1]
+  float* part = t1 + (size_t)C * D1;         // K-slice partials
   const int thr = 256;
-  if (C > 0 && D > 0)
-    hipLaunchKernelGGL(k_decode, dim3((unsigned)(((size_t)C * D + thr - 1) / thr)), dim3(thr), 0,
-                       st, d_codebooks, d_codes, (int)C, D, M, dsub, dec);
-  if (B > 0)
-    hipLaunchKernelGGL(k_rowsum, dim3((unsigned)((B + thr - 1) / thr)), dim3(thr), 0, st, d_grad,
-                       (int)B, (int)C, rs);
-  if (C > 0)
-    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((C + thr - 1) / thr)), dim3(thr), 0, st, d_grad,
-                       (int)B, (int)C, cs);
+  const int ct = (D1 + 63) / 64;
   if (d_dq && B > 0) {
-    // GDec [B, D] = G [B, C] . Dec [C, D]
-    hipLaunchKernelGGL(k_gemm_f32, dim3((D + 63) / 64, (unsigned)((B + 63) / 64)), dim3(kBlock), 0,
-                       st, d_grad, (int64_t)C, (int64_t)1, dec, (int64_t)D, (int)B, D, (int)C, gdec);
+    if (C > 0)
+      hipLaunchKernelGGL(k_decode1, dim3((unsigned)(((size_t)C * D1 + thr - 1) / thr)), dim3(thr),
+                         0, st, d_codebooks, d_codes, (int)C, D, M, dsub, dec1);
+    const int rt = (int)((B + 63) / 64), S = kslices(ct * rt, (int)C);
+    hipLaunchKernelGGL(k_gemm_f32, dim3(ct, rt, S), dim3(kBlock), 0, st, d_grad, (int64_t)C,
+                       (int64_t)1, dec1, (int64_t)D1, (int)B, D1, (int)C,
+                       (int)((C + S - 1) / S + 15) / 16 * 16, part);
+    const size_t nb = (size_t)B * D1;
+    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((nb + thr - 1) / thr)), dim3(thr), 0, st,
+                       part, S, nb, gd1);
     hipLaunchKernelGGL(k_dq, dim3((unsigned)(((size_t)B * D + thr - 1) / thr)), dim3(thr), 0, st,
-                       d_queries, rs, gdec, (int)B, D, d_dq);
+                       d_queries, gd1, (int)B, D, d_dq);
   }
   if (d_dcb) {
-    if (C > 0)  // T [C, D] = G^T [C, B] . Q [B, D]
-      hipLaunchKernelGGL(k_gemm_f32, dim3((D + 63) / 64, (unsigned)((C + 63) / 64)), dim3(kBlock),
-                         0, st, d_grad, (int64_t)1, (int64_t)C, d_queries, (int64_t)D, (int)C, D,
-                         (int)B, T);
-    hipLaunchKernelGGL(k_dcb, dim3((M * kKsub + thr - 1) / thr), dim3(thr), 0, st, d_codebooks,
-                       d_codes, T, cs, (int)C, D, M, dsub, d_dcb);
+    if (C > 0) {
+      hipLaunchKernelGGL(k_ones_col, dim3((unsigned)(((size_t)B * D1 + thr - 1) / thr)), dim3(thr),
+                         0, st, d_queries, (int)B, D, q1);
+      const int rt = (int)((C + 63) / 64), S = kslices(ct * rt, (int)B);
+      hipLaunchKernelGGL(k_gemm_f32, dim3(ct, rt, S), dim3(kBlock), 0, st, d_grad, (int64_t)1,
+                         (int64_t)C, q1, (int64_t)D1, (int)C, D1, (int)B,
+                         (int)((B + S - 1) / S + 15) / 16 * 16, part);
+      const size_t nc = (size_t)C * D1;
+      hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((nc + thr - 1) / thr)), dim3(thr), 0, st,
+                         part, S, nc, t1);
+    }
+    hipLaunchKernelGGL(k_dcb, dim3(M), dim3(kKsub), 0, st, d_codebooks, d_codes, t1, (int)C, D, M,
+                       dsub, d_dcb);
   }
   return hipGetLastError() == hipSuccess ? ANN_OK : diff_fail(ANN_EDEVICE, "launch failed");
 }

@@ -82,7 +82,8 @@ struct SelScratch {
 };
 
 template <class G>
-__device__ __forceinline__ uint64_t block_kth(G get, int cnt, int want, SelScratch* s) {
+__device__ __forceinline__ uint64_t block_kth(G get, int cnt, int want, SelScratch* s,
+                                               int min_shift = 0) {
   const int tid = threadIdx.x;
   if (tid == 0) {
     s->want = want;
@@ -120,7 +121,8 @@ __device__ __forceinline__ uint64_t block_kth(G get, int cnt, int want, SelScrat
   const int top_shift = ((63 - __clzll((long long)diff)) / 8) * 8;
   uint64_t mask = top_shift >= 56 ? 0ull : ~((1ull << (top_shift + 8)) - 1ull);
   if (tid == 0) s->prefix = s->lo & mask;
-  for (int shift = top_shift; shift >= 0; shift -= 8) {
+  // digits below min_shift are not resolved (keys equal above it count as one)
+  for (int shift = top_shift; shift >= min_shift; shift -= 8) {
     for (int i = tid; i < 256; i += blockDim.x) s->hist[i] = 0;
     __syncthreads();
     const uint64_t prefix = s->prefix;
@@ -645,10 +647,18 @@ __device__ __forceinline__ float adc_words(const uint32_t (&w)[W], const T* __re
 // moves to a position no later than its own (all reads precede all writes).
 constexpr int kCompactChunk = 8;  // cap <= kCompactChunk * kScanBlock
 
-__device__ __forceinline__ void scan_compact(uint64_t* s_buf, int* s_wsum, SelScratch* ss, ScanMisc* mc, int n) {
+// loose: keep every key whose distance is at most the n-th smallest distance
+// (n or a few more keys: ties at that distance are not broken by id), which
+// resolves only the distance half of the keys; the threshold stays valid (it
+// is never below the n-th smallest key).  Exact: keep exactly the n smallest.
+__device__ __forceinline__ void scan_compact(uint64_t* s_buf, int* s_wsum, SelScratch* ss, ScanMisc* mc, int n,
+                                             bool loose = false) {
   const int cnt = mc->count;
   if (cnt <= n) return;
-  const uint64_t K = block_kth([&](int i) { return s_buf[i]; }, cnt, n, ss);
+  const uint64_t K =
+      loose ? (block_kth([&](int i) { return s_buf[i] & 0xffffffff00000000ull; }, cnt, n, ss, 32) |
+               0xffffffffull)
+            : block_kth([&](int i) { return s_buf[i]; }, cnt, n, ss);
   const int ch = (cnt + (int)blockDim.x - 1) / (int)blockDim.x;
   const int b0 = threadIdx.x * ch;
   uint64_t r[kCompactChunk];
@@ -664,11 +674,13 @@ __device__ __forceinline__ void scan_compact(uint64_t* s_buf, int* s_wsum, SelSc
     c += k != ~0ull ? 1 : 0;
   }
   int pos = block_excl_scan(c, s_wsum);  // contains a barrier: all reads are done
+  if (threadIdx.x == blockDim.x - 1) mc->ncount = pos + c;  // survivors
 #pragma unroll
   for (int i = 0; i < kCompactChunk; ++i)
     if (r[i] != ~0ull) s_buf[pos++] = r[i];
+  __syncthreads();
   if (threadIdx.x == 0) {
-    mc->count = n;
+    mc->count = mc->ncount;
     mc->thr = K;
   }
   __syncthreads();
@@ -992,8 +1004,12 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
       rr = 0;
       __syncthreads();
       if constexpr (!TRACE) {
-        // cut back to the n best only when the next K rounds might not fit
-        if (mc->count > cap - K * kRound) scan_compact(s_buf, s_wsum, ss, mc, n);
+        // cut back to about the n best only when the next K rounds might not
+        // fit (by distance alone; exactly when ties at the cut would not fit)
+        if (mc->count > cap - K * kRound) {
+          scan_compact(s_buf, s_wsum, ss, mc, n, true);
+          if (mc->count > cap - K * kRound) scan_compact(s_buf, s_wsum, ss, mc, n);
+        }
       }
     }
   }

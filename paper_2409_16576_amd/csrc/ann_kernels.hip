@@ -192,22 +192,45 @@ __device__ __forceinline__ uint64_t block_kth(G get, int cnt, int want, SelScrat
 }
 
 // Ascending bitonic sort of s[0..p), p a power of two.
+// Ascending sort of s[0..p) (p a power of two) by the bitonic network.  The
+// stages whose partners lie within 64 consecutive elements run in registers,
+// one element per lane, exchanging through cross-lane shuffles, so a block
+// barrier is needed only per stage of stride >= 64 and per register pass.
+// The caller synchronises before (s complete) and the sort ends with a
+// barrier.
 __device__ void block_bitonic(uint64_t* s, int p) {
-  for (int k = 2; k <= p; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < p; i += blockDim.x) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t a = s[i], b = s[ixj];
-          const bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            s[i] = b;
-            s[ixj] = a;
-          }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // stages (k, j) for k in [k0, k1], j from min(k/2, 32) down to 1, on
+  // aligned 64-element blocks (lanes past p carry a sentinel and never store)
+  auto regs = [&](int k0, int k1) {
+    for (int b0 = w * 64; b0 < p; b0 += nw * 64) {  // wave-uniform
+      const int i = b0 + lane;
+      uint64_t a = i < p ? s[i] : ~0ull;
+      for (int k = k0; k <= k1; k <<= 1)
+        for (int j = min(k >> 1, 32); j > 0; j >>= 1) {
+          const uint64_t o = __shfl_xor(a, j, 64);
+          const bool lower = (i & j) == 0, up = (i & k) == 0;
+          a = (lower == up) ? (o < a ? o : a) : (o > a ? o : a);
+        }
+      if (i < p) s[i] = a;
+    }
+  };
+  regs(2, min(p, 64));
+  __syncthreads();
+  for (int k = 128; k <= p; k <<= 1) {
+    for (int j = k >> 1; j >= 64; j >>= 1) {
+      for (int t = threadIdx.x; t < (p >> 1); t += blockDim.x) {
+        const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+        const uint64_t a = s[i], b = s[i + j];
+        if ((a > b) == ((i & k) == 0)) {
+          s[i] = b;
+          s[i + j] = a;
         }
       }
       __syncthreads();
     }
+    regs(k, k);
+    __syncthreads();
   }
 }
 
@@ -1284,56 +1307,116 @@ __device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_t
   }
 }
 
+// Wave-aggregated append: lanes with take set get consecutive slots counted
+// by *cnt (LDS); returns this lane's slot (undefined where take is false).
+__device__ __forceinline__ int wave_append(bool take, int* cnt) {
+  const uint64_t m = __ballot(take);
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == 0 && m) base = atomicAdd(cnt, __popcll(m));
+  base = __shfl(base, 0, 64);
+  return base + __popcll(m & ((1ull << lane) - 1ull));
+}
+
 // Step 8 by the heuristic re-ranking (Alg. 1, change rate of Eq. 3): the
 // candidates s_top[0..nn), sorted ascending by (adc, id), are re-ranked in
 // mini-batches of hb; after each mini-batch the k best (distance, id) pairs
 // so far are the k smallest of (previous best, this mini-batch), and the
 // change rate is the number of their IDs absent from the previous best,
 // divided by k.  The loop stops once the rate has been <= eps for beta
-// mini-batches in a row.  k <= 64.  s_key2 holds >= nn keys, s_best 64,
-// s_cand 64 * (blockDim / 64 + 1); *reranked = candidates re-ranked.
-__device__ void rerank_heuristic(const DevIndex& ix, const float* s_q, const uint64_t* s_top,
-                                 int nn, uint64_t* s_key2, uint64_t* s_best, uint64_t* s_cand,
-                                 int* s_misc, int k, int hb, double eps, int beta,
+// mini-batches in a row; *reranked counts the candidates of the mini-batches
+// used.  Exact distances are gathered a chunk of whole mini-batches (about
+// 1024 candidates) at a time so that the loads of several mini-batches are in
+// flight together; the rule itself is evaluated mini-batch by mini-batch.
+// Per mini-batch, only keys below the current k-th best can enter the best;
+// they are merged with the best by counting ranks (after a radix select of
+// the k smallest when they are many).  k <= 64.  s_key2 holds >= nn keys;
+// s_best 64 keys; s_cand >= 256 keys; s_misc 3 ints.
+__device__ void rerank_heuristic(const DevIndex& ix, const float* s_q, uint64_t* s_top, int nn,
+                                 uint64_t* s_key2, uint64_t* s_best, uint64_t* s_cand,
+                                 int* s_misc, SelScratch* ss, int k, int hb, double eps, int beta,
                                  int64_t* out_ids, float* out_d, int32_t* reranked) {
+  constexpr int kU = 256;  // merge set: the previous best and at most kU - cur entrants
+  const int tid = threadIdx.x;
   int cur = 0, stable = 0, done = 0;
-  for (int i = 0; i < nn; i += hb) {
-    const int b = min(hb, nn - i);
-    exact_keys(ix, s_q, s_top + i, b, s_key2, b);
-    for (int t = threadIdx.x; t < cur; t += blockDim.x) s_key2[b + t] = s_best[t];  // b + cur <= nn
+  bool stop = false;
+  const int per = hb * max(1, 1024 / hb);  // candidates gathered per chunk
+  for (int c0 = 0; c0 < nn && !stop; c0 += per) {
+    const int cn = min(per, nn - c0);
+    exact_keys(ix, s_q, s_top + c0, cn, s_key2, cn);
     __syncthreads();
-    const int kk = min(k, b + cur);
-    block_topk_small(s_key2, b + cur, kk, s_cand);  // ascending in s_cand[0..kk)
-    if (threadIdx.x < 64) {  // IDs of the new best that the previous best lacked
-      const int lane = threadIdx.x;
-      bool fresh = false;
-      if (lane < kk) {
-        const uint32_t id = (uint32_t)s_cand[lane];
-        fresh = true;
-        for (int u = 0; u < cur; ++u) fresh = fresh && (uint32_t)s_best[u] != id;
+    // s_top[c0..c0+cn) has been read: it holds the entrants of each mini-batch
+    uint64_t* s_in = s_top + c0;
+    for (int i = c0; i < c0 + cn && !stop; i += hb) {  // block-uniform
+      const int b = min(hb, nn - i);
+      const uint64_t* seg = s_key2 + (i - c0);
+      const uint64_t T = cur == k ? s_best[k - 1] : ~0ull;
+      for (int t = tid; t < cur; t += blockDim.x) s_cand[t] = s_best[t];
+      if (tid == 0) s_misc[0] = s_misc[1] = s_misc[2] = 0;
+      __syncthreads();
+      for (int t0 = 0; t0 < b; t0 += blockDim.x) {  // entrants: keys below the k-th best
+        const int t = t0 + tid;
+        const uint64_t x = t < b ? seg[t] : ~0ull;
+        const bool take = x < T;
+        const int pos = wave_append(take, s_misc);
+        if (take) {
+          s_in[pos] = x;
+          if (cur + pos < kU) s_cand[cur + pos] = x;
+        }
       }
-      const uint64_t m = __ballot(fresh);
-      if (lane == 0) *s_misc = __popcll(m);
-    }
-    __syncthreads();
-    const int changed = *s_misc;
-    for (int t = threadIdx.x; t < kk; t += blockDim.x) s_best[t] = s_cand[t];
-    cur = kk;
-    done = i + b;
-    __syncthreads();
-    const double delta = (double)changed / (double)k;  // Eq. 3
-    if (delta <= eps) {
-      if (++stable >= beta) break;
-    } else {
-      stable = 0;
+      __syncthreads();
+      int m = cur + s_misc[0];
+      if (m > kU) {  // many entrants (the first mini-batches): keep their k smallest
+        const int ne = s_misc[0];
+        const uint64_t K = block_kth([&](int u) { return s_in[u]; }, ne, k, ss);
+        for (int t0 = 0; t0 < ne; t0 += blockDim.x) {
+          const int t = t0 + tid;
+          const uint64_t x = t < ne ? s_in[t] : ~0ull;
+          const bool take = t < ne && x <= K;
+          const int pos = wave_append(take, s_misc + 2);
+          if (take && cur + pos < kU) s_cand[cur + pos] = x;
+        }
+        __syncthreads();
+        m = min(kU, cur + s_misc[2]);  // k entrants when the keys are distinct
+      }
+      const int kk = min(k, m);
+      // rank of each member of the merge set (ties broken by position)
+      uint64_t x = ~0ull;
+      int r = kU;
+      if (tid < m) {
+        x = s_cand[tid];
+        r = 0;
+        for (int u = 0; u < m; ++u) {
+          const uint64_t y = s_cand[u];
+          r += (y < x) | ((y == x) & (u < tid));
+        }
+      }
+      bool fresh = false;  // an entrant in the new best whose ID the previous best lacks
+      if (tid >= cur && r < kk) {
+        fresh = true;
+        for (int u = 0; u < cur; ++u) fresh = fresh && (uint32_t)s_cand[u] != (uint32_t)x;
+      }
+      (void)wave_append(fresh, s_misc + 1);
+      __syncthreads();
+      if (r < kk) s_best[r] = x;
+      const int changed = s_misc[1];
+      cur = kk;
+      done = i + b;
+      __syncthreads();
+      const double delta = (double)changed / (double)k;  // Eq. 3
+      if (delta <= eps) {
+        if (++stable >= beta) stop = true;
+      } else {
+        stable = 0;
+      }
     }
   }
-  for (int t = threadIdx.x; t < k; t += blockDim.x) {
+  for (int t = tid; t < k; t += blockDim.x) {
     const bool v = t < cur;
     out_ids[t] = v ? (int64_t)(uint32_t)s_best[t] : -1;
     out_d[t] = v ? unord32((uint32_t)(s_best[t] >> 32)) : INFINITY;
   }
-  if (threadIdx.x == 0 && reranked) *reranked = done;
+  if (tid == 0 && reranked) *reranked = done;
 }
 
 struct MergeLayout {
@@ -1424,7 +1507,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     if (!topn_ids) block_bitonic(s_top, P);  // (already sorted when the top-n was written)
     __syncthreads();  // s_key2 aliases s_keys
     rerank_heuristic(ix, s_q, s_top, nn, s_key2, reinterpret_cast<uint64_t*>(smem + L.best),
-                     s_cand, s_cnt + 18, k, hb, h_eps, h_beta, out_ids + (size_t)q * k,
+                     s_cand, s_cnt + 18, ss, k, hb, h_eps, h_beta, out_ids + (size_t)q * k,
                      out_dists + (size_t)q * k, reranked ? reranked + q : nullptr);
   } else if (out_ids) {
     __syncthreads();  // s_key2 aliases s_keys

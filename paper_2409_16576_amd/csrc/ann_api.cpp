@@ -294,8 +294,10 @@ ann_status validate_args(ann_index* ix, const void* q, int64_t nq, int32_t np_ma
 }
 
 int chunk_queries(const DevIndex& d, int64_t nq) {
-  // the coarse-distance matrix of a chunk is the largest working buffer
-  const size_t budget = size_t(1) << 30;
+  // the coarse-distance matrix of a chunk is the largest working buffer; 4 GiB
+  // (1.4% of HBM) keeps a 16k-query chunk up to 65536 lists, so a batch of
+  // that size is one probe, one scan and one merge launch
+  const size_t budget = size_t(4) << 30;
   size_t by_dist = budget / ((size_t)d.nlist * 4);
   size_t qc = std::min<size_t>({(size_t)nq, by_dist, size_t(16384)});
   return (int)std::max<size_t>(qc, 1);

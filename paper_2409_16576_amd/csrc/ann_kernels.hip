@@ -649,17 +649,50 @@ __device__ __forceinline__ float lut_val(__half v) { return __half2float(v); }  
 // Eq. 1 for one code row: float32 sum over m = 0..M-1 in order.  The table
 // holds float32 entries, or binary16 entries (the half-precision variant,
 // widened exactly before the float32 sum).
+// Byte B of w times sizeof(T), the code's byte offset inside its subspace's
+// table: one VALU instruction (sub-dword operand select) instead of a
+// bit-field extract and a shift.  The scan issues one per code, so this is
+// most of its address arithmetic.
+#define ANN_BYTE_SCALED(SH, B)                                                            \
+  asm("v_lshlrev_b32_sdwa %0, " #SH ", %1 dst_sel:DWORD dst_unused:UNUSED_PAD "         \
+      "src0_sel:DWORD src1_sel:BYTE_" #B                                                   \
+      : "=v"(r)                                                                           \
+      : "v"(w))
+template <class T, int B>
+__device__ __forceinline__ uint32_t code_offset(uint32_t w) {
+  uint32_t r;
+  if constexpr (sizeof(T) == 4) {
+    if constexpr (B == 0) ANN_BYTE_SCALED(2, 0);
+    else if constexpr (B == 1) ANN_BYTE_SCALED(2, 1);
+    else if constexpr (B == 2) ANN_BYTE_SCALED(2, 2);
+    else ANN_BYTE_SCALED(2, 3);
+  } else {
+    if constexpr (B == 0) ANN_BYTE_SCALED(1, 0);
+    else if constexpr (B == 1) ANN_BYTE_SCALED(1, 1);
+    else if constexpr (B == 2) ANN_BYTE_SCALED(1, 2);
+    else ANN_BYTE_SCALED(1, 3);
+  }
+  return r;
+}
+#undef ANN_BYTE_SCALED
+
+template <class T, int B>
+__device__ __forceinline__ float table_at(const T* __restrict__ s_lut, int m, uint32_t w) {
+  const char* base = reinterpret_cast<const char*>(s_lut) + (size_t)m * kKsub * sizeof(T);
+  return lut_val(*reinterpret_cast<const T*>(base + code_offset<T, B>(w)));
+}
+
 template <int W, class T>
 __device__ __forceinline__ float adc_words(const uint32_t (&w)[W], const T* __restrict__ s_lut,
                                            int M) {
   float acc = 0.f;
 #pragma unroll
   for (int i = 0; i < W; ++i) {
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int m = 4 * i + b;
-      if (i < W - 1 || m < M) acc = acc + lut_val(s_lut[m * kKsub + ((w[i] >> (8 * b)) & 255u)]);
-    }
+    const int m = 4 * i;
+    if (i < W - 1 || m < M) acc = acc + table_at<T, 0>(s_lut, m, w[i]);
+    if (i < W - 1 || m + 1 < M) acc = acc + table_at<T, 1>(s_lut, m + 1, w[i]);
+    if (i < W - 1 || m + 2 < M) acc = acc + table_at<T, 2>(s_lut, m + 2, w[i]);
+    if (i < W - 1 || m + 3 < M) acc = acc + table_at<T, 3>(s_lut, m + 3, w[i]);
   }
   return acc;
 }
@@ -802,8 +835,12 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
 
   extern __shared__ __align__(16) unsigned char smem[];
   using LutT = std::conditional_t<H, __half, float>;
-  const ScanLayout L = scan_layout(M, ix.nlist, ix.R, np_max, max_runs, cap, sizeof(LutT));
-  LutT* s_lut = reinterpret_cast<LutT*>(smem + L.lut);
+  // The table is a static array sized for 4W subspaces, so its LDS address
+  // is a compile-time constant: every lookup's subspace offset folds into the
+  // load's immediate field and the code byte's offset is its whole address.
+  __shared__ __align__(16) LutT s_lut_st[4 * W * kKsub];
+  const ScanLayout L = scan_layout(M, ix.nlist, ix.R, np_max, max_runs, cap, 0);
+  LutT* s_lut = s_lut_st;
   uint32_t* s_bits = reinterpret_cast<uint32_t*>(smem + L.bits);
   int32_t* s_list = reinterpret_cast<int32_t*>(smem + L.list);
   uint32_t* s_rstart = reinterpret_cast<uint32_t*>(smem + L.rstart);
@@ -1860,8 +1897,7 @@ hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t
                          hipStream_t st) {
   const int seg = scan_segmented(ix, np_max) ? 1 : 0;
   const int max_runs = scan_runs(ix, np_max);
-  const ScanLayout L =
-      scan_layout(ix.M, ix.nlist, ix.R, np_max, max_runs, cap, (!trace && lut16) ? 2 : 4);
+  const ScanLayout L = scan_layout(ix.M, ix.nlist, ix.R, np_max, max_runs, cap, 0);
   const int qpad = (qc + 7) / 8 * 8;
   const dim3 grid((unsigned)((size_t)qpad * smax));
   if (trace) {
@@ -1907,14 +1943,19 @@ ScanFn scan_fn(int W) {
 
 int scan_smax(int n) { return std::max(1, std::min(16, 4096 / std::max(n, 1))); }
 
+// The scan kernel's static table: 4 * ceil(M / 4) subspaces of 256 entries.
+inline size_t scan_table_bytes(const DevIndex& ix, bool lut16) {
+  return (size_t)((ix.M + 3) / 4) * 4 * kKsub * (lut16 ? 2 : 4);
+}
+
 // Top-n buffer slots of a scan block: n + one round of entries at least;
 // more slack (fewer cut-backs) while the block still fits twice in a CU's LDS.
 int scan_cap(const DevIndex& ix, int np_max, int n, bool lut16) {
   constexpr size_t kTwoPerCU = 80 * 1024;
   constexpr int kRound = kScanBlock * kScanRT;
   const int base = n + kRound;
-  const size_t fixed =
-      scan_layout(ix.M, ix.nlist, ix.R, np_max, scan_runs(ix, np_max), 0, lut16 ? 2 : 4).total;
+  const size_t fixed = scan_table_bytes(ix, lut16) +
+                       scan_layout(ix.M, ix.nlist, ix.R, np_max, scan_runs(ix, np_max), 0, 0).total;
   int extra = 0;
   if (fixed + (size_t)base * 8 + 64 < kTwoPerCU)
     extra = (int)((kTwoPerCU - 64 - fixed - (size_t)base * 8) / 8) / 64 * 64;
@@ -1922,8 +1963,9 @@ int scan_cap(const DevIndex& ix, int np_max, int n, bool lut16) {
 }
 
 size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n, bool lut16) {
-  return scan_layout(ix.M, ix.nlist, ix.R, np_max, scan_runs(ix, np_max),
-                     scan_cap(ix, np_max, n, lut16), lut16 ? 2 : 4).total;
+  return scan_table_bytes(ix, lut16) + scan_layout(ix.M, ix.nlist, ix.R, np_max,
+                                                   scan_runs(ix, np_max),
+                                                   scan_cap(ix, np_max, n, lut16), 0).total;
 }
 
 static bool exact64(const DevIndex& ix) { return !ix.int_grid; }

@@ -63,7 +63,7 @@ ZIPF_F32_5M = Workload("zipf_f32_5m", 3, 5_000_000, 96, "f32", 2048, 0.0, 0.0, 0
                        sub_centres=4, sub_sigma=0.5, kmeans_iters=5, rerank_n_op=2400)
 # 100M x 100-d int8, 8192 centres U[-128,127]; 65536 lists; PQ 50 x 256.
 SERVE_I8_100M = Workload("serve_i8_100m", 5, 100_000_000, 100, "i8", 8192, -128.0, 127.0,
-                         10.0, 65536, 50, 10_000, 64, 100)
+                         10.0, 65536, 50, 10_000, 64, 100, rerank_n_op=200)
 
 ALL = {w.name: w for w in (IVF_F32_100K, IVF_U8_10M, ZIPF_F32_5M, SERVE_I8_100M)}
 

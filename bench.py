@@ -324,23 +324,30 @@ def main():
     n = args.rerank_n or w.rerank_n_op or w.rerank_n
     st = torch.cuda.current_stream(dev)
 
-    # ---- work counts (untimed): candidates scored and replica entries walked
-    _, _, ncand = g.search_topn(Q, nprobe_arg, n)
+    # ---- work counts (untimed): candidates scored and list entries walked.
+    # A probed list's first-list members are a contiguous row range (no ID is
+    # read); its replica entries (8 B each) are walked unless their whole
+    # group is skipped because the group's first list is probed too.
+    _, _, ncand, nwalk = g.search_topn(Q, nprobe_arg, n, walked=True)
     lists, _ = g.probe(Q, nprobe_arg, with_dists=False)
     torch.cuda.synchronize()
     ncand = ncand.cpu().numpy()
+    nwalk = nwalk.cpu().numpy()
     lists = lists.cpu().numpy()
     sizes, primary = builder.read_list_meta(path)
     valid = lists >= 0
     lsafe = np.where(valid, lists, 0)
     entries_q = (sizes[lsafe] * valid).sum(1)
-    rep_q = ((sizes - primary)[lsafe] * valid).sum(1)
+    prim_q = (primary[lsafe] * valid).sum(1)
+    rep_q = entries_q - prim_q
+    rep_walked = int((nwalk - prim_q).sum())
     cand_per_step = int(ncand.sum())
     M = g.desc["m"]
     row_bytes = (M + 3) // 4 * 4
-    scan_alg_bytes = cand_per_step * row_bytes + int(rep_q.sum()) * 8 + nq * M * 256 * 4
-    log(f"per step: {cand_per_step} candidates, {int(entries_q.sum())} list entries, "
-        f"{int(rep_q.sum())} replica entries; scan algorithmic bytes {scan_alg_bytes / 1e9:.2f} GB")
+    scan_alg_bytes = cand_per_step * row_bytes + rep_walked * 8 + nq * M * 256 * 4
+    log(f"per step: {cand_per_step} candidates, {int(entries_q.sum())} list entries "
+        f"({int(rep_q.sum())} replica), {int(nwalk.sum())} walked ({rep_walked} replica); "
+        f"scan algorithmic bytes {scan_alg_bytes / 1e9:.2f} GB")
 
     def step_plain():
         for b0 in range(0, nq, args.plain_batch):
@@ -439,7 +446,9 @@ def main():
                 "kernel": "k_scan (fused gather/dedup/Eq.1/top-n)",
                 "scan_ms_per_launch": round(scan_ms / scan_launches, 4),
                 "scan_launches_per_step": scan_launches,
-                "algorithmic_bytes_per_step": scan_alg_bytes}
+                "algorithmic_bytes_per_step": scan_alg_bytes,
+                "replica_entries_walked_per_step": rep_walked,
+                "replica_entries_listed_per_step": int(rep_q.sum())}
 
     line = {
         "metric": METRIC, "value": round(R["qps"], 1), "unit": "queries/s", "n_gpus": 1,

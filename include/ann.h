@@ -135,11 +135,15 @@ ann_status ann_search_heuristic(ann_index* ix, const float* d_queries, int64_t n
  * candidates (ascending by (ADC distance, id)) instead of re-ranking them.
  *   d_out_ids int32 [nq, rerank_n] (-1 padded), d_out_adc float32 [nq, rerank_n]
  *   d_out_ncand optional int64 [nq]: distinct candidates scored per query.
+ *   d_out_nwalk optional int64 [nq]: list entries the scan walked per query
+ *     (every first-list member of each probed list, plus the replica entries
+ *     it did not skip as a group because their first list is also probed);
+ *     a measure of work, not of results: it depends on the index layout.
  */
 ann_status ann_search_topn(ann_index* ix, const float* d_queries, int64_t nq,
                            const int32_t* d_nprobe, int32_t nprobe_max, int32_t rerank_n,
                            int32_t* d_out_ids, float* d_out_adc, int64_t* d_out_ncand,
-                           void* stream);
+                           int64_t* d_out_nwalk, void* stream);
 
 /*
  * Step 2 alone: the nearest lists of each query, ascending by

@@ -85,7 +85,7 @@ def lib():
         L.ann_free_index.argtypes = [P]
         L.ann_free_index.restype = None
         L.ann_search.argtypes = [P, P, i64, P, i32, i32, i32, P, P, P]
-        L.ann_search_topn.argtypes = [P, P, i64, P, i32, i32, P, P, P, P]
+        L.ann_search_topn.argtypes = [P, P, i64, P, i32, i32, P, P, P, P, P]
         L.ann_probe.argtypes = [P, P, i64, P, i32, P, P, P]
         L.ann_lut.argtypes = [P, P, i64, P, P]
         L.ann_scan_trace.argtypes = [P, P, i64, i32, P, i64, P, P, P, P]
@@ -204,17 +204,19 @@ class Index:
                                           _ptr(d), _ptr(rr), _stream(self.device, stream)))
         return ids, d, rr
 
-    def search_topn(self, queries, nprobe, rerank_n: int, stream=None):
-        """Steps 1-7: (ids int32 [nq, n], ADC distances float32 [nq, n], candidates int64 [nq])."""
+    def search_topn(self, queries, nprobe, rerank_n: int, stream=None, walked: bool = False):
+        """Steps 1-7: (ids int32 [nq, n], ADC distances float32 [nq, n], candidates int64 [nq]),
+        plus the list entries walked per query (int64 [nq]) when walked=True."""
         q = self._queries(queries)
         nq = q.shape[0]
         npt, npmax = self._nprobe(nprobe, nq)
         ids = torch.empty((nq, rerank_n), dtype=torch.int32, device=self.device)
         adc = torch.empty((nq, rerank_n), dtype=torch.float32, device=self.device)
         nc = torch.empty((nq,), dtype=torch.int64, device=self.device)
+        nw = torch.empty((nq,), dtype=torch.int64, device=self.device) if walked else None
         _check(lib().ann_search_topn(self._h, _ptr(q), nq, _ptr(npt), npmax, rerank_n, _ptr(ids),
-                                     _ptr(adc), _ptr(nc), _stream(self.device, stream)))
-        return ids, adc, nc
+                                     _ptr(adc), _ptr(nc), _ptr(nw), _stream(self.device, stream)))
+        return (ids, adc, nc, nw) if walked else (ids, adc, nc)
 
     def probe(self, queries, nprobe, with_dists: bool = True, stream=None):
         q = self._queries(queries)

@@ -169,7 +169,7 @@ ann_status ws_ensure(Workspace* ws, const Need& n) {
   WS(w.sq, g.qc * 4);
   WS(w.pkeys, g.keys * 8);
   WS(w.pcount, g.items * 4);
-  WS(w.pscan, g.items * 4);
+  WS(w.pscan, g.items * 8);
   WS(w.cand, g.cand * 4);
 #undef WS
   ws->cap_qc = g.qc; ws->cap_np = g.np; ws->cap_nlist = g.nlist; ws->cap_keys = g.keys;
@@ -607,7 +607,7 @@ struct Heur {
 ann_status run_chunk(ann_index* ix, Work& w, const float* q, int qc, const int32_t* nprobe,
                      int32_t np_max, int32_t k, int32_t n, int64_t* out_ids, float* out_d,
                      int32_t* topn_ids, float* topn_adc, int64_t* ncand, hipStream_t st,
-                     const Heur& h = Heur()) {
+                     const Heur& h = Heur(), int64_t* nwalk = nullptr) {
   const DevIndex& d = ix->d;
   LaunchCfg c = cfg_for(qc, np_max, n, k, ix->opt_tile, ix->opt_split);
   c.lut16 = ix->opt_lut16 != 0;
@@ -625,7 +625,8 @@ ann_status run_chunk(ann_index* ix, Work& w, const float* q, int qc, const int32
   }
   {
     StageMark m(ix, 3, st);
-    HIP_TRY(launch_merge(d, q, c, w, topn_ids, topn_adc, ncand, out_ids, out_d, h.reranked, st));
+    HIP_TRY(launch_merge(d, q, c, w, topn_ids, topn_adc, ncand, nwalk, out_ids, out_d, h.reranked,
+                         st));
   }
   return ANN_OK;
 }
@@ -633,7 +634,7 @@ ann_status run_chunk(ann_index* ix, Work& w, const float* q, int qc, const int32
 ann_status run_pipeline(ann_index* ix, const float* Q, int64_t nq, const int32_t* nprobe,
                         int32_t np_max, int32_t k, int32_t n, int64_t* out_ids, float* out_d,
                         int32_t* topn_ids, float* topn_adc, int64_t* ncand, hipStream_t st,
-                        const Heur& h = Heur()) {
+                        const Heur& h = Heur(), int64_t* nwalk = nullptr) {
   HIP_TRY(hipSetDevice(ix->device));
   ann_status s;
   if ((s = check_lds(ix, np_max, n)) != ANN_OK) return s;
@@ -649,7 +650,8 @@ ann_status run_pipeline(ann_index* ix, const float* Q, int64_t nq, const int32_t
                   out_ids ? out_ids + q0 * k : nullptr, out_d ? out_d + q0 * k : nullptr,
                   topn_ids ? topn_ids + q0 * n : nullptr, topn_adc ? topn_adc + q0 * n : nullptr,
                   ncand ? ncand + q0 : nullptr, st,
-                  Heur{h.batch, h.eps, h.beta, h.reranked ? h.reranked + q0 : nullptr});
+                  Heur{h.batch, h.eps, h.beta, h.reranked ? h.reranked + q0 : nullptr},
+                  nwalk ? nwalk + q0 : nullptr);
     if (s != ANN_OK) return s;
   }
   return ANN_OK;
@@ -668,7 +670,7 @@ size_t ann::work_bytes(const DevIndex& d, int qc, int np_max, int n) {
   const Need g = need_for(d, qc, np_max, n, smax);
   auto a = [](size_t b) { return align_up_sz(std::max<size_t>(b, 16), 256); };
   return a(g.qc * g.nlist * 4) + a(g.qc * g.np * 4) + a(g.qc * 4) + a(g.qc * 8) + a(g.qc * 4) +
-         a(g.keys * 8) + a(g.items * 4) + a(g.items * 4);
+         a(g.keys * 8) + a(g.items * 4) + a(g.items * 8);
 }
 
 Work ann::work_carve(const DevIndex& d, int qc, int np_max, int n, void* base) {
@@ -688,7 +690,7 @@ Work ann::work_carve(const DevIndex& d, int qc, int np_max, int n, void* base) {
   w.sq = static_cast<int32_t*>(take(g.qc * 4));
   w.pkeys = static_cast<uint64_t*>(take(g.keys * 8));
   w.pcount = static_cast<int32_t*>(take(g.items * 4));
-  w.pscan = static_cast<int32_t*>(take(g.items * 4));
+  w.pscan = static_cast<int32_t*>(take(g.items * 8));
   return w;
 }
 
@@ -760,7 +762,8 @@ extern "C" ann_status ann_search_heuristic(ann_index* ix, const float* d_queries
 extern "C" ann_status ann_search_topn(ann_index* ix, const float* d_queries, int64_t nq,
                                       const int32_t* d_nprobe, int32_t nprobe_max,
                                       int32_t rerank_n, int32_t* d_out_ids, float* d_out_adc,
-                                      int64_t* d_out_ncand, void* stream) {
+                                      int64_t* d_out_ncand, int64_t* d_out_nwalk,
+                                      void* stream) {
   ann_status s = validate_args(ix, d_queries, nq, nprobe_max);
   if (s != ANN_OK) return s;
   if (rerank_n < 1 || rerank_n > kMaxRerank)
@@ -768,7 +771,7 @@ extern "C" ann_status ann_search_topn(ann_index* ix, const float* d_queries, int
   if (nq > 0 && (!d_out_ids || !d_out_adc)) return fail(ANN_EINVAL, "output pointer is NULL");
   if (nq == 0) return ANN_OK;
   return run_pipeline(ix, d_queries, nq, d_nprobe, nprobe_max, 1, rerank_n, nullptr, nullptr,
-                      d_out_ids, d_out_adc, d_out_ncand, (hipStream_t)stream);
+                      d_out_ids, d_out_adc, d_out_ncand, (hipStream_t)stream, Heur(), d_out_nwalk);
 }
 
 extern "C" ann_status ann_probe(ann_index* ix, const float* d_queries, int64_t nq,

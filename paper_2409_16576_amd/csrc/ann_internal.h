@@ -61,7 +61,7 @@ struct Work {
   int32_t* sq = nullptr;        // [qc] work items per query
   uint64_t* pkeys = nullptr;    // [qc, smax, n] partial top-n keys
   int32_t* pcount = nullptr;    // [qc, smax]
-  int32_t* pscan = nullptr;     // [qc, smax] candidates scored per item
+  int32_t* pscan = nullptr;     // [qc, smax, 2] candidates scored, entries walked per item
   int32_t* cand = nullptr;      // [qc, n] (rerank-only entry point)
 };
 
@@ -92,8 +92,8 @@ hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const flo
                              int np_max, int64_t capacity, int32_t* out_ids, float* out_adc,
                              int64_t* out_count, Work& w, hipStream_t st);
 hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,
-                        int32_t* topn_ids, float* topn_adc, int64_t* ncand, int64_t* out_ids,
-                        float* out_dists, int32_t* reranked, hipStream_t st);
+                        int32_t* topn_ids, float* topn_adc, int64_t* ncand, int64_t* nwalk,
+                        int64_t* out_ids, float* out_dists, int32_t* reranked, hipStream_t st);
 hipError_t launch_rerank_only(const DevIndex& ix, const float* q, const int32_t* cand, int qc,
                               int n, int k, int64_t* out_ids, float* out_dists, hipStream_t st);
 

@@ -753,7 +753,7 @@ constexpr uint32_t kRunReplica = 0x80000000u;  // run start flag: replica-entry 
 // starts in s_rstart, exclusive entry offsets in s_pre[0..nruns], and
 // s_pre[nruns] = the query's entries; *s_nruns = nruns.
 __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_list, int np,
-                          const uint32_t* s_bits, int segmented, uint32_t* s_rstart,
+                          const uint32_t* s_bits, int segmented, int max_runs, uint32_t* s_rstart,
                           int32_t* s_pre, int* s_nruns) {
   const int lane = threadIdx.x & 63;
   int cnt = 0, l = 0, s0 = 0, s1 = 0;
@@ -764,18 +764,24 @@ __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_l
       s0 = ix.lseg[l];
       s1 = ix.lseg[l + 1];
       for (int s = s0; s < s1; ++s) cnt += testbit(s_bits, ix.segs[s].x) ? 0 : 1;
-    } else {
-      cnt += ix.rstart[l + 1] > ix.rstart[l] ? 1 : 0;
     }
   }
-  const int incl = (int)wave_incl_scan((uint32_t)cnt);
-  const int nruns = __shfl(incl, 63, 64);
+  int incl = (int)wave_incl_scan((uint32_t)cnt);
+  int nruns = __shfl(incl, 63, 64);
+  // groups that survive go in as runs of their own while they fit; otherwise
+  // each list's replica entries form one run, tested entry by entry
+  const bool seg = segmented && nruns <= max_runs;  // wave-uniform
+  if (!seg) {
+    cnt = lane < np ? 1 + (ix.rstart[l + 1] > ix.rstart[l] ? 1 : 0) : 0;
+    incl = (int)wave_incl_scan((uint32_t)cnt);
+    nruns = __shfl(incl, 63, 64);
+  }
   if (lane < np) {
     const int off = incl - cnt;
     s_rstart[off] = (uint32_t)ix.pstart[l];
     s_pre[off] = ix.pstart[l + 1] - ix.pstart[l];  // entry counts first
     int r = off + 1;
-    if (segmented) {
+    if (seg) {
       for (int s = s0; s < s1; ++s) {
         const int4 g = ix.segs[s];
         if (!testbit(s_bits, g.x)) {
@@ -903,12 +909,32 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   const bool wave_setup = np <= 64;
   if (wave_setup) {
     if (tid < 64) {
-      runs_wave(ix, s_list, np, s_bits, segmented, s_rstart, s_pre, &s_wsum[kScanBlock / 64]);
+      runs_wave(ix, s_list, np, s_bits, segmented, max_runs, s_rstart, s_pre,
+                &s_wsum[kScanBlock / 64]);
     } else {
       for (int i = tid - 64; i < M * kKsub; i += kScanBlock - 64) table_entry(i);
     }
     __syncthreads();
     nruns = s_wsum[kScanBlock / 64];
+  }
+  bool seg = segmented != 0;  // as in runs_wave: surviving groups as runs while they fit
+  if (!wave_setup && seg) {
+    int tot = 0;
+    for (int p0 = 0; p0 < np; p0 += kScanBlock) {  // uniform trip count
+      const int p = p0 + tid;
+      int cnt = 0;
+      if (p < np) {
+        const int l = s_list[p];
+        cnt = 1;
+        for (int s = ix.lseg[l]; s < ix.lseg[l + 1]; ++s) cnt += testbit(s_bits, ix.segs[s].x) ? 0 : 1;
+      }
+      const int off = block_excl_scan(cnt, s_wsum);
+      if (tid == kScanBlock - 1) s_wsum[kScanBlock / 64] = off + cnt;
+      __syncthreads();
+      tot += s_wsum[kScanBlock / 64];
+      __syncthreads();
+    }
+    seg = tot <= max_runs;
   }
   for (int p0 = 0; !wave_setup && p0 < np; p0 += kScanBlock) {  // uniform trip count
     const int p = p0 + tid;
@@ -916,7 +942,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     if (p < np) {
       l = s_list[p];
       cnt = 1;
-      if (segmented) {
+      if (seg) {
         for (int s = ix.lseg[l]; s < ix.lseg[l + 1]; ++s) cnt += testbit(s_bits, ix.segs[s].x) ? 0 : 1;
       } else {
         cnt += ix.rstart[l + 1] > ix.rstart[l] ? 1 : 0;
@@ -927,7 +953,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
       s_rstart[off] = (uint32_t)ix.pstart[l];
       s_pre[off] = ix.pstart[l + 1] - ix.pstart[l];  // entry count, turned into offsets below
       int r = off + 1;
-      if (segmented) {
+      if (seg) {
         for (int s = ix.lseg[l]; s < ix.lseg[l + 1]; ++s) {
           const int4 g = ix.segs[s];
           if (!testbit(s_bits, g.x)) {
@@ -1088,7 +1114,8 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     for (int i = tid; i < cnt; i += kScanBlock) dst[i] = s_buf[i];
     if (tid == 0) {
       pcount[(size_t)q * smax + j] = cnt;
-      pscan[(size_t)q * smax + j] = mc->scanned;
+      pscan[2 * ((size_t)q * smax + j)] = mc->scanned;
+      pscan[2 * ((size_t)q * smax + j) + 1] = e1 - e0;  // entries walked
     }
   }
 }
@@ -1481,7 +1508,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     DevIndex ix, const float* __restrict__ Q, int qc, const int32_t* __restrict__ sq, int smax,
     int n, int k, const uint64_t* __restrict__ pkeys, const int32_t* __restrict__ pcount,
     const int32_t* __restrict__ pscan, int32_t* __restrict__ topn_ids, float* __restrict__ topn_adc,
-    int64_t* __restrict__ ncand, int64_t* __restrict__ out_ids, float* __restrict__ out_dists,
+    int64_t* __restrict__ ncand, int64_t* __restrict__ nwalk, int64_t* __restrict__ out_ids,
+    float* __restrict__ out_dists,
     int hb, double h_eps, int h_beta, int32_t* __restrict__ reranked) {
   extern __shared__ __align__(16) unsigned char smem[];
   const MergeLayout L = merge_layout(smax, n, ix.dim);
@@ -1499,15 +1527,17 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   for (int t = tid; t < ix.dim; t += BS) s_q[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
   if (tid == 0) {
     int acc = 0;
-    int64_t sc = 0;
+    int64_t sc = 0, sw = 0;
     for (int j = 0; j < S; ++j) {
       s_off[j] = acc;
       acc += pcount[(size_t)q * smax + j];
-      sc += pscan[(size_t)q * smax + j];
+      sc += pscan[2 * ((size_t)q * smax + j)];
+      sw += pscan[2 * ((size_t)q * smax + j) + 1];
     }
     s_off[S] = acc;
     *s_cnt = 0;
     if (ncand) ncand[q] = sc;
+    if (nwalk) nwalk[q] = sw;
   }
   __syncthreads();
   const int total = s_off[S];
@@ -1880,12 +1910,14 @@ __global__ __launch_bounds__(kScanBlock) void k_order(const int32_t* __restrict_
 // Segmented replica runs when their LDS bound stays small.
 constexpr int kMaxSegRuns = 1024;
 
-inline bool scan_segmented(const DevIndex& ix, int np_max) {
-  return ix.segs != nullptr && scan_max_runs(np_max, ix.max_segs, true) <= kMaxSegRuns;
-}
+// Run slots of a scan block: room for every list's surviving replica groups
+// when that worst case is small, else two runs per probed list, in which case
+// a query's groups become runs only when they fit (the block checks).
+inline bool scan_segmented(const DevIndex& ix, int) { return ix.segs != nullptr; }
 
 inline int scan_runs(const DevIndex& ix, int np_max) {
-  return scan_max_runs(np_max, ix.max_segs, scan_segmented(ix, np_max));
+  const int worst = scan_max_runs(np_max, ix.max_segs, true);
+  return ix.segs != nullptr && worst <= kMaxSegRuns ? worst : scan_max_runs(np_max, 0, false);
 }
 
 template <int W>
@@ -2052,8 +2084,8 @@ hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const flo
 }
 
 hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,
-                        int32_t* topn_ids, float* topn_adc, int64_t* ncand, int64_t* out_ids,
-                        float* out_dists, int32_t* reranked, hipStream_t st) {
+                        int32_t* topn_ids, float* topn_adc, int64_t* ncand, int64_t* nwalk,
+                        int64_t* out_ids, float* out_dists, int32_t* reranked, hipStream_t st) {
   if (c.qc <= 0) return hipSuccess;
   const MergeLayout L = merge_layout(c.smax, c.n, ix.dim);
   // more threads only pay off when there are many candidates to re-rank
@@ -2062,7 +2094,7 @@ hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, 
   if (L.total > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
   hipLaunchKernelGGL(kern, dim3(c.qc), dim3(big ? kMergeBlock : 256), L.total, st, ix, q, c.qc, w.sq, c.smax,
-                     c.n, c.k, w.pkeys, w.pcount, w.pscan, topn_ids, topn_adc, ncand, out_ids,
+                     c.n, c.k, w.pkeys, w.pcount, w.pscan, topn_ids, topn_adc, ncand, nwalk, out_ids,
                      out_dists, c.hb, c.h_eps, c.h_beta, reranked);
   return hipGetLastError();
 }

@@ -1179,20 +1179,22 @@ __device__ void rerank_int16(const DevIndex& ix, const float* s_q, const uint64_
   constexpr int U = 4;
   for (int i0 = 0; i0 < P; i0 += ngrp * U) {
     uint4 v[U];
-    uint32_t id[U];
+    uint32_t id[U], row[U];
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = i0 + u * ngrp + grp;
       ok[u] = i < nn;
-      id[u] = ok[u] ? (uint32_t)s_top[i] : 0u;
+      const uint64_t t = ok[u] ? s_top[i] : 0ull;
+      id[u] = (uint32_t)t;
+      row[u] = (uint32_t)(t >> 32);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       v[u] = make_uint4(0u, 0u, 0u, 0u);
       if (ok[u])
         v[u] = *reinterpret_cast<const uint4*>(static_cast<const uint8_t*>(ix.vecs) +
-                                               (size_t)ix.ext2row[id[u]] * ix.dim + lg * 16);
+                                               (size_t)row[u] * ix.dim + lg * 16);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -1230,59 +1232,35 @@ __device__ void rerank_int16(const DevIndex& ix, const float* s_q, const uint64_
   }
 }
 
-// The kk <= 64 smallest of the distinct keys s_key[0..nn), ascending, by
-// repeated wave minima: each wave extracts the kk smallest of its share into
-// s_cand (each lane caches the minimum of its strided keys and rescans only
-// when its key is taken), then wave 0 extracts the kk smallest of those.
-// Keys of s_key are consumed (overwritten with ~0).  Results: s_cand[0..kk).
-__device__ __forceinline__ void wave_take_min(uint64_t* s_key, int i0, int i1, int kk,
-                                                  uint64_t* out) {
-  const int lane = threadIdx.x & 63;
-  uint64_t mn = ~0ull;
-  int mi = -1;
-  auto rescan = [&]() {
-    mn = ~0ull;
-    mi = -1;
-    for (int i = i0 + lane; i < i1; i += 64) {
-      const uint64_t v = s_key[i];
-      if (v < mn) {
-        mn = v;
-        mi = i;
-      }
-    }
-  };
-  rescan();
-  for (int r = 0; r < kk; ++r) {
-    uint64_t m = mn;
+// The row of each candidate s_top[0..nn) (external ID in the low half) into
+// the high half, every lookup of the block in flight at once, so the gathers
+// that follow wait on one memory round trip instead of two.  The caller
+// synchronises before the rows are read.
+__device__ __forceinline__ void attach_rows(const DevIndex& ix, uint64_t* s_top, int nn) {
+  constexpr int U = 4;
+  for (int i0 = 0; i0 < nn; i0 += U * (int)blockDim.x) {  // uniform trip count
+    uint32_t id[U];
+    int row[U];
 #pragma unroll
-    for (int d = 32; d > 0; d >>= 1) {
-      const uint64_t o = __shfl_xor(m, d, 64);
-      m = o < m ? o : m;
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+      id[u] = i < nn ? (uint32_t)s_top[i] : 0u;
     }
-    if (lane == 0) out[r] = m;
-    if (m != ~0ull && mn == m) {  // keys are distinct: exactly one lane holds it
-      s_key[mi] = ~0ull;
-      rescan();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+      row[u] = i < nn ? ix.ext2row[id[u]] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+      if (i < nn) s_top[i] = ((uint64_t)(uint32_t)row[u] << 32) | id[u];
     }
   }
 }
 
-__device__ void block_topk_small(uint64_t* s_key, int nn, int kk, uint64_t* s_cand) {
-  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int chunk = (nn + nw - 1) / nw;
-  const int i0 = min(nn, w * chunk), i1 = min(nn, i0 + chunk);
-  wave_take_min(s_key, i0, i1, kk, s_cand + kk * (w + 1));
-  __syncthreads();
-  if (w == 0) wave_take_min(s_cand + kk, 0, kk * nw, kk, s_cand);
-  __syncthreads();
-}
-
-// Re-rank s_top[0..nn) (keys of (adc, id)) by exact distance and write the
-// top-k, sorted.  s_key2 holds P >= nn keys; s_top is reused for the result
-// (it needs pow2_at_least(min(k, nn)) slots); s_cand holds
-// 64 * (blockDim / 64 + 1) keys.
-// Exact keys (squared distance, id) of the candidates s_top[0..nn) (keys of
-// (adc, id)) into s_key2[0..P), P >= nn, ~0 beyond nn.
+// Exact keys (distance << 32 | external ID) of the candidates s_top[0..nn),
+// whose rows attach_rows has put in the high halves; s_key2[nn..P) = ~0.
 __device__ void exact_keys(const DevIndex& ix, const float* s_q, const uint64_t* s_top, int nn,
                            uint64_t* s_key2, int P) {
   const int g16 = ix.dim % 16 == 0 ? ix.dim / 16 : 0;
@@ -1306,7 +1284,7 @@ __device__ void exact_keys(const DevIndex& ix, const float* s_q, const uint64_t*
       if (i < nn) {
         id = (uint32_t)s_top[i];
         const uint32_t* x = reinterpret_cast<const uint32_t*>(
-            static_cast<const uint8_t*>(ix.vecs) + (size_t)ix.ext2row[id] * ix.dim);
+            static_cast<const uint8_t*>(ix.vecs) + (size_t)(uint32_t)(s_top[i] >> 32) * ix.dim);
         for (int t = jl; t < nd; t += 8) {
           const uint32_t v = x[t];
 #pragma unroll
@@ -1329,7 +1307,7 @@ __device__ void exact_keys(const DevIndex& ix, const float* s_q, const uint64_t*
       uint64_t key = ~0ull;
       if (i < nn) {
         const uint32_t id = (uint32_t)s_top[i];
-        const float e = exact_row(ix, s_q, ix.ext2row[id]);
+        const float e = exact_row(ix, s_q, (int)(uint32_t)(s_top[i] >> 32));
         key = ((uint64_t)ord32(e) << 32) | id;
       }
       s_key2[i] = key;
@@ -1337,18 +1315,19 @@ __device__ void exact_keys(const DevIndex& ix, const float* s_q, const uint64_t*
   }
 }
 
+// Re-rank s_top[0..nn) (keys of (adc, id)) by exact distance and write the
+// top-k, sorted.  s_key2 holds P >= nn keys; s_top is reused for the result
+// (it needs pow2_at_least(min(k, nn)) slots).
 __device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_top, int nn,
                              uint64_t* s_key2, int P, int k, int64_t* out_ids, float* out_d,
-                             SelScratch* ss, int* s_cnt, uint64_t* s_cand) {
+                             SelScratch* ss, int* s_cnt) {
+  attach_rows(ix, s_top, nn);
+  __syncthreads();
   exact_keys(ix, s_q, s_top, nn, s_key2, P);
   __syncthreads();
-  // the kk smallest keys, ascending
+  // the kk smallest keys, ascending: select the kk-th, collect, sort kk
   const int kk = min(k, nn);
-  if (kk > 0 && kk <= 64) {
-    block_topk_small(s_key2, nn, kk, s_cand);
-    for (int i = threadIdx.x; i < kk; i += blockDim.x) s_top[i] = s_cand[i];
-    __syncthreads();
-  } else if (kk > 0) {  // select the kk-th, collect, sort kk
+  if (kk > 0) {
     const int pk = pow2_at_least(kk);
     const uint64_t K = kk == nn ? ~0ull : block_kth([&](int i) { return s_key2[i]; }, nn, kk, ss);
     if (threadIdx.x == 0) *s_cnt = 0;
@@ -1407,6 +1386,8 @@ __device__ void rerank_heuristic(const DevIndex& ix, const float* s_q, uint64_t*
   const int per = hb * max(1, 1024 / hb);  // candidates gathered per chunk
   for (int c0 = 0; c0 < nn && !stop; c0 += per) {
     const int cn = min(per, nn - c0);
+    attach_rows(ix, s_top + c0, cn);  // rows of this chunk only: the loop may stop early
+    __syncthreads();
     exact_keys(ix, s_q, s_top + c0, cn, s_key2, cn);
     __syncthreads();
     // s_top[c0..c0+cn) has been read: it holds the entrants of each mini-batch
@@ -1496,14 +1477,16 @@ __host__ __device__ inline MergeLayout merge_layout(int smax, int n, int dim) {
   L.top = o; o += (size_t)P * 8;
   L.q = o; o += (size_t)dim * 4; o = align_up(o, 16);
   L.sel = o; o += sizeof(SelScratch); o = align_up(o, 16);
-  L.cand = o; o += (size_t)64 * (kMergeBlock / 64 + 1) * 8;
+  L.cand = o; o += (size_t)256 * 8;  // the heuristic re-ranking's merge set
   L.best = o; o += 64 * 8;
   L.misc = o; o += 16 + 4 * 18;
   L.total = align_up(o, 16);
   return L;
 }
 
-template <int BS>
+// HEUR: step 8 by the heuristic re-ranking (a kernel of its own, so the
+// plain form's registers are not sized for it).
+template <int BS, bool HEUR>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_merge(
     DevIndex ix, const float* __restrict__ Q, int qc, const int32_t* __restrict__ sq, int smax,
     int n, int k, const uint64_t* __restrict__ pkeys, const int32_t* __restrict__ pcount,
@@ -1570,16 +1553,17 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
       topn_adc[(size_t)q * n + i] = v ? unord32((uint32_t)(s_top[i] >> 32)) : INFINITY;
     }
   }
-  if (out_ids && hb > 0) {  // heuristic re-ranking: candidates in ascending ADC order
+  if (!out_ids) return;
+  if constexpr (HEUR) {  // heuristic re-ranking: candidates in ascending ADC order
     if (!topn_ids) block_bitonic(s_top, P);  // (already sorted when the top-n was written)
     __syncthreads();  // s_key2 aliases s_keys
     rerank_heuristic(ix, s_q, s_top, nn, s_key2, reinterpret_cast<uint64_t*>(smem + L.best),
                      s_cand, s_cnt + 18, ss, k, hb, h_eps, h_beta, out_ids + (size_t)q * k,
                      out_dists + (size_t)q * k, reranked ? reranked + q : nullptr);
-  } else if (out_ids) {
+  } else {
     __syncthreads();  // s_key2 aliases s_keys
     rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k,
-                 out_dists + (size_t)q * k, ss, s_cnt, s_cand);
+                 out_dists + (size_t)q * k, ss, s_cnt);
   }
 }
 
@@ -1593,8 +1577,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   const int P = pow2_at_least(n);
   uint64_t* s_top = reinterpret_cast<uint64_t*>(smem);
   uint64_t* s_key2 = s_top + P;
-  uint64_t* s_cand = s_key2 + P;  // 64 * (kMergeBlock / 64 + 1)
-  float* s_q = reinterpret_cast<float*>(s_cand + 64 * (kMergeBlock / 64 + 1));
+  float* s_q = reinterpret_cast<float*>(s_key2 + P);
   int* s_cnt = reinterpret_cast<int*>(s_q + ix.dim);
   const int q = blockIdx.x, tid = threadIdx.x;
   for (int t = tid; t < ix.dim; t += BS) s_q[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
@@ -1608,7 +1591,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   const int nn = *s_cnt;
   __shared__ SelScratch ss;
   rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k, out_dists + (size_t)q * k,
-               &ss, s_cnt, s_cand);
+               &ss, s_cnt);
 }
 
 // Step 2 on integer-grid indexes without materialising the distance matrix:
@@ -2090,7 +2073,9 @@ hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, 
   const MergeLayout L = merge_layout(c.smax, c.n, ix.dim);
   // more threads only pay off when there are many candidates to re-rank
   const bool big = c.n > 512;
-  auto kern = big ? k_merge<kMergeBlock> : k_merge<256>;
+  const bool heur = c.hb > 0 && out_ids;
+  auto kern = heur ? (big ? k_merge<kMergeBlock, true> : k_merge<256, true>)
+                   : (big ? k_merge<kMergeBlock, false> : k_merge<256, false>);
   if (L.total > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
   hipLaunchKernelGGL(kern, dim3(c.qc), dim3(big ? kMergeBlock : 256), L.total, st, ix, q, c.qc, w.sq, c.smax,
@@ -2103,8 +2088,7 @@ hipError_t launch_rerank_only(const DevIndex& ix, const float* q, const int32_t*
                               int n, int k, int64_t* out_ids, float* out_dists, hipStream_t st) {
   if (qc <= 0) return hipSuccess;
   const int P = pow2_at_least(n);
-  const size_t lds = (size_t)P * 16 + (size_t)64 * (kMergeBlock / 64 + 1) * 8 +
-                     (size_t)ix.dim * 4 + 16;
+  const size_t lds = (size_t)P * 16 + (size_t)ix.dim * 4 + 16;
   const bool big = n > 512;
   auto kern = big ? k_rerank_only<kMergeBlock> : k_rerank_only<256>;
   if (lds > 65536)

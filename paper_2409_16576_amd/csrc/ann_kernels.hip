@@ -1595,14 +1595,16 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
 }
 
 // Step 2 on integer-grid indexes without materialising the distance matrix:
-// a block takes kFQ = 8 queries (one 16-row MFMA tile, rows 8..15 zero) through
-// every list tile of 256 lists (int8 MFMA, same exact arithmetic as
-// k_probe_mfma), keeps each query's keys
-// (ordered distance bits, list) below its running threshold in an LDS buffer,
-// and cuts a buffer back to its NP smallest keys when another tile might not
-// fit.  At the end the NP smallest of each query come out ascending.
-constexpr int kFQ = 8;
-constexpr int kFTile = 256;
+// a block takes kFQ = 16 queries (the rows of one MFMA tile) through every
+// list tile of 128 lists (int8 MFMA, same exact arithmetic as k_probe_mfma),
+// keeps each query's keys (ordered distance bits, list) below its running
+// threshold in an LDS buffer, and cuts a buffer back to its NP smallest keys
+// when another tile might not fit.  At the end the NP smallest of each query
+// come out ascending.  16 queries per block keep a 10k-query batch within
+// one round of resident blocks (3 per CU at NP = 64).
+constexpr int kFQ = 16;
+constexpr int kFTile = 128;
+constexpr int kFCols = kFTile / 4 / 16;  // 16-list MFMA column blocks per wave and tile
 constexpr int kFusedMinQueries = 4096;
 
 template <int NP>
@@ -1756,58 +1758,62 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int r16 = lane & 15, g = lane >> 4;
   int qn[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) qn[r] = 4 * g + r < kFQ ? s_qn[4 * g + r] : 0;
-  const bool rows = 4 * g < kFQ;  // this lane's output rows are real queries
+  for (int r = 0; r < 4; ++r) qn[r] = s_qn[4 * g + r];
   // KS = dim_pad / 64 K-steps.  The query fragments stay in registers; the
-  // centroid fragments of the next list tile are loaded while this one is
-  // being filtered (software pipelining across tiles).
+  // centroid fragments and norms of the next list tile are loaded while this
+  // one is being filtered (software pipelining across tiles).
   v4i_t fa[KS];
 #pragma unroll
   for (int k = 0; k < KS; ++k)
     fa[k] = *reinterpret_cast<const v4i_t*>(s_q8 + r16 * Dp + 64 * k + 16 * g);
-  v4i_t fn[KS][4];
+  v4i_t fn[KS][kFCols];
+  int cnn[kFCols];
   auto load_tile = [&](int t0) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int l = t0 + w * 64 + b * 16 + r16;
+    for (int b = 0; b < kFCols; ++b) {
+      const int l = t0 + w * (kFTile / 4) + b * 16 + r16;
 #pragma unroll
       for (int k = 0; k < KS; ++k)
         fn[k][b] = l < ix.nlist
                        ? *reinterpret_cast<const v4i_t*>(ix.cent8 + (size_t)l * Dp + 64 * k + 16 * g)
                        : v4i_t{0, 0, 0, 0};
+      cnn[b] = l < ix.nlist ? ix.cnorm8[l] : 0;
     }
   };
   load_tile(0);
   for (int t0 = 0; t0 < ix.nlist; t0 += kFTile) {
-    const int l0 = t0 + w * 64;
-    v4i_t fb[KS][4];
+    const int l0 = t0 + w * (kFTile / 4);
+    v4i_t fb[KS][kFCols];
+    int cnb[kFCols];
 #pragma unroll
-    for (int k = 0; k < KS; ++k)
+    for (int b = 0; b < kFCols; ++b) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) fb[k][b] = fn[k][b];
+      for (int k = 0; k < KS; ++k) fb[k][b] = fn[k][b];
+      cnb[b] = cnn[b];
+    }
     if (t0 + kFTile < ix.nlist) load_tile(t0 + kFTile);
-    v4i_t acc[4];
+    v4i_t acc[kFCols];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = v4i_t{0, 0, 0, 0};
+    for (int b = 0; b < kFCols; ++b) acc[b] = v4i_t{0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < KS; ++k)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < kFCols; ++b)
         acc[b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[k], fb[k][b], acc[b], 0, 0, 0);
     // thresholds as (distance, list) integer pairs: the distances are exact
     // non-negative integers, so comparing them as ints orders like the keys
     int dT[4], lT[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const uint64_t t = rows ? s_thr[4 * g + r] : 0ull;
+      const uint64_t t = s_thr[4 * g + r];
       dT[r] = t == ~0ull ? INT_MAX : (int)unord32((uint32_t)(t >> 32));
       lT[r] = t == ~0ull ? INT_MAX : (int)(uint32_t)t;
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < kFCols; ++b) {
       const int l = l0 + b * 16 + r16;  // output column = lane % 16
-      if (!rows || l >= ix.nlist) continue;
-      const int cn = ix.cnorm8[l];
+      if (l >= ix.nlist) continue;
+      const int cn = cnb[b];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {  // output row = 4 * (lane / 16) + r
         const int d = qn[r] + cn - 2 * acc[b][r];

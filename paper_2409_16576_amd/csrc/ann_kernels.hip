@@ -597,7 +597,7 @@ struct ScanMisc {
   int count;
   int ncount;
   int scanned;
-  int pad;
+  int done;  // waves that have walked all their entries
 };
 
 // Exclusive prefix sum of v over the block (in thread order); s_wsum holds
@@ -707,10 +707,13 @@ constexpr int kCompactChunk = 8;  // cap <= kCompactChunk * kScanBlock
 // (n or a few more keys: ties at that distance are not broken by id), which
 // resolves only the distance half of the keys; the threshold stays valid (it
 // is never below the n-th smallest key).  Exact: keep exactly the n smallest.
-__device__ __forceinline__ void scan_compact(uint64_t* s_buf, int* s_wsum, SelScratch* ss, ScanMisc* mc, int n,
-                                             bool loose = false) {
+// Returns the buffer's count afterwards, the same value in every thread (read
+// between two barriers, before any wave can insert again).  Call with every
+// wave of the block present and none inserting.
+__device__ __forceinline__ int scan_compact(uint64_t* s_buf, int* s_wsum, SelScratch* ss, ScanMisc* mc, int n,
+                                            bool loose = false) {
   const int cnt = mc->count;
-  if (cnt <= n) return;
+  if (cnt <= n) return cnt;
   const uint64_t K =
       loose ? (block_kth([&](int i) { return s_buf[i] & 0xffffffff00000000ull; }, cnt, n, ss, 32) |
                0xffffffffull)
@@ -740,6 +743,9 @@ __device__ __forceinline__ void scan_compact(uint64_t* s_buf, int* s_wsum, SelSc
     mc->thr = K;
   }
   __syncthreads();
+  const int out = mc->count;
+  __syncthreads();
+  return out;
 }
 
 // One block = one work item (a contiguous range of one query's gathered
@@ -867,6 +873,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     mc->thr = ~0ull;
     mc->count = 0;
     mc->scanned = 0;
+    mc->done = 0;
   }
   // The distance table is computed here (step 1 fused into the scan) unless
   // the caller passed one in; the converted query is staged in the (still
@@ -1002,100 +1009,121 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   const uint64_t lanemask = (1ull << lane) - 1ull;
   int scanned = 0;
   int cur = 0;  // run of this thread's current entry (entries only increase)
-  // The block synchronises (and may cut its buffer back) every K rounds, K
-  // as large as the buffer's slack above n allows (at most 3).
+  // Each wave walks its part of every round (kScanRT entries per lane) at its
+  // own pace; the block meets only when some wave has seen the buffer above
+  // T = cap - kRound, or has finished.  A wave inserts at most kScanRT * 64
+  // keys per round and checks the count after each round, so once the count
+  // passes T every wave adds at most one more round before it meets: the
+  // count never exceeds cap.  At a meeting the decision (cut back? all
+  // done?) is read between two barriers, so every wave takes the same path
+  // and every meeting is reached by every wave.
   constexpr int kRound = kScanBlock * kScanRT;
-  const int K = TRACE ? 1 : max(1, min(3, (cap - n) / kRound));
-  int rr = 0;
+  const int T = cap - kRound;
+  int base = e0;
+  bool wdone = base >= e1;
+  bool counted = false;
 
-  for (int base = e0; base < e1; base += kRound) {
-    const uint64_t thr = mc->thr;
-    const uint32_t thr_hi = (uint32_t)(thr >> 32);
-    int rows[kScanRT];
-    bool keep[kScanRT];
-    // resolve entries -> rows; replica entries owned by an earlier probed list are dropped
+  for (;;) {
+    if (!wdone) {
+      const uint64_t thr = mc->thr;
+      const uint32_t thr_hi = (uint32_t)(thr >> 32);
+      int rows[kScanRT];
+      bool keep[kScanRT];
+      // resolve entries -> rows; replica entries owned by an earlier probed list are dropped
 #pragma unroll
-    for (int u = 0; u < kScanRT; ++u) {
-      const int e = base + u * kScanBlock + tid;
-      keep[u] = false;
-      rows[u] = 0;
-      if (e < e1) {
-        while (s_pre[cur + 1] <= e) ++cur;  // s_pre[nruns] = E > e bounds the walk
-        const int o = e - s_pre[cur];
-        const uint32_t rs = s_rstart[cur];
-        if (!(rs & kRunReplica)) {
-          rows[u] = (int)rs + o;
-          keep[u] = true;
-        } else {
-          const int2 r = ix.rep[(int)(rs & ~kRunReplica) + o];
-          const int row = (int)((uint32_t)r.x & kRowMask);
-          const int rank = (int)((uint32_t)r.x >> kRankShift);
-          bool k = !testbit(s_bits, r.y);
-          for (int i = 1; i < rank && k; ++i)
-            k = !testbit(s_bits, ix.assign_rows[(size_t)row * ix.R + i]);
-          rows[u] = row;
-          keep[u] = k;
+      for (int u = 0; u < kScanRT; ++u) {
+        const int e = base + u * kScanBlock + tid;
+        keep[u] = false;
+        rows[u] = 0;
+        if (e < e1) {
+          while (s_pre[cur + 1] <= e) ++cur;  // s_pre[nruns] = E > e bounds the walk
+          const int o = e - s_pre[cur];
+          const uint32_t rs = s_rstart[cur];
+          if (!(rs & kRunReplica)) {
+            rows[u] = (int)rs + o;
+            keep[u] = true;
+          } else {
+            const int2 r = ix.rep[(int)(rs & ~kRunReplica) + o];
+            const int row = (int)((uint32_t)r.x & kRowMask);
+            const int rank = (int)((uint32_t)r.x >> kRankShift);
+            bool k = !testbit(s_bits, r.y);
+            for (int i = 1; i < rank && k; ++i)
+              k = !testbit(s_bits, ix.assign_rows[(size_t)row * ix.R + i]);
+            rows[u] = row;
+            keep[u] = k;
+          }
         }
       }
-    }
-    // all code-row loads of the round in flight together
-    uint32_t cw[kScanRT][W];
+      // all code-row loads of the round in flight together
+      uint32_t cw[kScanRT][W];
 #pragma unroll
-    for (int u = 0; u < kScanRT; ++u) {
-      if (keep[u]) {
-        load_row<W>(ix.codes + (size_t)rows[u] * ix.row_bytes, cw[u]);
-      } else {
+      for (int u = 0; u < kScanRT; ++u) {
+        if (keep[u]) {
+          load_row<W>(ix.codes + (size_t)rows[u] * ix.row_bytes, cw[u]);
+        } else {
 #pragma unroll
-        for (int i = 0; i < W; ++i) cw[u][i] = 0u;
+          for (int i = 0; i < W; ++i) cw[u][i] = 0u;
+        }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < kScanRT; ++u) {
-      const float acc = adc_words<W, LutT>(cw[u], s_lut, M);
-      scanned += keep[u] ? 1 : 0;
-      if constexpr (TRACE) {
-        const uint64_t m = __ballot(keep[u]);
-        if (m) {
-          unsigned long long bpos = 0;
-          if (lane == 0) bpos = atomicAdd(&t_count[q], (unsigned long long)__popcll(m));
-          bpos = __shfl(bpos, 0, 64);
-          if (keep[u]) {
-            const unsigned long long pos = bpos + __popcll(m & lanemask);
-            if ((int64_t)pos < t_capacity) {
-              t_ids[(size_t)q * t_capacity + pos] = ix.row2ext[rows[u]];
-              t_adc[(size_t)q * t_capacity + pos] = acc;
+      for (int u = 0; u < kScanRT; ++u) {
+        const float acc = adc_words<W, LutT>(cw[u], s_lut, M);
+        scanned += keep[u] ? 1 : 0;
+        if constexpr (TRACE) {
+          const uint64_t m = __ballot(keep[u]);
+          if (m) {
+            unsigned long long bpos = 0;
+            if (lane == 0) bpos = atomicAdd(&t_count[q], (unsigned long long)__popcll(m));
+            bpos = __shfl(bpos, 0, 64);
+            if (keep[u]) {
+              const unsigned long long pos = bpos + __popcll(m & lanemask);
+              if ((int64_t)pos < t_capacity) {
+                t_ids[(size_t)q * t_capacity + pos] = ix.row2ext[rows[u]];
+                t_adc[(size_t)q * t_capacity + pos] = acc;
+              }
             }
           }
-        }
-      } else {
-        bool pass = false;
-        uint64_t key = 0;
-        if (keep[u]) {
-          const uint32_t h = ord32(acc);
-          if (h <= thr_hi) {
-            key = ((uint64_t)h << 32) | (uint32_t)ix.row2ext[rows[u]];
-            pass = key < thr;
+        } else {
+          bool pass = false;
+          uint64_t key = 0;
+          if (keep[u]) {
+            const uint32_t h = ord32(acc);
+            if (h <= thr_hi) {
+              key = ((uint64_t)h << 32) | (uint32_t)ix.row2ext[rows[u]];
+              pass = key < thr;
+            }
+          }
+          const uint64_t m = __ballot(pass);
+          if (m) {
+            int bpos = 0;
+            if (lane == 0) bpos = atomicAdd(&mc->count, (int)__popcll(m));
+            bpos = __shfl(bpos, 0, 64);
+            const int pos = bpos + __popcll(m & lanemask);
+            if (pass && pos < cap) s_buf[pos] = key;  // (pos < cap always holds, see above)
           }
         }
-        const uint64_t m = __ballot(pass);
-        if (m) {
-          int bpos = 0;
-          if (lane == 0) bpos = atomicAdd(&mc->count, (int)__popcll(m));
-          bpos = __shfl(bpos, 0, 64);
-          if (pass) s_buf[bpos + __popcll(m & lanemask)] = key;
-        }
       }
+      base += kRound;
+      wdone = base >= e1;
     }
-    if (++rr == K || base + kRound >= e1) {  // uniform over the block
-      rr = 0;
+    bool meet = wdone;
+    if constexpr (!TRACE)
+      meet = meet || __hip_atomic_load(&mc->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > T;
+    if (meet) {  // wave-uniform
+      if (wdone && !counted) {
+        if (lane == 0) atomicAdd(&mc->done, 1);
+        counted = true;
+      }
       __syncthreads();
+      const bool all = mc->done == kScanBlock / 64;
+      const bool cut = !TRACE && !all && mc->count > T;
+      __syncthreads();
+      if (all) break;
       if constexpr (!TRACE) {
-        // cut back to about the n best only when the next K rounds might not
-        // fit (by distance alone; exactly when ties at the cut would not fit)
-        if (mc->count > cap - K * kRound) {
-          scan_compact(s_buf, s_wsum, ss, mc, n, true);
-          if (mc->count > cap - K * kRound) scan_compact(s_buf, s_wsum, ss, mc, n);
-        }
+        // cut back to about the n best (by distance alone; exactly when ties
+        // at the cut would still leave the count above T)
+        if (cut && scan_compact(s_buf, s_wsum, ss, mc, n, true) > T)
+          scan_compact(s_buf, s_wsum, ss, mc, n);
       }
     }
   }

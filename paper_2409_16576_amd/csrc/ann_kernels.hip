@@ -1853,17 +1853,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
       }
     }
     __syncthreads();
-    // cut back the buffers that might not take another tile
-    for (int m = w; m < kFQ; m += 4) {
+    // cut back the buffers that might not take another tile; the cuts are
+    // dealt round-robin to the waves (the full set is read by every wave
+    // before any cut rewrites a count)
+    const uint64_t full = __ballot(lane < kFQ && s_cnt[lane] > CAP - kFTile);
+    __syncthreads();
+    int job = 0;
+    for (uint64_t f = full; f; f &= f - 1, ++job) {
+      if ((job & 3) != w) continue;
+      const int m = __ffsll((unsigned long long)f) - 1;
       const int c = s_cnt[m];
-      if (c > CAP - kFTile) {
-        const uint64_t K = wave_kth(s_buf + m * CAP, c, NP, s_hist + w * 256);
-        wave_collect_le(s_buf + m * CAP, c, K, s_tmp + w * NP);  // exactly NP keys
-        for (int i = lane; i < NP; i += 64) s_buf[m * CAP + i] = s_tmp[w * NP + i];
-        if (lane == 0) {
-          s_cnt[m] = NP;
-          s_thr[m] = K;
-        }
+      const uint64_t K = wave_kth(s_buf + m * CAP, c, NP, s_hist + w * 256);
+      wave_collect_le(s_buf + m * CAP, c, K, s_tmp + w * NP);  // exactly NP keys
+      for (int i = lane; i < NP; i += 64) s_buf[m * CAP + i] = s_tmp[w * NP + i];
+      if (lane == 0) {
+        s_cnt[m] = NP;
+        s_thr[m] = K;
       }
     }
     __syncthreads();

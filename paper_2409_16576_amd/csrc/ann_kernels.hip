@@ -549,6 +549,29 @@ __device__ __forceinline__ float lut_entry_v4(const DevIndex& ix, const float* q
   return acc;
 }
 
+// The entry of a 4-dimensional subspace from its codeword c (same arithmetic
+// and order as lut_entry_v4).
+__device__ __forceinline__ float lut_entry_d4(const DevIndex& ix, const float* qs, float4 c) {
+  if (!ix.int_grid) {
+    double acc = 0.0;
+    const double u0 = (double)qs[0] - (double)c.x, u1 = (double)qs[1] - (double)c.y;
+    const double u2 = (double)qs[2] - (double)c.z, u3 = (double)qs[3] - (double)c.w;
+    const double s0 = u0 * u0, s1 = u1 * u1, s2 = u2 * u2, s3 = u3 * u3;
+    acc = acc + s0;
+    acc = acc + s1;
+    acc = acc + s2;
+    acc = acc + s3;
+    return (float)acc;
+  }
+  const float u0 = qs[0] - c.x, u1 = qs[1] - c.y, u2 = qs[2] - c.z, u3 = qs[3] - c.w;
+  float acc = 0.f;
+  acc = acc + u0 * u0;
+  acc = acc + u1 * u1;
+  acc = acc + u2 * u2;
+  acc = acc + u3 * u3;
+  return acc;
+}
+
 // One block per query, thread = codeword, loop over subspaces.
 __global__ __launch_bounds__(kBlock) void k_lut(DevIndex ix, const float* __restrict__ Q, int qc,
                                                  float* __restrict__ lut) {
@@ -909,6 +932,34 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     }
   };
 
+  // Table entries i0, i0 + stride, ...: with 4-dimensional subspaces the
+  // codewords of four entries are loaded before any is computed.
+  auto build_table = [&](int i0, int stride) {
+    const int total = M * kKsub;
+    if (!TRACE && ix.dsub == 4) {
+      const float4* cb4 = reinterpret_cast<const float4*>(ix.codebooks);
+      for (int i = i0; i < total; i += 4 * stride) {
+        float4 c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = i + u * stride;
+          c[u] = k < total ? cb4[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = i + u * stride;
+          if (k < total) {
+            const float e = lut_entry_d4(ix, s_qv + (k >> 8) * 4, c[u]);
+            if constexpr (H) s_lut[k] = __float2half_rn(e);  // nearest binary16, ties to even
+            else s_lut[k] = e;
+          }
+        }
+      }
+    } else {
+      for (int i = i0; i < total; i += stride) table_entry(i);
+    }
+  };
+
   // Runs of every probed list (slot order), then their entry prefix sums.
   // Up to 64 probed lists: wave 0 lays the runs out (one list per lane) while
   // the other waves build the table; otherwise the whole block does both in turn.
@@ -919,7 +970,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
       runs_wave(ix, s_list, np, s_bits, segmented, max_runs, s_rstart, s_pre,
                 &s_wsum[kScanBlock / 64]);
     } else {
-      for (int i = tid - 64; i < M * kKsub; i += kScanBlock - 64) table_entry(i);
+      build_table(tid - 64, kScanBlock - 64);
     }
     __syncthreads();
     nruns = s_wsum[kScanBlock / 64];
@@ -1000,7 +1051,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   if (j >= S) return;
 
   if (!wave_setup) {
-    for (int i = tid; i < M * kKsub; i += kScanBlock) table_entry(i);
+    build_table(tid, kScanBlock);
     __syncthreads();
   }
 

@@ -1060,6 +1060,8 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   const uint64_t lanemask = (1ull << lane) - 1ull;
   int scanned = 0;
   int cur = 0;  // run of this thread's current entry (entries only increase)
+  int run_lo = 0, run_hi = -1;  // entries [run_lo, run_hi) of run cur (none yet)
+  uint32_t run_rs = 0;
   // Each wave walks its part of every round (kScanRT entries per lane) at its
   // own pace; the block meets only when some wave has seen the buffer above
   // T = cap - kRound, or has finished.  A wave inserts at most kScanRT * 64
@@ -1087,9 +1089,14 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
         keep[u] = false;
         rows[u] = 0;
         if (e < e1) {
-          while (s_pre[cur + 1] <= e) ++cur;  // s_pre[nruns] = E > e bounds the walk
-          const int o = e - s_pre[cur];
-          const uint32_t rs = s_rstart[cur];
+          if (e >= run_hi) {
+            while (s_pre[cur + 1] <= e) ++cur;  // s_pre[nruns] = E > e bounds the walk
+            run_lo = s_pre[cur];
+            run_hi = s_pre[cur + 1];
+            run_rs = s_rstart[cur];
+          }
+          const int o = e - run_lo;
+          const uint32_t rs = run_rs;
           if (!(rs & kRunReplica)) {
             rows[u] = (int)rs + o;
             keep[u] = true;
@@ -1105,17 +1112,12 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
           }
         }
       }
-      // all code-row loads of the round in flight together
+      // all code-row loads of the round in flight together (an entry not
+      // kept reads row 0, a valid row whose sum is then ignored)
       uint32_t cw[kScanRT][W];
 #pragma unroll
-      for (int u = 0; u < kScanRT; ++u) {
-        if (keep[u]) {
-          load_row<W>(ix.codes + (size_t)rows[u] * ix.row_bytes, cw[u]);
-        } else {
-#pragma unroll
-          for (int i = 0; i < W; ++i) cw[u][i] = 0u;
-        }
-      }
+      for (int u = 0; u < kScanRT; ++u)
+        load_row<W>(ix.codes + (size_t)(keep[u] ? rows[u] : 0) * ix.row_bytes, cw[u]);
 #pragma unroll
       for (int u = 0; u < kScanRT; ++u) {
         const float acc = adc_words<W, LutT>(cw[u], s_lut, M);

@@ -49,6 +49,11 @@ def indexes(tmp_path_factory, orc):
     X = fx.mixture(37, 6000, 96, "f32", n_centres=4)
     p, _ = fx.built(d, "f32m24", X, "f32", nlist=96, M=24)
     out["f32m24"] = (orc.read_index(p), p, fx.mixture(38, 19, 96, "f32", n_centres=4).astype(np.float32))
+    # float32, dimension 30, M = 10 (dsub 3: 12-byte rows with two padding
+    # codes; table entries and exact distances without 4-wide vector paths)
+    X = fx.mixture(39, 8000, 30, "f32", n_centres=8)
+    p, _ = fx.built(d, "f32d30", X, "f32", nlist=32, M=10)
+    out["f32d30"] = (orc.read_index(p), p, fx.mixture(40, 23, 30, "f32", n_centres=8).astype(np.float32))
     return out
 
 
@@ -63,7 +68,7 @@ def gpu_index(ann, indexes):
     return get
 
 
-KINDS = ["u8", "f32", "i8", "f32m24"]
+KINDS = ["u8", "f32", "i8", "f32m24", "f32d30"]
 
 
 def _cuda(a):

@@ -174,6 +174,115 @@ __global__ __launch_bounds__(kKsub) void k_dcb(const float* __restrict__ CB,
   }
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_prefix(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+// The members of every codeword, in increasing candidate order: one wave per
+// subspace m counts the codes, turns the counts into starts
+// (starts[m][j] .. starts[m][j + 1]) and places the candidates 64 at a time,
+// a candidate's rank among the lanes holding the same code coming from eight
+// ballots (one per code bit), so the order within a codeword is stable.
+__global__ __launch_bounds__(64) void k_dcb_order(const uint8_t* __restrict__ codes, int C, int M,
+                                                  int32_t* __restrict__ order,
+                                                  int32_t* __restrict__ starts) {
+  __shared__ int s_cur[kKsub];
+  const int m = blockIdx.x, lane = threadIdx.x;
+  for (int j = lane; j < kKsub; j += 64) s_cur[j] = 0;
+  __threadfence_block();
+  for (int c = lane; c < C; c += 64) atomicAdd(&s_cur[codes[(size_t)c * M + m]], 1);
+  __threadfence_block();
+  int v[4], sum = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    v[b] = s_cur[4 * lane + b];
+    sum += v[b];
+  }
+  int run = wave_prefix(sum) - sum;
+  int32_t* st = starts + (size_t)m * (kKsub + 1);
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    s_cur[4 * lane + b] = run;
+    st[4 * lane + b] = run;
+    run += v[b];
+  }
+  if (lane == 63) st[kKsub] = run;  // = C
+  __threadfence_block();
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int c0 = 0; c0 < C; c0 += 64) {
+    const int c = c0 + lane;
+    const bool ok = c < C;
+    const int code = ok ? codes[(size_t)c * M + m] : 0;
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (code >> b) & 1;
+      const uint64_t ones = __ballot(ok && bit);
+      peers &= bit ? ones : ~ones;
+    }
+    const int base = ok ? s_cur[code] : 0;
+    const int rank = __popcll(peers & below);
+    if (ok) order[(size_t)m * C + base + rank] = c;
+    __threadfence_block();  // every lane has read its cursor
+    if (ok && rank == 0) s_cur[code] = base + __popcll(peers);
+    __threadfence_block();
+  }
+}
+
+// dCB as k_dcb, one thread per (subspace, codeword): the members' rows of T1
+// are read four at a time (loads in flight together) and added in increasing
+// candidate order, so every sum is the same float sequence as k_dcb's.
+template <int DS>
+__global__ __launch_bounds__(kKsub) void k_dcb_sum(const float* __restrict__ CB,
+                                                    const int32_t* __restrict__ order,
+                                                    const int32_t* __restrict__ starts,
+                                                    const float* __restrict__ T1, int C, int D,
+                                                    float* __restrict__ dcb) {
+  const int m = blockIdx.x, j = threadIdx.x;
+  const int32_t* st = starts + (size_t)m * (kKsub + 1);
+  const int32_t* mem = order + (size_t)m * C;
+  const int e = st[j + 1];
+  float s_cs = 0.f;
+  float s_t[DS];
+#pragma unroll
+  for (int t = 0; t < DS; ++t) s_t[t] = 0.f;
+  int i = st[j];
+  for (; i + 4 <= e; i += 4) {
+    float r[4][DS + 1];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float* row = T1 + (size_t)mem[i + u] * (D + 1);
+      r[u][DS] = row[D];
+#pragma unroll
+      for (int t = 0; t < DS; ++t) r[u][t] = row[m * DS + t];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      s_cs += r[u][DS];
+#pragma unroll
+      for (int t = 0; t < DS; ++t) s_t[t] += r[u][t];
+    }
+  }
+  for (; i < e; ++i) {
+    const float* row = T1 + (size_t)mem[i] * (D + 1);
+    s_cs += row[D];
+#pragma unroll
+    for (int t = 0; t < DS; ++t) s_t[t] += row[m * DS + t];
+  }
+#pragma unroll
+  for (int t = 0; t < DS; ++t) {
+    const float cb = CB[((size_t)m * kKsub + j) * DS + t];
+    dcb[((size_t)m * kKsub + j) * DS + t] = -2.f * (s_t[t] - s_cs * cb);
+  }
+}
+
 // Decoded candidates with a ones column: Dec1 [C, D + 1] = [Dec | 1].
 __global__ void k_decode1(const float* __restrict__ CB, const uint8_t* __restrict__ codes, int C,
                           int D, int M, int dsub, float* __restrict__ dec1) {
@@ -226,8 +335,10 @@ extern "C" size_t ann_adc_backward_workspace(int64_t B, int64_t C, int32_t M, in
   const int t1 = (int)(((D1 + 63) / 64) * ((B + 63) / 64)), t2 = (int)(((D1 + 63) / 64) * ((C + 63) / 64));
   const size_t s1 = (size_t)kslices(t1, (int)C), s2 = (size_t)kslices(t2, (int)B);
   // Dec1 [C, D1], Q1 [B, D1], GD1 [B, D1], T1 [C, D1], K-slice partials
+  // + the members of every codeword: order [M, C] and starts [M, 257] (int32)
   return sizeof(float) * ((size_t)C * D1 + 2 * (size_t)B * D1 + (size_t)C * D1 +
-                          std::max(s1 * (size_t)B * D1, s2 * (size_t)C * D1)) + 256;
+                          std::max(s1 * (size_t)B * D1, s2 * (size_t)C * D1)) +
+         sizeof(int32_t) * ((size_t)M * C + (size_t)M * (kKsub + 1)) + 256;
 }
 
 extern "C" ann_status ann_adc_backward(const float* d_queries, int64_t B, const float* d_codebooks,
@@ -276,8 +387,30 @@ extern "C" ann_status ann_adc_backward(const float* d_queries, int64_t B, const 
       hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)((nc + thr - 1) / thr)), dim3(thr), 0, st,
                          part, S, nc, t1);
     }
-    hipLaunchKernelGGL(k_dcb, dim3(M), dim3(kKsub), 0, st, d_codebooks, d_codes, t1, (int)C, D, M,
-                       dsub, d_dcb);
+    const int t1c = (int)(((size_t)D1 + 63) / 64) * (int)((C + 63) / 64);
+    const int t2c = (int)(((size_t)D1 + 63) / 64) * (int)((B + 63) / 64);
+    const size_t part_n = std::max((size_t)kslices(t2c, (int)C) * (size_t)B * D1,
+                                   (size_t)kslices(t1c, (int)B) * (size_t)C * D1);
+    int32_t* order = reinterpret_cast<int32_t*>(part + part_n);  // [M, C]
+    int32_t* starts = order + (size_t)M * C;                      // [M, 257]
+    if (dsub <= 8 && C > 0)
+      hipLaunchKernelGGL(k_dcb_order, dim3(M), dim3(64), 0, st, d_codes, (int)C, M, order, starts);
+    switch (dsub) {
+#define ANN_DCB(DS)                                                                            \
+  case DS:                                                                                     \
+    if (C > 0)                                                                                 \
+      hipLaunchKernelGGL(k_dcb_sum<DS>, dim3(M), dim3(kKsub), 0, st, d_codebooks, order,       \
+                         starts, t1, (int)C, D, d_dcb);                                        \
+    else                                                                                       \
+      hipLaunchKernelGGL(k_dcb, dim3(M), dim3(kKsub), 0, st, d_codebooks, d_codes, t1, (int)C, \
+                         D, M, dsub, d_dcb);                                                   \
+    break;
+      ANN_DCB(1) ANN_DCB(2) ANN_DCB(3) ANN_DCB(4) ANN_DCB(5) ANN_DCB(6) ANN_DCB(7) ANN_DCB(8)
+#undef ANN_DCB
+      default:
+        hipLaunchKernelGGL(k_dcb, dim3(M), dim3(kKsub), 0, st, d_codebooks, d_codes, t1, (int)C,
+                           D, M, dsub, d_dcb);
+    }
   }
   return hipGetLastError() == hipSuccess ? ANN_OK : diff_fail(ANN_EDEVICE, "launch failed");
 }

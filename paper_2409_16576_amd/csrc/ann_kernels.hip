@@ -1326,6 +1326,54 @@ __device__ void rerank_int16(const DevIndex& ix, const float* s_q, const uint64_
   }
 }
 
+// Wave-aggregated append: lanes with take set get consecutive slots counted
+// by *cnt (LDS); returns this lane's slot (undefined where take is false).
+__device__ __forceinline__ int wave_append(bool take, int* cnt) {
+  const uint64_t m = __ballot(take);
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == 0 && m) base = atomicAdd(cnt, __popcll(m));
+  base = __shfl(base, 0, 64);
+  return base + __popcll(m & ((1ull << lane) - 1ull));
+}
+
+// Ascending bitonic sort of the 64 R keys a wave holds in registers (element
+// r * 64 + lane in a[r]): strides below 64 exchange across lanes, larger ones
+// between a lane's own registers.  Stage (K, J) is a template so every
+// register index is a constant (the keys stay in registers).
+template <int R, int K, int J>
+__device__ __forceinline__ void wave_sort_stage(uint64_t (&a)[R], int lane) {
+  if constexpr (J >= 64) {
+    constexpr int RJ = J / 64;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if ((r & RJ) == 0) {
+        const bool up = ((r * 64 + lane) & K) == 0;
+        const uint64_t x = a[r], y = a[r | RJ];
+        const bool sw = (x > y) == up;
+        a[r] = sw ? y : x;
+        a[r | RJ] = sw ? x : y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t o = __shfl_xor(a[r], J, 64);
+      const bool lower = (lane & J) == 0, up = ((r * 64 + lane) & K) == 0;
+      a[r] = (lower == up) ? (o < a[r] ? o : a[r]) : (o > a[r] ? o : a[r]);
+    }
+  }
+  if constexpr (J > 1) wave_sort_stage<R, K, J / 2>(a, lane);
+}
+
+template <int R, int K = 2>
+__device__ __forceinline__ void wave_sort_regs(uint64_t (&a)[R]) {
+  if constexpr (K <= 64 * R) {
+    wave_sort_stage<R, K, K / 2>(a, threadIdx.x & 63);
+    wave_sort_regs<R, K * 2>(a);
+  }
+}
+
 // The row of each candidate s_top[0..nn) (external ID in the low half) into
 // the high half, every lookup of the block in flight at once, so the gathers
 // that follow wait on one memory round trip instead of two.  The caller
@@ -1409,18 +1457,68 @@ __device__ void exact_keys(const DevIndex& ix, const float* s_q, const uint64_t*
   }
 }
 
-// Re-rank s_top[0..nn) (keys of (adc, id)) by exact distance and write the
-// top-k, sorted.  s_key2 holds P >= nn keys; s_top is reused for the result
-// (it needs pow2_at_least(min(k, nn)) slots).
+// Re-rank s_top[0..nn) (keys of (adc, id), or already (row, id) when
+// rows_attached) by exact distance and write the top-k, sorted.  s_key2 holds
+// P >= nn keys; s_top is reused for the result (it needs
+// max(128, pow2_at_least(min(k, nn))) slots).
 __device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_top, int nn,
                              uint64_t* s_key2, int P, int k, int64_t* out_ids, float* out_d,
-                             SelScratch* ss, int* s_cnt) {
-  attach_rows(ix, s_top, nn);
-  __syncthreads();
+                             SelScratch* ss, int* s_cnt, bool rows_attached) {
+  if (!rows_attached) {
+    attach_rows(ix, s_top, nn);
+    __syncthreads();
+  }
   exact_keys(ix, s_q, s_top, nn, s_key2, P);
   __syncthreads();
-  // the kk smallest keys, ascending: select the kk-th, collect, sort kk
   const int kk = min(k, nn);
+  const int lane = threadIdx.x & 63;
+  auto write_out = [&](int i, uint64_t key) {  // output slot i < k
+    const bool v = i < kk;
+    out_ids[i] = v ? (int64_t)(uint32_t)key : -1;
+    out_d[i] = v ? unord32((uint32_t)(key >> 32)) : INFINITY;
+  };
+  if (kk <= 64 && k <= 64) {
+    // The first min(nn, 256) keys sorted by one wave: the answer if they are
+    // all, else their kk-th smallest bounds the kk-th smallest of all, and
+    // the keys up to it (at least kk) are usually few enough for one wave.
+    if (threadIdx.x < 64) {
+      uint64_t a[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = r * 64 + lane < nn ? s_key2[r * 64 + lane] : ~0ull;
+      wave_sort_regs<4>(a);
+      const uint64_t t = __shfl(a[0], max(kk, 1) - 1, 64);
+      if (nn <= 256) {
+        if (lane < k) write_out(lane, a[0]);
+      } else if (lane == 0) {
+        ss->lo = t;
+        *s_cnt = 0;
+      }
+    }
+    if (nn <= 256) return;  // uniform
+    __syncthreads();
+    const uint64_t T = ss->lo;
+    for (int i0 = 0; i0 < nn; i0 += blockDim.x) {  // uniform trip count
+      const int i = i0 + threadIdx.x;
+      const uint64_t key = i < nn ? s_key2[i] : ~0ull;
+      const bool take = i < nn && key <= T;
+      const int pos = wave_append(take, s_cnt);
+      if (take && pos < 128) s_top[pos] = key;
+    }
+    __syncthreads();
+    const int ns = *s_cnt;
+    if (ns <= 128) {  // uniform
+      if (threadIdx.x < 64) {
+        uint64_t a[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) a[r] = r * 64 + lane < ns ? s_top[r * 64 + lane] : ~0ull;
+        wave_sort_regs<2>(a);
+        if (lane < k) write_out(lane, a[0]);
+      }
+      return;
+    }
+    __syncthreads();  // (rare) too many keys up to the bound: select exactly
+  }
+  // the kk smallest keys, ascending: select the kk-th, collect, sort kk
   if (kk > 0) {
     const int pk = pow2_at_least(kk);
     const uint64_t K = kk == nn ? ~0ull : block_kth([&](int i) { return s_key2[i]; }, nn, kk, ss);
@@ -1437,23 +1535,9 @@ __device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_t
     __syncthreads();
     block_bitonic(s_top, pk);
   }
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    const bool v = i < kk;
-    out_ids[i] = v ? (int64_t)(uint32_t)s_top[i] : -1;
-    out_d[i] = v ? unord32((uint32_t)(s_top[i] >> 32)) : INFINITY;
-  }
+  for (int i = threadIdx.x; i < k; i += blockDim.x) write_out(i, s_top[i]);
 }
 
-// Wave-aggregated append: lanes with take set get consecutive slots counted
-// by *cnt (LDS); returns this lane's slot (undefined where take is false).
-__device__ __forceinline__ int wave_append(bool take, int* cnt) {
-  const uint64_t m = __ballot(take);
-  const int lane = threadIdx.x & 63;
-  int base = 0;
-  if (lane == 0 && m) base = atomicAdd(cnt, __popcll(m));
-  base = __shfl(base, 0, 64);
-  return base + __popcll(m & ((1ull << lane) - 1ull));
-}
 
 // Step 8 by the heuristic re-ranking (Alg. 1, change rate of Eq. 3): the
 // candidates s_top[0..nn), sorted ascending by (adc, id), are re-ranked in
@@ -1602,31 +1686,57 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   const int S = sq[q];
   const int P = pow2_at_least(n);
   for (int t = tid; t < ix.dim; t += BS) s_q[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
-  if (tid == 0) {
-    int acc = 0;
+  if (tid < 64) {  // one wave: the items' offsets (S <= 16) and the work counts
+    int c = 0;
     int64_t sc = 0, sw = 0;
-    for (int j = 0; j < S; ++j) {
-      s_off[j] = acc;
-      acc += pcount[(size_t)q * smax + j];
-      sc += pscan[2 * ((size_t)q * smax + j)];
-      sw += pscan[2 * ((size_t)q * smax + j) + 1];
+    if (tid < S) {
+      c = pcount[(size_t)q * smax + tid];
+      sc = pscan[2 * ((size_t)q * smax + tid)];
+      sw = pscan[2 * ((size_t)q * smax + tid) + 1];
     }
-    s_off[S] = acc;
-    *s_cnt = 0;
-    if (ncand) ncand[q] = sc;
-    if (nwalk) nwalk[q] = sw;
+    const int incl = (int)wave_incl_scan((uint32_t)c);
+    if (tid < S) s_off[tid] = incl - c;
+    if (tid == S - 1) s_off[S] = incl;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      sc += __shfl_xor(sc, d, 64);
+      sw += __shfl_xor(sw, d, 64);
+    }
+    if (tid == 0) {
+      *s_cnt = 0;
+      if (ncand) ncand[q] = sc;
+      if (nwalk) nwalk[q] = sw;
+    }
   }
   __syncthreads();
   const int total = s_off[S];
-  for (int j = 0; j < S; ++j) {
-    const int c = s_off[j + 1] - s_off[j];
-    const uint64_t* src = pkeys + ((size_t)q * smax + j) * n;
-    for (int i = tid; i < c; i += BS) s_keys[s_off[j] + i] = src[i];
-  }
   const int nn = min(n, total);
+  // No selection needed: the keys go straight to s_top, and on the plain
+  // re-rank path their rows are looked up on the way (one round trip less).
+  const bool direct = total <= n;
+  const bool rows_now = direct && !HEUR && !topn_ids && out_ids;
+  uint64_t* dst = direct ? s_top : s_keys;
+  auto fetch = [&](int i) -> uint64_t {  // key i of the query's items, in item order
+    int j = 0;
+    while (j + 1 < S && s_off[j + 1] <= i) ++j;
+    return pkeys[((size_t)q * smax + j) * n + (i - s_off[j])];
+  };
+  for (int i0 = 0; i0 < total; i0 += 2 * BS) {  // two keys per thread in flight
+    const int ia = i0 + tid, ib = ia + BS;
+    const bool oa = ia < total, ob = ib < total;
+    const uint64_t ka = oa ? fetch(ia) : 0ull, kb = ob ? fetch(ib) : 0ull;
+    if (rows_now) {
+      const int ra = oa ? ix.ext2row[(uint32_t)ka] : 0, rb = ob ? ix.ext2row[(uint32_t)kb] : 0;
+      if (oa) dst[ia] = ((uint64_t)(uint32_t)ra << 32) | (uint32_t)ka;
+      if (ob) dst[ib] = ((uint64_t)(uint32_t)rb << 32) | (uint32_t)kb;
+    } else {
+      if (oa) dst[ia] = ka;
+      if (ob) dst[ib] = kb;
+    }
+  }
   for (int i = nn + tid; i < P; i += BS) s_top[i] = ~0ull;
   __syncthreads();
-  if (total > n) {
+  if (!direct) {
     const uint64_t K = block_kth([&](int i) { return s_keys[i]; }, total, n, ss);
     for (int i = tid; i < total; i += BS) {
       const uint64_t key = s_keys[i];
@@ -1635,8 +1745,6 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
         if (pos < P) s_top[pos] = key;
       }
     }
-  } else {
-    for (int i = tid; i < total; i += BS) s_top[i] = s_keys[i];
   }
   __syncthreads();
   if (topn_ids) {
@@ -1657,7 +1765,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   } else {
     __syncthreads();  // s_key2 aliases s_keys
     rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k,
-                 out_dists + (size_t)q * k, ss, s_cnt);
+                 out_dists + (size_t)q * k, ss, s_cnt, rows_now);
   }
 }
 
@@ -1685,7 +1793,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   const int nn = *s_cnt;
   __shared__ SelScratch ss;
   rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k, out_dists + (size_t)q * k,
-               &ss, s_cnt);
+               &ss, s_cnt, false);
 }
 
 // Step 2 on integer-grid indexes without materialising the distance matrix:

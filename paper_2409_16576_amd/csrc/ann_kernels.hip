@@ -2284,14 +2284,22 @@ hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, 
                         int64_t* out_ids, float* out_dists, int32_t* reranked, hipStream_t st) {
   if (c.qc <= 0) return hipSuccess;
   const MergeLayout L = merge_layout(c.smax, c.n, ix.dim);
-  // more threads only pay off when there are many candidates to re-rank
-  const bool big = c.n > 512;
+  // More threads only pay off when there are many candidates to re-rank.
+  // Then four 512-thread blocks per CU, where their LDS fits, beat two of
+  // 1024: while one block sits in its barrier-bound selection and sort, the
+  // others' row gathers keep memory busy (rerank_n 600: 0.34 -> 0.26 ms;
+  // heuristic rerank_n 2000: 1.73 -> 1.25 ms).
   const bool heur = c.hb > 0 && out_ids;
-  auto kern = heur ? (big ? k_merge<kMergeBlock, true> : k_merge<256, true>)
-                   : (big ? k_merge<kMergeBlock, false> : k_merge<256, false>);
+  const int bs = c.n <= 512 ? 256 : 4 * L.total <= (size_t)kLdsPerCu ? 512 : kMergeBlock;
+  auto kern = heur ? (bs == 256   ? k_merge<256, true>
+                      : bs == 512 ? k_merge<512, true>
+                                  : k_merge<kMergeBlock, true>)
+                   : (bs == 256   ? k_merge<256, false>
+                      : bs == 512 ? k_merge<512, false>
+                                  : k_merge<kMergeBlock, false>);
   if (L.total > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
-  hipLaunchKernelGGL(kern, dim3(c.qc), dim3(big ? kMergeBlock : 256), L.total, st, ix, q, c.qc, w.sq, c.smax,
+  hipLaunchKernelGGL(kern, dim3(c.qc), dim3(bs), L.total, st, ix, q, c.qc, w.sq, c.smax,
                      c.n, c.k, w.pkeys, w.pcount, w.pscan, topn_ids, topn_adc, ncand, nwalk, out_ids,
                      out_dists, c.hb, c.h_eps, c.h_beta, reranked);
   return hipGetLastError();

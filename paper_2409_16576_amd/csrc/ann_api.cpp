@@ -509,12 +509,10 @@ extern "C" ann_status ann_load_index(const char* path, int device, ann_index** o
   const int row_bytes = (M + 3) / 4 * 4;
   const int es = elem_size(dtype);
   std::vector<uint8_t> codes_rows((size_t)n * row_bytes, 0);
-  std::vector<uint8_t> vec_rows((size_t)n * dim * es);
   std::vector<int32_t> asg_rows((size_t)n * R);
   for (uint64_t row = 0; row < n; ++row) {
     const uint64_t v = (uint64_t)row2ext[row];
     std::memcpy(&codes_rows[row * row_bytes], codes + v * M, M);
-    std::memcpy(&vec_rows[row * dim * es], vecs + v * dim * es, (size_t)dim * es);
     std::memcpy(&asg_rows[row * R], asg + v * R, (size_t)R * 4);
   }
   std::vector<float> cent_t((size_t)dim * nlist);
@@ -537,11 +535,11 @@ extern "C" ann_status ann_load_index(const char* path, int device, ann_index** o
   const uint8_t* pv = nullptr;
   const int2* prep = nullptr;
   if ((s = dev_upload(ix.get(), codes_rows.data(), codes_rows.size(), &pc)) != ANN_OK) return s;
-  if ((s = dev_upload(ix.get(), vec_rows.data(), vec_rows.size(), &pv)) != ANN_OK) return s;
+  // raw vectors stay in external-ID order: the re-rank reads them by ID
+  if ((s = dev_upload(ix.get(), vecs, (size_t)n * dim * es, &pv)) != ANN_OK) return s;
   d.codes = pc;
   d.vecs = pv;
   if ((s = dev_upload(ix.get(), row2ext.data(), row2ext.size(), &d.row2ext)) != ANN_OK) return s;
-  if ((s = dev_upload(ix.get(), ext2row.data(), ext2row.size(), &d.ext2row)) != ANN_OK) return s;
   if ((s = dev_upload(ix.get(), cent, (size_t)nlist * dim, &d.centroids)) != ANN_OK) return s;
   if ((s = dev_upload(ix.get(), cent_t.data(), cent_t.size(), &d.centroids_t)) != ANN_OK) return s;
   if ((s = dev_upload(ix.get(), cb, (size_t)M * ksub * dsub, &d.codebooks)) != ANN_OK) return s;

@@ -24,15 +24,15 @@ constexpr int kRankShift = 28;        // replica entry: row | rank << 28
 constexpr uint32_t kRowMask = (1u << kRankShift) - 1;
 
 // Device view of a loaded index.  Rows are the vectors reordered by their
-// first (nearest) posting list; a list's first-list members are one
+// first (nearest) posting list (codes and list data are by row, raw vectors
+// by external ID); a list's first-list members are one
 // contiguous row range, its other members ("replica entries") are explicit.
 struct DevIndex {
   int dtype, dim, nlist, M, row_bytes, dsub, R, int_grid;
   int64_t n;
   const uint8_t* codes;       // [n, row_bytes] PQ codes by row (M used bytes)
-  const void* vecs;           // [n, dim] raw vectors by row
+  const void* vecs;           // [n, dim] raw vectors by external ID
   const int32_t* row2ext;     // [n]
-  const int32_t* ext2row;     // [n]
   const float* centroids;     // [nlist, dim]
   const float* centroids_t;   // [dim, nlist]
   const float* codebooks;     // [M, 256, dsub]

@@ -1202,14 +1202,14 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
 }
 
 // ---------------------------------------------------------------------------
-// Step 8: exact squared distance of one raw row (float64 in order for float
-// data, exact integers for uint8/int8).
+// Step 8: exact squared distance of one raw vector, addressed by its external
+// ID (float64 in order for float data, exact integers for uint8/int8).
 
 __device__ __forceinline__ float exact_row(const DevIndex& ix, const float* __restrict__ s_q,
-                                           int row) {
+                                           uint32_t id) {
   const int D = ix.dim;
   if (ix.dtype == F32) {
-    const float* x = static_cast<const float*>(ix.vecs) + (size_t)row * D;
+    const float* x = static_cast<const float*>(ix.vecs) + (size_t)id * D;
     double acc = 0.0;
     auto add = [&](float qv, float xv) {
       const double u = (double)qv - (double)xv;
@@ -1233,13 +1233,13 @@ __device__ __forceinline__ float exact_row(const DevIndex& ix, const float* __re
   }
   int acc = 0;
   if (ix.dtype == U8) {
-    const uint8_t* x = static_cast<const uint8_t*>(ix.vecs) + (size_t)row * D;
+    const uint8_t* x = static_cast<const uint8_t*>(ix.vecs) + (size_t)id * D;
     for (int t = 0; t < D; ++t) {
       const int u = (int)s_q[t] - (int)x[t];
       acc += u * u;
     }
   } else {
-    const int8_t* x = static_cast<const int8_t*>(ix.vecs) + (size_t)row * D;
+    const int8_t* x = static_cast<const int8_t*>(ix.vecs) + (size_t)id * D;
     for (int t = 0; t < D; ++t) {
       const int u = (int)s_q[t] - (int)x[t];
       acc += u * u;
@@ -1273,22 +1273,20 @@ __device__ void rerank_int16(const DevIndex& ix, const float* s_q, const uint64_
   constexpr int U = 4;
   for (int i0 = 0; i0 < P; i0 += ngrp * U) {
     uint4 v[U];
-    uint32_t id[U], row[U];
+    uint32_t id[U];
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = i0 + u * ngrp + grp;
       ok[u] = i < nn;
-      const uint64_t t = ok[u] ? s_top[i] : 0ull;
-      id[u] = (uint32_t)t;
-      row[u] = (uint32_t)(t >> 32);
+      id[u] = ok[u] ? (uint32_t)s_top[i] : 0u;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       v[u] = make_uint4(0u, 0u, 0u, 0u);
       if (ok[u])
         v[u] = *reinterpret_cast<const uint4*>(static_cast<const uint8_t*>(ix.vecs) +
-                                               (size_t)row[u] * ix.dim + lg * 16);
+                                               (size_t)id[u] * ix.dim + lg * 16);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -1374,35 +1372,8 @@ __device__ __forceinline__ void wave_sort_regs(uint64_t (&a)[R]) {
   }
 }
 
-// The row of each candidate s_top[0..nn) (external ID in the low half) into
-// the high half, every lookup of the block in flight at once, so the gathers
-// that follow wait on one memory round trip instead of two.  The caller
-// synchronises before the rows are read.
-__device__ __forceinline__ void attach_rows(const DevIndex& ix, uint64_t* s_top, int nn) {
-  constexpr int U = 4;
-  for (int i0 = 0; i0 < nn; i0 += U * (int)blockDim.x) {  // uniform trip count
-    uint32_t id[U];
-    int row[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
-      id[u] = i < nn ? (uint32_t)s_top[i] : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
-      row[u] = i < nn ? ix.ext2row[id[u]] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
-      if (i < nn) s_top[i] = ((uint64_t)(uint32_t)row[u] << 32) | id[u];
-    }
-  }
-}
-
-// Exact keys (distance << 32 | external ID) of the candidates s_top[0..nn),
-// whose rows attach_rows has put in the high halves; s_key2[nn..P) = ~0.
+// Exact keys (distance << 32 | external ID) of the candidates s_top[0..nn)
+// (external ID in the low half); s_key2[nn..P) = ~0.
 __device__ void exact_keys(const DevIndex& ix, const float* s_q, const uint64_t* s_top, int nn,
                            uint64_t* s_key2, int P) {
   const int g16 = ix.dim % 16 == 0 ? ix.dim / 16 : 0;
@@ -1426,7 +1397,7 @@ __device__ void exact_keys(const DevIndex& ix, const float* s_q, const uint64_t*
       if (i < nn) {
         id = (uint32_t)s_top[i];
         const uint32_t* x = reinterpret_cast<const uint32_t*>(
-            static_cast<const uint8_t*>(ix.vecs) + (size_t)(uint32_t)(s_top[i] >> 32) * ix.dim);
+            static_cast<const uint8_t*>(ix.vecs) + (size_t)id * ix.dim);
         for (int t = jl; t < nd; t += 8) {
           const uint32_t v = x[t];
 #pragma unroll
@@ -1449,7 +1420,7 @@ __device__ void exact_keys(const DevIndex& ix, const float* s_q, const uint64_t*
       uint64_t key = ~0ull;
       if (i < nn) {
         const uint32_t id = (uint32_t)s_top[i];
-        const float e = exact_row(ix, s_q, (int)(uint32_t)(s_top[i] >> 32));
+        const float e = exact_row(ix, s_q, id);
         key = ((uint64_t)ord32(e) << 32) | id;
       }
       s_key2[i] = key;
@@ -1457,17 +1428,13 @@ __device__ void exact_keys(const DevIndex& ix, const float* s_q, const uint64_t*
   }
 }
 
-// Re-rank s_top[0..nn) (keys of (adc, id), or already (row, id) when
-// rows_attached) by exact distance and write the top-k, sorted.  s_key2 holds
+// Re-rank s_top[0..nn) (external IDs in the low halves) by exact distance
+// and write the top-k, sorted.  s_key2 holds
 // P >= nn keys; s_top is reused for the result (it needs
 // max(128, pow2_at_least(min(k, nn))) slots).
 __device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_top, int nn,
                              uint64_t* s_key2, int P, int k, int64_t* out_ids, float* out_d,
-                             SelScratch* ss, int* s_cnt, bool rows_attached) {
-  if (!rows_attached) {
-    attach_rows(ix, s_top, nn);
-    __syncthreads();
-  }
+                             SelScratch* ss, int* s_cnt) {
   exact_keys(ix, s_q, s_top, nn, s_key2, P);
   __syncthreads();
   const int kk = min(k, nn);
@@ -1564,8 +1531,7 @@ __device__ void rerank_heuristic(const DevIndex& ix, const float* s_q, uint64_t*
   const int per = hb * max(1, 1024 / hb);  // candidates gathered per chunk
   for (int c0 = 0; c0 < nn && !stop; c0 += per) {
     const int cn = min(per, nn - c0);
-    attach_rows(ix, s_top + c0, cn);  // rows of this chunk only: the loop may stop early
-    __syncthreads();
+    __syncthreads();  // the previous chunk's exact keys have been read
     exact_keys(ix, s_q, s_top + c0, cn, s_key2, cn);
     __syncthreads();
     // s_top[c0..c0+cn) has been read: it holds the entrants of each mini-batch
@@ -1711,10 +1677,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   __syncthreads();
   const int total = s_off[S];
   const int nn = min(n, total);
-  // No selection needed: the keys go straight to s_top, and on the plain
-  // re-rank path their rows are looked up on the way (one round trip less).
+  // No selection needed: the keys go straight to s_top.
   const bool direct = total <= n;
-  const bool rows_now = direct && !HEUR && !topn_ids && out_ids;
   uint64_t* dst = direct ? s_top : s_keys;
   auto fetch = [&](int i) -> uint64_t {  // key i of the query's items, in item order
     int j = 0;
@@ -1725,14 +1689,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     const int ia = i0 + tid, ib = ia + BS;
     const bool oa = ia < total, ob = ib < total;
     const uint64_t ka = oa ? fetch(ia) : 0ull, kb = ob ? fetch(ib) : 0ull;
-    if (rows_now) {
-      const int ra = oa ? ix.ext2row[(uint32_t)ka] : 0, rb = ob ? ix.ext2row[(uint32_t)kb] : 0;
-      if (oa) dst[ia] = ((uint64_t)(uint32_t)ra << 32) | (uint32_t)ka;
-      if (ob) dst[ib] = ((uint64_t)(uint32_t)rb << 32) | (uint32_t)kb;
-    } else {
-      if (oa) dst[ia] = ka;
-      if (ob) dst[ib] = kb;
-    }
+    if (oa) dst[ia] = ka;
+    if (ob) dst[ib] = kb;
   }
   for (int i = nn + tid; i < P; i += BS) s_top[i] = ~0ull;
   __syncthreads();
@@ -1765,7 +1723,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   } else {
     __syncthreads();  // s_key2 aliases s_keys
     rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k,
-                 out_dists + (size_t)q * k, ss, s_cnt, rows_now);
+                 out_dists + (size_t)q * k, ss, s_cnt);
   }
 }
 
@@ -1793,7 +1751,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
   const int nn = *s_cnt;
   __shared__ SelScratch ss;
   rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k, out_dists + (size_t)q * k,
-               &ss, s_cnt, false);
+               &ss, s_cnt);
 }
 
 // Step 2 on integer-grid indexes without materialising the distance matrix:

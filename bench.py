@@ -143,8 +143,11 @@ def run_served(ann, g, Qh, npq, w, k, n, args):
         th.join()
         return done["t_end"] - t0, pos
 
-    # warm-up (kernels, pinned pages)
+    # warm-up (kernels of every launch shape, pinned pages): a burst, then a
+    # short stream of single arrivals of mixed sizes, none of it measured
     play(np.zeros(8), [256] * 8)
+    wr = np.random.default_rng(17)
+    play(np.cumsum(wr.exponential(1.0, size=400)) * 5e-4, wr.integers(1, 257, size=400))
     srv.stats(reset=True)
     loads = []
     for rate_m in [float(x) for x in args.served_rates.split(",") if x]:

@@ -91,7 +91,14 @@ def parse():
     ap.add_argument("--build-only", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    known = {"plain", "batched", "served", "heuristic"}
+    names = [f for f in args.forms.split(",") if f]
+    if not set(names) <= known:
+        ap.error(f"--forms: unknown form(s) {sorted(set(names) - known)}")
+    if not set(names) - {"served"}:
+        ap.error("--forms: the stage times and the roofline need plain, batched or heuristic too")
+    return args
 
 
 def run_served(ann, g, Qh, npq, w, k, n, args):

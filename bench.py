@@ -289,8 +289,8 @@ def run_diff(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); every box in this "
-              "setup has a single MI355X and the search path uses no collectives.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the search path "
+              "runs on a single MI355X and uses no collectives.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -76,8 +76,8 @@ typedef struct {
  * centroids, PQ codebooks, one M-byte code per vector, raw vectors, posting
  * lists of external IDs and each vector's list assignment) onto `device`.
  * The file is validated (magic, version, sizes, CRC32 of every section,
- * list / assignment consistency) and copied to HBM with the code rows and raw
- * vectors reordered by first list.  *out receives an index owned by the
+ * list / assignment consistency) and copied to HBM, the code rows reordered
+ * by first list, the raw vectors kept in external-ID order.  *out receives an index owned by the
  * caller, freed with ann_free_index.  Errors: ANN_EIO, ANN_EFORMAT,
  * ANN_EUNSUPPORTED (ksub != 256, R > 15, N >= 2^28), ANN_ENOMEM, ANN_EDEVICE.
  */

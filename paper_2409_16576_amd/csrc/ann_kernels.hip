@@ -372,6 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_mfma(DevIndex ix, const float*
 // collected and sorted.  Otherwise (or if too many keys tie below the
 // threshold) a block radix select finds the exact np-th key.
 constexpr int kSelCand = 1024;
+constexpr int kSelU = 8;
 
 __global__ __launch_bounds__(kBlock) void k_probe_select(const float* __restrict__ dist, int nlist,
                                                           const int32_t* __restrict__ nprobe,
@@ -391,31 +392,43 @@ __global__ __launch_bounds__(kBlock) void k_probe_select(const float* __restrict
   if (np > 0) {
     bool done = false;
     if (np < nlist && np <= kBlock) {
+      // both passes load kSelU distances per thread before using any, so a
+      // thread has kSelU loads in flight instead of one
       uint64_t mn = ~0ull;
-      for (int i = tid; i < nlist; i += kBlock) {
-        const uint64_t k = get(i);
-        mn = k < mn ? k : mn;
+      for (int i0 = tid; i0 < nlist; i0 += kBlock * kSelU) {
+        float v[kSelU];
+#pragma unroll
+        for (int u = 0; u < kSelU; ++u)  // (clamped index: no branch between the loads)
+          v[u] = row[min(i0 + u * kBlock, nlist - 1)];
+#pragma unroll
+        for (int u = 0; u < kSelU; ++u) {
+          const int i = i0 + u * kBlock;
+          const uint64_t k = ((uint64_t)ord32(v[u]) << 32) | (uint32_t)i;
+          if (i < nlist) mn = k < mn ? k : mn;
+        }
       }
       s_min[tid] = mn;
       if (tid == 0) s_cnt = 0;
       __syncthreads();
       block_bitonic(s_min, kBlock);
       const uint64_t tau = s_min[np - 1];
-      for (int i0 = 0; i0 < nlist; i0 += kBlock) {
-        const int i = i0 + tid;
-        uint64_t k = ~0ull;
-        bool take = false;
-        if (i < nlist) {
-          k = get(i);
-          take = k <= tau;
-        }
-        const uint64_t m = __ballot(take);
-        if (m) {
-          int base = 0;
-          if (lane == 0) base = atomicAdd(&s_cnt, (int)__popcll(m));
-          base = __shfl(base, 0, 64);
-          const int pos = base + (int)__popcll(m & ((1ull << lane) - 1ull));
-          if (take && pos < kSelCand) s_sel[pos] = k;
+      for (int i0 = 0; i0 < nlist; i0 += kBlock * kSelU) {  // block-uniform trip count
+        float v[kSelU];
+#pragma unroll
+        for (int u = 0; u < kSelU; ++u) v[u] = row[min(i0 + u * kBlock + tid, nlist - 1)];
+#pragma unroll
+        for (int u = 0; u < kSelU; ++u) {
+          const int i = i0 + u * kBlock + tid;
+          const uint64_t k = ((uint64_t)ord32(v[u]) << 32) | (uint32_t)i;
+          const bool take = i < nlist && k <= tau;
+          const uint64_t m = __ballot(take);
+          if (m) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&s_cnt, (int)__popcll(m));
+            base = __shfl(base, 0, 64);
+            const int pos = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+            if (take && pos < kSelCand) s_sel[pos] = k;
+          }
         }
       }
       __syncthreads();

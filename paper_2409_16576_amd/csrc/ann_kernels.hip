@@ -307,11 +307,23 @@ __global__ __launch_bounds__(kBlock) void k_probe_mfma(DevIndex ix, const float*
   int* s_qn = reinterpret_cast<int*>(s_q8 + kPM * Dp);
   const int q0 = blockIdx.y * kPM;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = tid; i < kPM * Dp; i += kBlock) {
-    const int qq = q0 + i / Dp, t = i % Dp;
-    int v = 0;
-    if (qq < qc && t < D) v = (int)conv_query(Q[(size_t)qq * D + t], ix.dtype) - ix.shift8;
-    s_q8[i] = (int8_t)v;
+  // the block's queries as shifted int8: 8 loads in flight per thread (clamped
+  // addresses, so no branch sits between them), then the conversions
+  constexpr int U = 8;
+  for (int i0 = tid; i0 < kPM * Dp; i0 += kBlock * U) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kBlock;
+      v[u] = Q[(size_t)min(q0 + i / Dp, qc - 1) * D + min(i % Dp, D - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kBlock;
+      const int qq = q0 + i / Dp, t = i % Dp;
+      if (i < kPM * Dp)
+        s_q8[i] = (int8_t)(qq < qc && t < D ? (int)conv_query(v[u], ix.dtype) - ix.shift8 : 0);
+    }
   }
   __syncthreads();
   if (tid < kPM) {

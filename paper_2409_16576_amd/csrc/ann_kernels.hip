@@ -1920,11 +1920,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int Dp = ix.dim_pad, D = ix.dim;
   const int q0 = blockIdx.x * kFQ;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = tid; i < 16 * Dp; i += kBlock) {
-    const int qi = i / Dp, qq = q0 + qi, t = i % Dp;
-    int v = 0;
-    if (qi < kFQ && qq < qc && t < D) v = (int)conv_query(Q[(size_t)qq * D + t], ix.dtype) - ix.shift8;
-    s_q8[i] = (int8_t)v;
+  {  // the block's queries as shifted int8, 8 loads in flight per thread
+    constexpr int U = 8;
+    for (int i0 = tid; i0 < 16 * Dp; i0 += kBlock * U) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kBlock;
+        v[u] = Q[(size_t)min(q0 + i / Dp, qc - 1) * D + min(i % Dp, D - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kBlock;
+        const int qi = i / Dp, qq = q0 + qi, t = i % Dp;
+        if (i < 16 * Dp)
+          s_q8[i] = (int8_t)(qi < kFQ && qq < qc && t < D
+                                 ? (int)conv_query(v[u], ix.dtype) - ix.shift8
+                                 : 0);
+      }
+    }
   }
   if (tid < kFQ) {
     s_thr[tid] = ~0ull;

@@ -35,6 +35,7 @@
 #ifndef ANN_H
 #define ANN_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus

@@ -702,7 +702,11 @@ int ann::search_on(ann_index* ix, Work& w, const float* d_q, int qc, const int32
 
 int ann::max_chunk(const DevIndex& d) { return chunk_queries(d, INT32_MAX); }
 
-void ann::set_capturing(bool on) { g_capturing = on; }
+bool ann::set_capturing(bool on) {
+  const bool was = g_capturing;
+  g_capturing = on;
+  return was;
+}
 
 int ann::get_opt(const ann_index* ix, int option, int64_t* v) {
   switch (option) {

@@ -107,7 +107,8 @@ Work work_carve(const DevIndex& d, int qc, int np_max, int n, void* base);
 int search_on(ann_index* ix, Work& w, const float* d_q, int qc, const int32_t* d_nprobe,
               int np_max, int k, int n, int64_t* d_ids, float* d_dists, hipStream_t st);
 int max_chunk(const DevIndex& d);  // most queries one search_on call may take
-void set_capturing(bool on);       // this thread is capturing a graph: no stage events
+bool set_capturing(bool on);       // this thread records no stage events (graph capture,
+                                   // no-alloc calls); returns the previous setting
 int get_opt(const ann_index* ix, int option, int64_t* v);
 
 // Records the thread's last error message (ann_last_error) and returns s.

@@ -3,6 +3,9 @@ the product package never reaches the CPU oracle (no compute calls here)."""
 import ctypes
 import os
 import re
+import subprocess
+
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ann.h")
@@ -38,3 +41,33 @@ def test_product_code_does_not_use_the_oracle():
                 src = open(os.path.join(dirpath, f), errors="replace").read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", src, flags=re.M), f
                 assert "ann_oracle" not in src, f
+
+
+def _caller_source(names):
+    """A caller that includes the header and takes the address of every
+    declared entry point (so the link resolves each one)."""
+    body = ",\n  ".join(f"(ann_fn){n}" for n in names)
+    return ('#include "ann.h"\n'
+            "typedef void (*ann_fn)(void);\n"
+            f"static ann_fn const table[] = {{\n  {body}\n}};\n"
+            "int main(void) { return table[0] == 0; }\n")
+
+
+@pytest.mark.parametrize("lang", ["c11", "c++17"])
+def test_header_compiles_and_links_for_plain_callers(tmp_path, lang):
+    """include/ann.h is self-contained for C11 and C++17 callers (-Wall
+    -Werror -pedantic, no HIP headers), and every entry point it declares
+    resolves against libann.so at link time and at load time."""
+    assert os.path.exists(LIB), "build libann.so first (__graft_entry__.build())"
+    names = declared()
+    src = tmp_path / ("caller.c" if lang == "c11" else "caller.cpp")
+    src.write_text(_caller_source(names))
+    exe = tmp_path / "caller"
+    cc = ["gcc", "-std=c11"] if lang == "c11" else ["g++", "-std=c++17"]
+    cmd = [*cc, "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", os.path.dirname(HEADER),
+           str(src), "-o", str(exe), LIB, "-Wl,-rpath," + os.path.dirname(LIB),
+           "-Wl,-rpath-link,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr

@@ -339,7 +339,11 @@ def test_heuristic_rerank_reductions_and_rule(tmp_path, orc):
     never = orc.search(ix, Q, 6, k, n, heuristic=(32, 0.0, 10 ** 6))
     assert np.array_equal(never.ids, fixed.ids) and np.array_equal(never.dists, fixed.dists)
     assert (never.reranked == np.minimum(n, fixed.ncand)).all()
-    for B, eps, beta in ((40, 1.0, 1), (16, 0.0, 2), (8, 0.1, 3), (25, 0.2, 1)):
+    # (8, 0.85, 1) and (6, 0.7, 2): after a first mini-batch smaller than k the
+    # change rate is batch/k (Eq. 3 divides by k), below eps, while dividing
+    # by the heap's size would give 1 -- so only the k reading stops there
+    for B, eps, beta in ((40, 1.0, 1), (16, 0.0, 2), (8, 0.1, 3), (25, 0.2, 1), (8, 0.85, 1),
+                         (6, 0.7, 2)):
         r = orc.search(ix, Q, 6, k, n, heuristic=(B, eps, beta))
         for i in range(len(Q)):
             cand = fixed.topn_ids[i][fixed.topn_ids[i] >= 0]
@@ -360,3 +364,95 @@ def test_heuristic_rerank_reductions_and_rule(tmp_path, orc):
             assert r.dists[i][:len(o)].tolist() == ex[:stop][o].astype(np.float32).tolist()
             if (B, eps, beta) == (40, 1.0, 1):
                 assert stop == min(40, len(cand))
+            if (B, eps, beta) == (8, 0.85, 1):
+                assert stop == min(8, len(cand))
+
+
+def test_int8_exact_and_bruteforce_match_numpy(tmp_path, orc):
+    """int8 data (Table 1's 100-d int8 set): exact squared distances and brute
+    force against numpy int64 arithmetic on signed values.  Rows hold negative
+    values down to -128 and queries hit both saturation bounds, so reading the
+    rows as unsigned bytes, or skipping the query's saturation, changes the
+    distances."""
+    rng = np.random.default_rng(31)
+    n, dim = 1500, 20
+    X = rng.integers(-128, 128, size=(n, dim)).astype(np.int8)
+    X[::7, ::3] = -128
+    cb = np.tile(np.arange(-128, 128, dtype=np.float32).reshape(1, 256, 1), (dim, 1, 1))
+    cent = np.rint(rng.uniform(-128, 127, size=(4, dim))).astype(np.float32)
+    d = ((X[:, None, :].astype(np.int64) - cent[None].astype(np.int64)) ** 2).sum(-1)
+    assign = np.stack([np.argmin(d, axis=1), -np.ones(n, dtype=np.int64)], axis=1)
+    codes = (X.astype(np.int16) + 128).astype(np.uint8)
+    path, _ = fx.write_arrays(tmp_path, "i8x", "i8", cent, cb, codes, X, assign)
+    ix = orc.read_index(path)
+    Q = rng.integers(-128, 128, size=(9, dim)).astype(np.float32)
+    Q[0, :5] = [-300.0, 250.0, -128.0, 127.0, -0.5]  # saturate / round half to even
+    Qc = np.clip(np.rint(Q), -128, 127).astype(np.int64)
+    D = ((Qc[:, None, :] - X[None].astype(np.int64)) ** 2).sum(-1)
+    ids = np.arange(0, n, 3, dtype=np.int32)
+    for i in range(len(Q)):
+        got = orc.exact(ix, Q[i], ids)
+        assert got.tolist() == D[i][ids].astype(np.float32).tolist()
+    bi, bd = orc.bruteforce(ix, Q, 8)
+    for i in range(len(Q)):
+        want = np.lexsort((np.arange(n), D[i]))[:8]
+        assert bi[i].tolist() == want.tolist()
+        assert bd[i].tolist() == D[i][want].astype(np.float32).tolist()
+    # lossless codebook (dsub = 1, every int8 value a codeword): ADC = exact
+    r = orc.search(ix, Q, 4, 8, 8)
+    assert np.array_equal(r.ids, bi) and np.array_equal(r.dists, bd)
+
+
+def test_float_distances_are_one_rounding_of_the_exact_sum(tmp_path, orc):
+    """Float data: every exact squared distance (probe, re-rank, brute force)
+    and every table entry is the exact real sum rounded once to float32.
+
+    Coordinates are multiples of 2^-4 below 64 in magnitude, so each squared
+    difference is a multiple of 2^-8 below 2^14 and a sum over 128 dimensions
+    needs up to 29 + 8 significant bits: float64 holds every partial sum
+    exactly, float32 does not.  The exact value comes from integer
+    arithmetic; a float32 running sum (or any second rounding) differs from it
+    in the last bits for most vectors."""
+    rng = np.random.default_rng(37)
+    n, dim, nlist, M = 600, 128, 8, 16
+    grid = lambda *s: (rng.integers(-1023, 1024, size=s) / 16.0).astype(np.float32)  # noqa: E731
+    X, cent, cb = grid(n, dim), grid(nlist, dim), grid(M, 256, dim // M)
+    Q = grid(11, dim)
+    xi, ci, qi, cbi = ((a.astype(np.float64) * 16).astype(np.int64) for a in (X, cent, Q, cb))
+    dc = ((xi[:, None, :] - ci[None]) ** 2).sum(-1)
+    assign = np.stack([np.argmin(dc, axis=1), -np.ones(n, dtype=np.int64)], axis=1)
+    codes = rng.integers(0, 256, size=(n, M)).astype(np.uint8)
+    path, _ = fx.write_arrays(tmp_path, "grid", "f32", cent, cb, codes, X, assign)
+    ix = orc.read_index(path)
+
+    def once(S):  # integer multiple of 2^-8 -> float32, one rounding (S < 2^53)
+        return (np.asarray(S, np.int64).astype(np.float64) / 256.0).astype(np.float32)
+
+    DX = ((qi[:, None, :] - xi[None]) ** 2).sum(-1)
+    DC = ((qi[:, None, :] - ci[None]) ** 2).sum(-1)
+    ids = np.arange(n, dtype=np.int32)
+    diff32 = 0
+    for i in range(len(Q)):
+        want = once(DX[i])
+        assert orc.exact(ix, Q[i], ids).view(np.uint32).tolist() == want.view(np.uint32).tolist()
+        acc = np.zeros(n, np.float32)  # the float32 running sum the reading rules out
+        for t in range(dim):
+            acc = (acc + ((Q[i, t] - X[:, t]) ** 2).astype(np.float32)).astype(np.float32)
+        diff32 += int((acc != want).sum())
+    assert diff32 > n  # the fixture separates the two accumulations
+    lists, pd = orc.probe(ix, Q, nlist)
+    for i in range(len(Q)):
+        order = np.lexsort((np.arange(nlist), once(DC[i])))
+        assert lists[i].tolist() == order.tolist()
+        assert pd[i].view(np.uint32).tolist() == once(DC[i])[order].view(np.uint32).tolist()
+    bi, bd = orc.bruteforce(ix, Q, 6)
+    for i in range(len(Q)):
+        w = once(DX[i])
+        order = np.lexsort((np.arange(n), w))[:6]
+        assert bi[i].tolist() == order.tolist()
+        assert bd[i].view(np.uint32).tolist() == w[order].view(np.uint32).tolist()
+    l32, _ = orc.lut(ix, Q)
+    ds = dim // M
+    for m in range(M):
+        E = ((qi[:, None, m * ds:(m + 1) * ds] - cbi[m][None]) ** 2).sum(-1)  # [nq, 256]
+        assert l32[:, m, :].view(np.uint32).tolist() == once(E).view(np.uint32).tolist()

@@ -28,14 +28,32 @@ _DTYPES = {0: np.float32, 1: np.uint8, 2: np.int8}
 _KIND = {0: "f32", 1: "u8", 2: "i8"}
 
 
+_CFLAGS = ["-O3", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc: -O2, OpenMP, no FP contraction, no fast-math."""
+    """Compile the oracle with gcc: -O3, OpenMP, no FP contraction, no
+    fast-math (so no reassociation: every sum keeps the order of the source)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC",
-                        "-shared", SRC, "-o", tmp, "-lm"], check=True)
+        subprocess.run(["gcc", *_CFLAGS, SRC, "-o", tmp, "-lm"], check=True)
         os.replace(tmp, LIB)
     return LIB
+
+
+def use_native(directory: str | None = None) -> str:
+    """Build a copy tuned for this host's CPU (-march=native, same flags
+    otherwise, so the same results) in a scratch directory and make it the
+    library this module calls.  For timing the oracle on the machine that runs
+    it; the in-tree build stays portable."""
+    global _lib
+    import tempfile
+    d = directory or tempfile.mkdtemp(prefix="ann_oracle_")
+    out = os.path.join(d, "_ann_oracle_native.so")
+    subprocess.run(["gcc", *_CFLAGS, "-march=native", SRC, "-o", out, "-lm"], check=True)
+    _lib = None
+    _load(out)
+    return out
 
 
 class _OrcIndex(ctypes.Structure):
@@ -52,12 +70,14 @@ class _OrcIndex(ctypes.Structure):
 _lib = None
 
 
-def _load():
+def _load(path: str | None = None):
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build(force=True)
-        lib = ctypes.CDLL(LIB)
+        if path is None:
+            if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+                build(force=True)
+            path = LIB
+        lib = ctypes.CDLL(path)
         P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         lib.orc_probe.argtypes = [P, P, i64, P, i32, P, P, ctypes.c_int]
         lib.orc_lut.argtypes = [P, P, i64, P, P, ctypes.c_int]

@@ -227,77 +227,54 @@ static float adc_one(const orc_index* ix, const float* lut32, int64_t v) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Step 8, heuristic form (Alg. 1 with the change rate of Eq. 3).            */
-/* A max-heap Q of at most k (distance, id) pairs; candidates are taken in   */
-/* ascending ADC order, in mini-batches of `batch`.  A candidate enters Q    */
-/* while Q holds fewer than k pairs, otherwise if it is smaller than Q's     */
-/* maximum (which it replaces).  After each mini-batch the change rate is    */
-/* the number of IDs in Q that were not in Q before the mini-batch, divided  */
-/* by k; the process stops once it has been <= eps for beta mini-batches in  */
-/* a row.  Returns the number of candidates re-ranked.                       */
+/* Step 8, heuristic form: re-ranking in mini-batches that stops once the    */
+/* exact top-k has settled (Alg. 1; change rate of Eq. 3).                   */
+/*                                                                           */
+/* The candidates are visited in ascending (ADC distance, id) order, `batch` */
+/* at a time.  `best` holds the k smallest (exact distance, id) pairs of the */
+/* candidates visited so far, ascending, each with its candidate's position  */
+/* in the visiting order.  A pair that drops out of `best` never returns     */
+/* (the k-th smallest pair only decreases), so the IDs that are in `best`    */
+/* after a mini-batch but were not before it are exactly the members whose   */
+/* position lies inside that mini-batch.  Their number divided by k is the   */
+/* change rate.  Re-ranking ends once the change rate has been <= eps after  */
+/* beta mini-batches in a row, or when the candidates run out.  Returns the  */
+/* number of candidates whose exact distance was computed.                   */
 
-static void heap_sift_down(pair_t* h, int n, int i) {
-  for (;;) {
-    int l = 2 * i + 1, r = l + 1, m = i;
-    if (l < n && pair_cmp(&h[l], &h[m]) > 0) m = l;
-    if (r < n && pair_cmp(&h[r], &h[m]) > 0) m = r;
-    if (m == i) return;
-    pair_t t = h[i];
-    h[i] = h[m];
-    h[m] = t;
-    i = m;
-  }
-}
-
-static void heap_push(pair_t* h, int* n, pair_t p) {
-  int i = (*n)++;
-  h[i] = p;
-  while (i > 0) {
-    int up = (i - 1) / 2;
-    if (pair_cmp(&h[i], &h[up]) <= 0) break;
-    pair_t t = h[i];
-    h[i] = h[up];
-    h[up] = t;
-    i = up;
-  }
-}
+typedef struct {
+  pair_t p;
+  int64_t pos;
+} member_t;
 
 static int64_t heuristic_rerank(const orc_index* ix, const double* q, const int32_t* qi,
                                 const pair_t* tasks, int64_t ntask, int k, int batch, double eps,
-                                int beta, pair_t* heap, int32_t* prev_ids, int* out_n) {
-  int hn = 0, stable = 0;
-  int64_t done = 0;
-  for (int64_t i = 0; i < ntask; i += batch) {
-    int nprev = hn;
-    for (int t = 0; t < hn; ++t) prev_ids[t] = heap[t].id;          /* S_{n-1} */
-    for (int64_t j = i; j < i + batch && j < ntask; ++j) {
-      pair_t c;
-      c.id = tasks[j].id;
-      c.d = exact_dist(ix, q, qi, c.id);
-      if (hn < k) {
-        heap_push(heap, &hn, c);
-      } else if (pair_cmp(&c, &heap[0]) < 0) {
-        heap[0] = c;
-        heap_sift_down(heap, hn, 0);
+                                int beta, member_t* best, int* out_n) {
+  int nbest = 0, quiet = 0;
+  int64_t pos = 0;
+  while (pos < ntask) {
+    const int64_t start = pos;
+    const int64_t end = ntask - pos > batch ? pos + batch : ntask;
+    for (; pos < end; ++pos) {
+      member_t c;
+      c.p.id = tasks[pos].id;
+      c.p.d = exact_dist(ix, q, qi, c.p.id);
+      c.pos = pos;
+      if (nbest == k && pair_cmp(&c.p, &best[k - 1].p) >= 0) continue;
+      int at = nbest < k ? nbest++ : k - 1; /* when full, the largest pair drops out */
+      while (at > 0 && pair_cmp(&c.p, &best[at - 1].p) < 0) {
+        best[at] = best[at - 1];
+        --at;
       }
-      done = j + 1;
+      best[at] = c;
     }
-    int changed = 0;                                                 /* |S_n - S_n & S_{n-1}| */
-    for (int t = 0; t < hn; ++t) {
-      int seen = 0;
-      for (int u = 0; u < nprev && !seen; ++u) seen = prev_ids[u] == heap[t].id;
-      changed += !seen;
-    }
-    double delta = (double)changed / (double)k;                      /* Eq. 3 */
-    if (delta <= eps) {
-      if (++stable >= beta) break;
-    } else {
-      stable = 0;
-    }
+    int joined = 0;
+    for (int t = 0; t < nbest; ++t) joined += best[t].pos >= start;
+    const double rate = (double)joined / (double)k; /* Eq. 3: over k, however full */
+    quiet = rate <= eps ? quiet + 1 : 0;
+    if (quiet >= beta) break;
   }
-  qsort(heap, (size_t)hn, sizeof(pair_t), pair_cmp);
-  *out_n = hn;
-  return done;
+  *out_n = nbest;
+  return pos;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -415,7 +392,7 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
     float* lut = (float*)malloc(sizeof(float) * ix->m * ix->ksub);
     int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * maxg);
     pair_t* rr = (pair_t*)malloc(sizeof(pair_t) * (rerank_n > 0 ? rerank_n : 1));
-    int32_t* prev = (int32_t*)malloc(sizeof(int32_t) * (k > 0 ? k : 1));
+    member_t* best = (member_t*)malloc(sizeof(member_t) * (k > 0 ? k : 1));
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 1)
 #endif
@@ -441,7 +418,8 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
       int64_t nout = nn, nre = nn;
       if (h_batch > 0) {                                           /* step 8, Alg. 1 */
         int hn = 0;
-        nre = heuristic_rerank(ix, q, qi, scratch, nn, k, h_batch, h_eps, h_beta, rr, prev, &hn);
+        nre = heuristic_rerank(ix, q, qi, scratch, nn, k, h_batch, h_eps, h_beta, best, &hn);
+        for (int c = 0; c < hn; ++c) rr[c] = best[c].p;
         nout = hn;
       } else {                                                     /* step 8, fixed n */
         for (int64_t c = 0; c < nn; ++c) {
@@ -465,7 +443,7 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
     free(lut);
     free(buf);
     free(rr);
-    free(prev);
+    free(best);
   }
 }
 

@@ -87,7 +87,9 @@ def _load(path: str | None = None):
         lib.orc_adc.argtypes = [P, P, P, P, i64, P, P]
         lib.orc_exact.argtypes = [P, P, P, i64, P]
         lib.orc_search.argtypes = [P, P, i64, P, i32, i32, P, P, P, P, P, P, ctypes.c_int,
-                                   ctypes.c_int, i32, ctypes.c_double, i32, P]
+                                   ctypes.c_int, i32, ctypes.c_double, i32, P, P, P]
+        lib.orc_page_layout.argtypes = [P, i64, i32, i32, i32, P, P]
+        lib.orc_page_layout.restype = i64
         lib.orc_bruteforce.argtypes = [P, P, i64, i32, P, P, ctypes.c_int]
         _lib = lib
     return _lib
@@ -236,6 +238,37 @@ def exact(ix: Index, q, ids):
 
 
 @dataclass
+class PageLayout:
+    """Raw vectors on fixed-size pages, bucketed by nearest list (Sec. 4.3)."""
+    page: np.ndarray      # [n] page of each vector
+    slot: np.ndarray      # [n] slot of each vector inside its page
+    pages: int
+    per_page: int
+
+
+def page_layout(bucket_of, nbuckets: int, row_bytes: int, page_bytes: int = 4096) -> PageLayout:
+    """Buckets (one per list: the vectors whose nearest list it is, ascending
+    ID) laid out on pages of page_bytes holding whole vectors of row_bytes:
+    every bucket's full pages first, then the buckets' leftover tails combined
+    onto shared pages, largest tail first and then the largest that still fits."""
+    b = np.ascontiguousarray(np.asarray(bucket_of, dtype=np.int32))
+    n = len(b)
+    page = np.empty(n, dtype=np.int32)
+    slot = np.empty(n, dtype=np.int32)
+    np_ = _load().orc_page_layout(_p(b), n, int(nbuckets), int(row_bytes), int(page_bytes),
+                                  _p(page), _p(slot))
+    if np_ < 0:
+        raise ValueError("a vector does not fit a page")
+    return PageLayout(page, slot, int(np_), page_bytes // row_bytes)
+
+
+def index_page_layout(ix: "Index", page_bytes: int = 4096) -> PageLayout:
+    """The layout of an index's raw vectors: bucket = each vector's first (nearest) list."""
+    row = ix.dim * (4 if ix.kind == "f32" else 1)
+    return page_layout(ix.assign[:, 0], ix.nlist, row, page_bytes)
+
+
+@dataclass
 class SearchResult:
     ids: np.ndarray
     dists: np.ndarray
@@ -244,12 +277,15 @@ class SearchResult:
     ncand: np.ndarray
     nentries: np.ndarray
     reranked: np.ndarray = None
+    page_reads: np.ndarray = None
 
 
 def search(ix: Index, Q, nprobe, k: int, rerank_n: int, threads: int = 0,
-           lut_f16: bool = False, heuristic=None) -> SearchResult:
+           lut_f16: bool = False, heuristic=None, pages: PageLayout = None) -> SearchResult:
     """Steps 1-8 for a batch of queries (lut_f16: half-precision table variant;
-    heuristic = (batch_size, eps, beta): step 8 by the heuristic re-ranking)."""
+    heuristic = (batch_size, eps, beta): step 8 by the heuristic re-ranking;
+    pages: a page layout of the raw vectors, whose page reads per query are
+    then counted)."""
     Q = _q(Q)
     nq = Q.shape[0]
     npr = _np(nprobe, nq)
@@ -261,10 +297,12 @@ def search(ix: Index, Q, nprobe, k: int, rerank_n: int, threads: int = 0,
     ne = np.empty(nq, dtype=np.int64)
     hb, he, hbeta = heuristic if heuristic else (0, 0.0, 1)
     rr = np.empty(nq, dtype=np.int64)
+    pr = np.empty(nq, dtype=np.int64) if pages is not None else None
     _load().orc_search(ctypes.byref(ix.cstruct()), _p(Q), nq, _p(npr), k, rerank_n, _p(ids),
                        _p(dists), _p(tids), _p(tadc), _p(nc), _p(ne), threads,
-                       1 if lut_f16 else 0, int(hb), float(he), int(hbeta), _p(rr))
-    return SearchResult(ids, dists, tids, tadc, nc, ne, rr)
+                       1 if lut_f16 else 0, int(hb), float(he), int(hbeta), _p(rr),
+                       _p(pages.page) if pages is not None else None, _p(pr))
+    return SearchResult(ids, dists, tids, tadc, nc, ne, rr, pr)
 
 
 def bruteforce(ix: Index, Q, k: int, threads: int = 0):

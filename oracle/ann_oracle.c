@@ -278,6 +278,112 @@ static int64_t heuristic_rerank(const orc_index* ix, const double* q, const int3
 }
 
 /* ------------------------------------------------------------------------ */
+/* Raw vectors on pages (Sec. 4.3, optimized storage layout): one bucket per */
+/* posting list holding the vectors whose nearest list it is (no vector in  */
+/* two buckets), ascending ID.  A page holds floor(page_bytes / row_bytes)   */
+/* whole vectors.  Each bucket's full pages come first, bucket by bucket;   */
+/* the leftover tails (fewer vectors than a page) are then combined onto    */
+/* shared pages: a new page takes the largest remaining tail, then keeps     */
+/* taking the largest remaining tail that still fits its free slots (ties:  */
+/* lower bucket), until none fits.  Reading of the paper's max-min          */
+/* combination of unaligned bucket portions.                                 */
+
+typedef struct {
+  int32_t* head; /* per tail size: first bucket on that size's list, ascending bucket */
+  int32_t* next;
+} tail_lists;
+
+int64_t orc_page_layout(const int32_t* bucket_of, int64_t n, int32_t nbuckets, int32_t row_bytes,
+                        int32_t page_bytes, int32_t* page, int32_t* slot) {
+  const int P = page_bytes / row_bytes;
+  if (P < 1) return -1;
+  int64_t* cnt = (int64_t*)calloc((size_t)nbuckets + 1, sizeof(int64_t));
+  for (int64_t v = 0; v < n; ++v) cnt[bucket_of[v] + 1]++;
+  for (int b = 0; b < nbuckets; ++b) cnt[b + 1] += cnt[b]; /* bucket starts */
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)nbuckets);
+  int32_t* members = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  for (int b = 0; b < nbuckets; ++b) fill[b] = cnt[b];
+  for (int64_t v = 0; v < n; ++v) members[fill[bucket_of[v]]++] = (int32_t)v; /* ascending ID */
+  int64_t pages = 0;
+  for (int b = 0; b < nbuckets; ++b) { /* full pages */
+    const int64_t c = cnt[b + 1] - cnt[b];
+    for (int64_t i = 0; i < c / P * P; ++i) {
+      const int32_t v = members[cnt[b] + i];
+      page[v] = (int32_t)(pages + i / P);
+      slot[v] = (int32_t)(i % P);
+    }
+    pages += c / P;
+  }
+  /* tails, largest first; per size a list of buckets in ascending order */
+  tail_lists tl;
+  tl.head = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+  tl.next = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nbuckets > 0 ? nbuckets : 1));
+  int32_t* tail = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+  for (int t = 0; t < P; ++t) tl.head[t] = tail[t] = -1;
+  int64_t left = 0;
+  for (int b = 0; b < nbuckets; ++b) {
+    const int t = (int)((cnt[b + 1] - cnt[b]) % P);
+    tl.next[b] = -1;
+    if (t == 0) continue;
+    if (tail[t] < 0) tl.head[t] = b;
+    else tl.next[tail[t]] = b;
+    tail[t] = b;
+    ++left;
+  }
+  while (left > 0) {
+    int free_slots = P, used = 0;
+    for (;;) {
+      int t = free_slots < P - 1 ? free_slots : P - 1;
+      while (t > 0 && tl.head[t] < 0) --t;
+      if (t == 0) break;
+      const int b = tl.head[t];
+      tl.head[t] = tl.next[b];
+      const int64_t c = cnt[b + 1] - cnt[b];
+      for (int i = 0; i < t; ++i) {
+        const int32_t v = members[cnt[b] + c - t + i];
+        page[v] = (int32_t)pages;
+        slot[v] = used + i;
+      }
+      used += t;
+      free_slots -= t;
+      --left;
+    }
+    ++pages;
+  }
+  free(cnt);
+  free(fill);
+  free(members);
+  free(tl.head);
+  free(tl.next);
+  free(tail);
+  return pages;
+}
+
+/* Pages read for one query's re-ranking with intra- and inter-mini-batch
+ * de-duplication (Sec. 4.3): the candidates are re-ranked in mini-batches
+ * (the fixed re-rank is one mini-batch of all of them); a mini-batch reads
+ * each page its candidates lie on once, and none that an earlier mini-batch
+ * of the same query has already read (those stay in the buffer).  `order`:
+ * the candidates in visiting order, of which the first `used` were re-ranked
+ * in mini-batches of `batch`.  `seen` has room for `used` page IDs. */
+static int64_t count_page_reads(const int32_t* page, const pair_t* order, int64_t used,
+                                int64_t batch, int32_t* seen) {
+  int64_t nseen = 0, reads = 0;
+  for (int64_t b0 = 0; b0 < used; b0 += batch) {
+    const int64_t b1 = used - b0 > batch ? b0 + batch : used;
+    const int64_t before = nseen; /* pages held when the mini-batch starts */
+    for (int64_t i = b0; i < b1; ++i) {
+      const int32_t pg = page[order[i].id];
+      int have = 0;
+      for (int64_t j = 0; j < nseen && !have; ++j) have = seen[j] == pg;
+      if (!have) seen[nseen++] = pg;
+    }
+    reads += nseen - before;
+  }
+  return reads;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Public entry points.  All arrays are host arrays owned by the caller.     */
 
 /* Step 2 for a batch.  probe/pdist: nq x nprobe_max, padded with -1/+inf. */
@@ -373,11 +479,14 @@ void orc_exact(const orc_index* ix, const float* q32, const int32_t* ids, int64_
  *                        mini-batches of h_batch, threshold h_eps, count h_beta;
  *                        0: the fixed-n re-rank
  *   reranked             optional nq: candidates whose exact distance was computed
+ *   page, page_reads     optional: the page of every vector (orc_page_layout) and,
+ *                        per query, the pages its re-ranking reads (Sec. 4.3)
  */
 void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* nprobe,
                 int32_t k, int32_t rerank_n, int64_t* ids, float* dists, int32_t* topn_ids,
                 float* topn_adc, int64_t* ncand, int64_t* nentries, int nthreads, int lut_f16,
-                int32_t h_batch, double h_eps, int32_t h_beta, int64_t* reranked) {
+                int32_t h_batch, double h_eps, int32_t h_beta, int64_t* reranked,
+                const int32_t* page, int64_t* page_reads) {
   int64_t maxg = ix->offsets[ix->nlist];
   if (maxg < 1) maxg = 1;
 #ifdef _OPENMP
@@ -393,6 +502,7 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
     int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * maxg);
     pair_t* rr = (pair_t*)malloc(sizeof(pair_t) * (rerank_n > 0 ? rerank_n : 1));
     member_t* best = (member_t*)malloc(sizeof(member_t) * (k > 0 ? k : 1));
+    int32_t* seen = (int32_t*)malloc(sizeof(int32_t) * (rerank_n > 0 ? rerank_n : 1));
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 1)
 #endif
@@ -433,6 +543,9 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
         dists[i * k + c] = c < nout ? rr[c].d : INFINITY;
       }
       if (reranked) reranked[i] = nre;
+      if (page && page_reads)
+        page_reads[i] = count_page_reads(page, scratch, nre, h_batch > 0 ? h_batch : (nn > 0 ? nn : 1),
+                                         seen);
       if (ncand) ncand[i] = nu;
       if (nentries) nentries[i] = g;
     }
@@ -444,6 +557,7 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
     free(buf);
     free(rr);
     free(best);
+    free(seen);
   }
 }
 

@@ -1,15 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the GPU filtering stage on one MI355X.
 
-Workload (default): 10M uint8 vectors of dimension 128 drawn from a seeded
-Gaussian mixture (4096 centres), IVF with 16384 lists (Eq. 2 replication,
-at most 2 lists per vector), PQ with 32 subspaces x 256 codewords, 10,000
-queries, nprobe 64, rerank_n 200, k 10.  A step is one pass of the whole path
-(probe, distance table, gather + dedup, Eq. 1 scan, top-n, exact re-rank)
-over all queries, with the index and the queries already in HBM.
+Workload (default): 100M int8 vectors of dimension 100 drawn from a seeded
+Gaussian mixture (8192 centres U[-128,127]^100, sigma 10, rounded and
+clipped), IVF with 65536 lists (Eq. 2 replication, at most 2 lists per
+vector), PQ with 50 subspaces x 256 codewords (5 GB of codes, raw vectors in
+HBM), 10,000 queries, nprobe 64, k 10, rerank_n at the recall@10 >= 0.9
+operating point.  The index is built on the host first (about 2.5 minutes).
+A step is one pass of the whole path (probe, distance table, gather + dedup,
+Eq. 1 scan, top-n, exact re-rank) over all queries, with the index and the
+queries already in HBM.  --workload ivf_u8_10m runs the 10M uint8 one.
 
 Forms timed:
-  plain    one ann_search call per batch of 256 queries (default work split)
+  plain    one ann_search call per batch of 256 queries (default work split);
+           also the latency of single-query calls
   batched  the whole batch as one HIP-graph launch (ann_graph_launch) with the
            work split the autotuner picked; its per-stage times come from an
            event-bracketed eager run of the same search ("batched_eager")
@@ -19,7 +23,9 @@ The headline value is the batched form's queries/s.
 
 Also reported: candidates/s, recall@10 against exact kNN of a query sample,
 bit-exact parity of a query sample against the CPU oracle, the scan kernel's
-roofline (HBM), and the CPU oracle's own throughput on a bounded sample.
+roofline (HBM: code bytes of the scored candidates plus 4 bytes per replica
+entry walked, over the scan's per-launch time from HIP events), and the CPU
+oracle's own throughput on a bounded sample (all host threads, and one).
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -39,6 +45,23 @@ HBM_PEAK_GBS = 8000.0
 SCAN_SOURCES = ["paper_2409_16576_amd/csrc/ann_kernels.hip"]
 
 
+# Per-workload defaults, sized so a default run (index build included) ends
+# within a few minutes: oracle sample, brute-force sample, served loads
+# (million queries/s) and window, heuristic (rerank_n, batch, eps, beta).
+WORKLOAD_DEFAULTS = {
+    "serve_i8_100m": dict(cpu_queries=2000, recall_queries=200,
+                          served_rates="0.005,0.01,0.02,0.05,0.2,0.5", served_seconds=2.0,
+                          heur="400,100,0,2"),
+    "ivf_u8_10m": dict(cpu_queries=10000, recall_queries=500,
+                       served_rates="0.25,0.5,1,1.5,2,3", served_seconds=1.5,
+                       heur="2000,200,0,2"),
+    "zipf_f32_5m": dict(cpu_queries=2000, recall_queries=200, served_rates="0.1,0.2,0.5",
+                        served_seconds=1.5, heur="3200,400,0,2"),
+    "ivf_f32_100k": dict(cpu_queries=1000, recall_queries=1000, served_rates="0.1,0.5,1",
+                         served_seconds=1.0, heur="800,100,0,2"),
+}
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -51,10 +74,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str):
-    """HBM traffic per scan launch from the committed counter summary, if it
-    was taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", f"scan_traffic_{workload}.json")
+def load_traffic(stage: str, workload: str):
+    """HBM traffic per launch of a stage's kernel from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{stage}_{workload}.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
@@ -69,25 +92,27 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="ivf_u8_10m")
+    ap.add_argument("--workload", default="serve_i8_100m")
     ap.add_argument("--plain-batch", type=int, default=256)
-    ap.add_argument("--cpu-queries", type=int, default=10000)
-    ap.add_argument("--recall-queries", type=int, default=500)
+    ap.add_argument("--cpu-queries", type=int, default=None)
+    ap.add_argument("--recall-queries", type=int, default=None)
     ap.add_argument("--rerank-n", type=int, default=0,
                     help="top-n re-ranked (default: the workload's recall>=0.9 operating point)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--forms", default="plain,batched,served,heuristic")
-    ap.add_argument("--heur", default="2000,200,0,2",
+    ap.add_argument("--heur", default=None,
                     help="heuristic form: rerank_n,batch_size,eps,beta (Alg. 1)")
-    ap.add_argument("--served-rates", default="0.25,0.5,1,1.5,2,3",
+    ap.add_argument("--served-rates", default=None,
                     help="offered loads of the served form, million queries/s")
-    ap.add_argument("--served-seconds", type=float, default=1.5,
+    ap.add_argument("--served-seconds", type=float, default=None,
                     help="arrival window per offered load")
     ap.add_argument("--lut16", action="store_true",
                     help="half-precision distance table (binary16 entries, float32 sums)")
     ap.add_argument("--split", type=int, default=0,
                     help="batched form: this work split instead of the autotuner's")
     ap.add_argument("--tile", type=int, default=65536, help="with --split: entries per item")
+    ap.add_argument("--lm", default="",
+                    help="with --split: list-major alpha,rows,blocks instead of per-query only")
     ap.add_argument("--build-only", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
@@ -98,6 +123,9 @@ def parse():
         ap.error(f"--forms: unknown form(s) {sorted(set(names) - known)}")
     if not set(names) - {"served"}:
         ap.error("--forms: the stage times and the roofline need plain, batched or heuristic too")
+    for key, v in WORKLOAD_DEFAULTS.get(args.workload, WORKLOAD_DEFAULTS["ivf_u8_10m"]).items():
+        if getattr(args, key) is None:
+            setattr(args, key, v)
     return args
 
 
@@ -352,9 +380,11 @@ def main():
     rep_q = entries_q - prim_q
     rep_walked = int((nwalk - prim_q).sum())
     cand_per_step = int(ncand.sum())
+    # algorithmic bytes of the scan: M code bytes per scored candidate and a
+    # 4-byte ID per replica entry walked (first-list members are a row range:
+    # no ID read); the distance table is built on chip and not counted
     M = g.desc["m"]
-    row_bytes = (M + 3) // 4 * 4
-    scan_alg_bytes = cand_per_step * row_bytes + rep_walked * 8 + nq * M * 256 * 4
+    scan_alg_bytes = cand_per_step * M + rep_walked * 4
     log(f"per step: {cand_per_step} candidates, {int(entries_q.sum())} list entries "
         f"({int(rep_q.sum())} replica), {int(nwalk.sum())} walked ({rep_walked} replica); "
         f"scan algorithmic bytes {scan_alg_bytes / 1e9:.2f} GB")
@@ -384,35 +414,50 @@ def main():
     forms = {"plain": step_plain, "batched": step_graph, "batched_eager": step_eager,
              "heuristic": step_heur}
     names = args.forms.split(",")
-    default_split = (g.get_option(g.OPT_SCAN_TILE), g.get_option(g.OPT_SCAN_SPLIT))
+    # tuning options (none changes results): the index's defaults for the
+    # plain form, the autotuner's choice for the batched form
+    OPTS = (g.OPT_SCAN_TILE, g.OPT_SCAN_SPLIT, g.OPT_LIST_MAJOR, g.OPT_LM_ALPHA, g.OPT_LM_TILE,
+            g.OPT_LM_BLOCKS)
+
+    def get_opts():
+        return {o: g.get_option(o) for o in OPTS}
+
+    def set_opts(d):
+        for o, v in d.items():
+            g.set_option(o, v)
+
+    default_opts = get_opts()
     if "batched" in names:
-        # the batched form: work split picked by the autotuner for this batch
-        # (or given), then the whole search captured once into a HIP graph; its
-        # stage times (and the scan roofline) come from an eager,
+        # the batched form: options picked by the autotuner for this batch (or
+        # a given per-query split), then the whole search captured once into a
+        # HIP graph; its stage times (and the roofline) come from an eager,
         # event-bracketed run of the same search right after
         if args.split:
             g.set_option(g.OPT_SCAN_TILE, args.tile)
             g.set_option(g.OPT_SCAN_SPLIT, args.split)
-            tuned = {"tile": args.tile, "split": args.split, "tried": 0, "ms": 0.0}
+            tuned = {"tile": args.tile, "split": args.split, "tried": 0, "ms": 0.0,
+                     "list_major": 0}
+            if args.lm:
+                la, lt, lb = (int(x) for x in args.lm.split(","))
+                for o, v in ((g.OPT_LIST_MAJOR, 1), (g.OPT_LM_ALPHA, la), (g.OPT_LM_TILE, lt),
+                             (g.OPT_LM_BLOCKS, lb)):
+                    g.set_option(o, v)
+                tuned.update(list_major=1, lm_alpha=la, lm_tile=lt, lm_blocks=lb)
         else:
             tuned = ann.autotune(g, Q, nprobe_arg, k, n, reps=2)
-        log(f"work split: tile {tuned['tile']}, split {tuned['split']} ({tuned['tried']} tried, "
-            f"{tuned['ms']:.3f} ms)")
+        log(f"autotuned: {tuned}")
         graph = ann.Graph(g, Q, nprobe_arg, k, n)
         names.insert(names.index("batched") + 1, "batched_eager")
-    batched_split = (g.get_option(g.OPT_SCAN_TILE), g.get_option(g.OPT_SCAN_SPLIT))
+    batched_opts = get_opts()
     results = {}
     for name in names:
         if name == "served":  # the server launches with the tuned work split
-            g.set_option(g.OPT_SCAN_TILE, batched_split[0])
-            g.set_option(g.OPT_SCAN_SPLIT, batched_split[1])
+            set_opts({**batched_opts, g.OPT_LIST_MAJOR: 0})
             results[name] = run_served(ann, g, Qh, npq, w, k, n, args)
             continue
         fn = forms[name]
-        # plain runs with the index's default work split
-        sp = batched_split if name.startswith("batched") or name == "heuristic" else default_split
-        g.set_option(g.OPT_SCAN_TILE, sp[0])
-        g.set_option(g.OPT_SCAN_SPLIT, sp[1])
+        set_opts(batched_opts if name.startswith("batched") or name == "heuristic"
+                 else default_opts)
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
@@ -443,22 +488,80 @@ def main():
             f"{results[name]['candidates_per_s'] / 1e9:.2f} G cand/s, stages "
             + ", ".join(f"{s} {v['ms'] / args.steps:.3f}ms" for s, v in prof.items()))
 
+    if "plain" in results:
+        # latency of single-query calls (plain form, batch of one): each call is
+        # timed from submission to completion on the host clock
+        set_opts(default_opts)
+        lat = []
+        for i in range(220):
+            npb = nprobe_arg if fixed_np else nprobe_arg[i % nq:i % nq + 1]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.search(Q[i % nq:i % nq + 1], npb, k, n)
+            torch.cuda.synchronize()
+            if i >= 20:
+                lat.append((time.perf_counter() - t0) * 1e3)
+        lat = np.array(lat)
+        results["plain"]["batch1_latency_ms"] = {
+            "p50": round(float(np.percentile(lat, 50)), 4),
+            "p99": round(float(np.percentile(lat, 99)), 4),
+            "mean": round(float(lat.mean()), 4), "calls": int(lat.size)}
+        log(f"plain, one query per call: p50 {np.percentile(lat, 50):.3f} ms, "
+            f"p99 {np.percentile(lat, 99):.3f} ms")
+
     head = "batched" if "batched" in results else [f for f in results if f != "served"][0]
     R = results[head]
     RS = results["batched_eager"] if head == "batched" else R  # stage times (events)
-    scan_ms = RS["stage_ms_per_step"]["scan"]
-    scan_launches = max(1, RS["stage_launches_per_step"]["scan"])
-    achieved = scan_alg_bytes / (scan_ms / 1e3) / 1e9
-    tr = load_traffic(w.name)
+    st_ms, st_n = RS["stage_ms_per_step"], RS["stage_launches_per_step"]
+    lm_on = head == "batched" and batched_opts[g.OPT_LIST_MAJOR] == 1
+    lm = None
+    if lm_on:
+        # the list-major pass's work, from the probe lists and the same split
+        # rule the kernels apply (first-list rows of each query's leading lists
+        # until alpha * n rows stay with the per-query scan)
+        alpha = batched_opts[g.OPT_LM_ALPHA]
+        npv = valid.sum(1)
+        plen = np.where(valid, primary[lsafe], 0)
+        csum = np.cumsum(plen, axis=1)
+        reach = csum >= alpha * n
+        first = np.where(reach.any(1), reach.argmax(1) + 1, lists.shape[1])
+        walkp = np.minimum(first, npv)
+        slot = np.arange(lists.shape[1])[None, :]
+        in2 = valid & (slot >= walkp[:, None]) & (slot < npv[:, None]) & (plen > 0)
+        cnt_l = np.bincount(lists[in2], minlength=len(primary))
+        groups = (cnt_l + 15) // 16
+        lm = {"pairs_per_step": int((plen * in2).sum()),
+              "rows_distinct_per_step": int(primary[cnt_l > 0].sum()),
+              "rows_read_per_step": int((groups * primary).sum()),
+              "query_groups_per_step": int(groups.sum()), "alpha": int(alpha)}
+        log(f"list-major: {lm}")
+    # dominant kernel: the per-query scan or the list-major launch
+    kern = "scan"
+    if lm_on and st_ms.get("list_major", 0.0) > st_ms["scan"]:
+        kern = "list_major"
+    launches = max(1, st_n[kern])
+    if kern == "scan":
+        cand_q = cand_per_step - (lm["pairs_per_step"] if lm else 0)
+        alg_bytes = cand_q * M + rep_walked * 4
+        kname = "k_scan (fused gather/dedup/Eq.1/top-n)"
+        extra = {"replica_entries_walked_per_step": rep_walked,
+                 "replica_entries_listed_per_step": int(rep_q.sum()),
+                 "candidates_scored_per_step": cand_q}
+    else:
+        # each probed list's code rows read once (M bytes a row)
+        alg_bytes = lm["rows_distinct_per_step"] * M
+        kname = "k_lm_mfma (list-major decode + int8 MFMA Eq. 1 + threshold)"
+        extra = dict(lm)
+    # bytes per launch / average launch time = bytes per step / kernel time per step
+    achieved = alg_bytes / (st_ms[kern] / 1e3) / 1e9
+    tr = load_traffic(kern, w.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": (tr["bytes_per_step"] if tr else None),
-                "kernel": "k_scan (fused gather/dedup/Eq.1/top-n)",
-                "scan_ms_per_launch": round(scan_ms / scan_launches, 4),
-                "scan_launches_per_step": scan_launches,
-                "algorithmic_bytes_per_step": scan_alg_bytes,
-                "replica_entries_walked_per_step": rep_walked,
-                "replica_entries_listed_per_step": int(rep_q.sum())}
+                "traffic": (tr["bytes_per_launch"] if tr else None),
+                "kernel": kname, "stage": kern,
+                "ms_per_launch": round(st_ms[kern] / launches, 4),
+                "launches_per_step": launches,
+                "algorithmic_bytes_per_launch": alg_bytes // launches, **extra}
 
     line = {
         "metric": METRIC, "value": round(R["qps"], 1), "unit": "queries/s", "n_gpus": 1,
@@ -475,7 +578,7 @@ def main():
         "roofline": roofline,
     }
     if tuned:
-        line["config"]["tuned_split"] = {"tile": tuned["tile"], "split": tuned["split"]}
+        line["config"]["tuned"] = {kk: vv for kk, vv in tuned.items() if kk not in ("ms", "tried")}
     if "plain" in results and "batched" in results:
         line["batched_over_plain"] = round(results["batched"]["qps"] / results["plain"]["qps"], 3)
     if "plain" in results and "served" in results:
@@ -493,8 +596,11 @@ def main():
 
         log("oracle leg: reading the index on the host")
         oracle.build(force=False)
+        oracle.use_native()  # -march=native copy for this host (same arithmetic)
         oix = oracle.read_index(path, verify=False)
-        threads = os.cpu_count() or 1
+        # the host's CPU share for this GPU (OMP_NUM_THREADS where the host sets it)
+        threads = min(len(os.sched_getaffinity(0)),
+                      int(os.environ.get("OMP_NUM_THREADS") or 0) or 1 << 30) or 1
         ns = min(args.cpu_queries, nq)
         t0 = time.perf_counter()
         r = oracle.search(oix, Qh[:ns], npq[:ns], k, n, threads=threads, lut_f16=args.lut16)
@@ -510,6 +616,14 @@ def main():
                                 "cores": threads, "kind": "oracle",
                                 "sample": f"first {ns} of {nq} queries, full index, same knobs",
                                 "candidates_per_s": round(float(r.ncand.sum()) / cpu_s, 1)}
+        # the same oracle on one thread, on a smaller sample
+        n1 = max(1, ns // max(1, threads) // 2)
+        t0 = time.perf_counter()
+        oracle.search(oix, Qh[:n1], npq[:n1], k, n, threads=1, lut_f16=args.lut16)
+        cpu1_s = time.perf_counter() - t0
+        line["cpu_baseline"]["one_thread"] = {"value": round(n1 / cpu1_s, 2), "unit": "queries/s",
+                                              "sample": f"first {n1} queries"}
+        log(f"oracle, one thread: {n1} queries in {cpu1_s:.2f}s")
         nr = min(args.recall_queries, nq)
         t0 = time.perf_counter()
         gt, _ = oracle.bruteforce(oix, Qh[:nr], k, threads=threads)

@@ -70,7 +70,25 @@ typedef struct {
   int64_t hbm_bytes;       /* device memory held by the index */
   int32_t device;
   int32_t max_rerank_n;    /* largest rerank_n accepted */
+  int32_t raw_tier;        /* 0: raw vectors in HBM; 1: on pages in pinned host memory */
+  int32_t page_bytes;      /* raw tier 1: bytes per page */
+  int64_t pages;           /* raw tier 1: pages */
+  int64_t host_bytes;      /* raw tier 1: pinned host memory held by the index */
 } ann_index_desc;
+
+/*
+ * Load options.  raw_tier 0 (default): raw vectors in HBM, by external ID.
+ * raw_tier 1: the raw vectors stay in pinned host memory (hipHostMalloc) on
+ * pages of page_bytes (0: 4096), laid out by ann_page_layout with each
+ * vector's nearest list as its bucket (Sec. 4.3); only their page and slot
+ * numbers go to HBM.  Re-ranking then reads whole pages over PCIe (see
+ * ann_search_pages); rerank_n is limited to 2048 and ann_rerank is not
+ * available.
+ */
+typedef struct {
+  int32_t raw_tier;
+  int32_t page_bytes;  /* multiple of 16 in [16, 65536], at least one vector */
+} ann_load_cfg;
 
 /*
  * Load an index file (format: the paper's offline output, Sec. 3 / Sec. 4.1:
@@ -84,6 +102,12 @@ typedef struct {
  */
 ann_status ann_load_index(const char* path, int device, ann_index** out);
 
+/* ann_load_index with options (cfg NULL: the defaults).  Errors as
+ * ann_load_index; ANN_EINVAL for a bad option, ANN_ENOMEM also when the host
+ * pages cannot be allocated. */
+ann_status ann_load_index_ex(const char* path, int device, const ann_load_cfg* cfg,
+                             ann_index** out);
+
 /* Describe a loaded index.  Errors: ANN_EINVAL (NULL). */
 ann_status ann_index_info(const ann_index* ix, ann_index_desc* out);
 
@@ -93,6 +117,23 @@ void ann_free_index(ann_index* ix);
 
 /* Message of the last error on this thread ("" if none). */
 const char* ann_last_error(void);
+
+/*
+ * Layout of raw vectors on pages (Sec. 4.3, optimized storage layout), as the
+ * host-memory raw tier uses it: vectors are bucketed by bucket_of[v] (the
+ * nearest list), ascending ID inside a bucket; a page of page_bytes holds
+ * floor(page_bytes / row_bytes) whole vectors.  Every bucket's whole pages
+ * come first, bucket by bucket; the leftover tails are then packed onto
+ * shared pages -- each new page takes the largest remaining tail, then keeps
+ * adding the largest remaining tail that still fits (equal sizes: lower
+ * bucket first) -- so no tail is split over two pages.
+ *   bucket_of  host int32 [n], values in [0, nbuckets)
+ *   page, slot host int32 [n] outputs: page of each vector, position on it
+ * Returns the number of pages, or -1 on bad arguments (ann_last_error says
+ * which).  Host-only; touches no device.
+ */
+int64_t ann_page_layout(const int32_t* bucket_of, int64_t n, int32_t nbuckets, int32_t row_bytes,
+                        int32_t page_bytes, int32_t* page, int32_t* slot);
 
 /*
  * Steps 1-8 (plain form): search nq queries.
@@ -147,6 +188,31 @@ ann_status ann_search_topn(ann_index* ix, const float* d_queries, int64_t nq,
                            int64_t* d_out_nwalk, void* stream);
 
 /*
+ * Steps 1-8 on an index loaded with the host-memory raw tier (raw_tier 1),
+ * reporting the I/O of step 8 (Sec. 4.3, redundancy-aware I/O
+ * de-duplication).  Step 8 is the fixed re-rank of all rerank_n candidates
+ * (batch_size 0) or the heuristic re-ranking of Alg. 1 (batch_size >= 1,
+ * eps, beta as for ann_search_heuristic).  The candidates' raw vectors are
+ * read a whole page at a time from host memory: a page is read in the first
+ * mini-batch that re-ranks a candidate on it, and that one read serves every
+ * candidate of the query on the page -- requests for one page within a
+ * mini-batch are merged, and later mini-batches find their candidates on it
+ * already read (the page buffer across mini-batches).  Results equal
+ * ann_search / ann_search_heuristic on the same index kept in HBM.
+ *   d_out_reranked    optional int32 [nq]: candidates re-ranked
+ *   d_out_page_reads  optional int32 [nq]: pages read = distinct pages of
+ *                     the re-ranked candidates
+ * k <= rerank_n <= 2048 (and k <= 64 with batch_size >= 1).  Errors as
+ * ann_search_heuristic; ANN_EUNSUPPORTED on an index whose raw vectors are
+ * in HBM.
+ */
+ann_status ann_search_pages(ann_index* ix, const float* d_queries, int64_t nq,
+                            const int32_t* d_nprobe, int32_t nprobe_max, int32_t k,
+                            int32_t rerank_n, int32_t batch_size, double eps, int32_t beta,
+                            int64_t* d_out_ids, float* d_out_dists, int32_t* d_out_reranked,
+                            int32_t* d_out_page_reads, void* stream);
+
+/*
  * Step 2 alone: the nearest lists of each query, ascending by
  * (centroid distance, list id).
  *   d_out_lists int32 [nq, nprobe_max] (-1 padded)
@@ -192,12 +258,14 @@ ann_status ann_rerank(ann_index* ix, const float* d_queries, int64_t nq, const i
  * this index is bracketed by a pair of HIP events recorded on the caller's
  * stream.  ann_get_profile waits for the recorded events, returns the summed
  * elapsed times and launch counts, and (reset != 0) clears them.
- * Stages: 0 probe (distances + selection), 1 distance table, 2 scan
- * (planning + fused gather/dedup/Eq. 1/top-n), 3 merge + exact re-rank.
+ * Stages: 0 probe (distances + selection), 1 distance table, 2 per-query
+ * scan (planning + fused gather/dedup/Eq. 1/top-n), 3 merge + exact re-rank,
+ * 4 the list-major launch (ANN_OPT_LIST_MAJOR), 5 the list-major pass's
+ * bookkeeping (split, work list, per-query selection).
  */
 typedef struct {
-  double ms[4];
-  int64_t launches[4];
+  double ms[6];
+  int64_t launches[6];
 } ann_profile;
 
 ann_status ann_set_profiling(ann_index* ix, int enable);
@@ -217,6 +285,28 @@ ann_status ann_get_profile(ann_index* ix, ann_profile* out, int reset);
  *                       (default): input order.  Measured on the uint8 10M
  *                       workload the ordered scan was slower (2.32 vs 2.11
  *                       ms), so it stays off unless chosen.
+ * Batched form on integer-grid indexes (no effect on any result):
+ *   ANN_OPT_LIST_MAJOR  1: searches run list-major -- the (query, probed
+ *                       list) pairs of a chunk are inverted into per-list
+ *                       groups of up to 16 queries, and one persistent launch
+ *                       reads each probed list's code rows once per group,
+ *                       decodes them and scores the group on the int8 matrix
+ *                       cores (Eq. 1 equals ||q - decoded||^2 exactly there);
+ *                       the replica entries and a few leading lists per query
+ *                       stay with the per-query scan, which also bounds each
+ *                       query's top-n.  0 (default): per-query scan only.
+ *                       Applies to ann_search, ann_search_heuristic,
+ *                       ann_search_topn and graphs created while it is set;
+ *                       ignored on float indexes.
+ *   ANN_OPT_LM_ALPHA    the per-query part walks the first-list rows of the
+ *                       leading probed lists until alpha * rerank_n rows, in
+ *                       [1, 64] (default 2)
+ *   ANN_OPT_LM_TILE     rows of a list per work item, in [64, 2^24] (default 4096)
+ *   ANN_OPT_LM_BLOCKS   blocks of the persistent launch, in [0, 65536]
+ *                       (default 0: four per compute unit)
+ *   ANN_OPT_LM_CAP      list-major keys kept per query before it falls back
+ *                       to the per-query scan, in [0, 2^20] (default 0:
+ *                       min(32768, max(4096, 16 * rerank_n)))
  * Numeric variant (changes results, deterministically):
  *   ANN_OPT_LUT_F16     1: the distance table of Eq. 1 is held in binary16 --
  *                       each float32 entry rounded to the nearest binary16,
@@ -228,7 +318,17 @@ ann_status ann_get_profile(ann_index* ix, ann_profile* out, int reset);
  *                       ann_scan_trace stay float32.
  * Errors: ANN_EINVAL for an unknown option or an out-of-range value.
  */
-enum { ANN_OPT_SCAN_TILE = 1, ANN_OPT_SCAN_SPLIT = 2, ANN_OPT_LUT_F16 = 3, ANN_OPT_SCAN_ORDER = 4 };
+enum {
+  ANN_OPT_SCAN_TILE = 1,
+  ANN_OPT_SCAN_SPLIT = 2,
+  ANN_OPT_LUT_F16 = 3,
+  ANN_OPT_SCAN_ORDER = 4,
+  ANN_OPT_LIST_MAJOR = 5,
+  ANN_OPT_LM_ALPHA = 6,
+  ANN_OPT_LM_TILE = 7,
+  ANN_OPT_LM_BLOCKS = 8,
+  ANN_OPT_LM_CAP = 9
+};
 ann_status ann_set_option(ann_index* ix, int option, int64_t value);
 ann_status ann_get_option(ann_index* ix, int option, int64_t* value);
 
@@ -254,19 +354,26 @@ ann_status ann_graph_launch(ann_graph* g, void* stream);
 void ann_graph_free(ann_graph* g); /* waits for its last launch; NULL is a no-op */
 
 /*
- * Autotuner of the scan's work split for a batch: runs ann_search on the
- * given queries for each candidate (tile in {4096 .. 131072, 2^30}, split in
- * {1, 2, 4, 8, 16}), `reps` timed runs each after one warm-up, keeps the
- * split with the lowest median time and sets it on the index
- * (ANN_OPT_SCAN_TILE / ANN_OPT_SCAN_SPLIT).  The split never changes results.
- * Synchronous; allocates temporary outputs.  Errors: as ann_search, ANN_EINVAL
- * for reps outside [1, 100].
+ * Autotuner of the batched form for a batch: runs ann_search on the given
+ * queries for each candidate, `reps` timed runs each after one warm-up, and
+ * keeps the one with the lowest median time, setting its options on the
+ * index.  Candidates: first the per-query scan's work split (tile in {4096 ..
+ * 131072, 2^30}, split in {1, 2, 4, 8, 16}, ANN_OPT_LIST_MAJOR 0); then, on
+ * integer-grid indexes, the list-major form with the best split (alpha in
+ * {1, 2, 4, 8}, rows per work item in {1024, 4096, 16384}, persistent blocks
+ * in {2, 4, 8} per compute unit).  No option changes results.  Synchronous;
+ * allocates temporary outputs.  Errors: as ann_search, ANN_EINVAL for reps
+ * outside [1, 100].
  */
 typedef struct {
-  int64_t tile;   /* chosen ANN_OPT_SCAN_TILE */
-  int32_t split;  /* chosen ANN_OPT_SCAN_SPLIT */
-  int32_t tried;  /* candidates timed */
-  double ms;      /* median search time of the chosen split */
+  int64_t tile;        /* chosen ANN_OPT_SCAN_TILE */
+  int32_t split;       /* chosen ANN_OPT_SCAN_SPLIT */
+  int32_t tried;       /* candidates timed */
+  double ms;           /* median search time of the chosen candidate */
+  int32_t list_major;  /* chosen ANN_OPT_LIST_MAJOR; when 1, the three below */
+  int32_t lm_alpha;    /* ANN_OPT_LM_ALPHA */
+  int32_t lm_tile;     /* ANN_OPT_LM_TILE */
+  int32_t lm_blocks;   /* ANN_OPT_LM_BLOCKS */
 } ann_tune_result;
 ann_status ann_autotune(ann_index* ix, const float* d_queries, int64_t nq, const int32_t* d_nprobe,
                         int32_t nprobe_max, int32_t k, int32_t rerank_n, int32_t reps,

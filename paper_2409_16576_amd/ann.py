@@ -32,20 +32,27 @@ class IndexDesc(ctypes.Structure):
         ("dsub", ctypes.c_int32), ("r", ctypes.c_int32), ("int_grid", ctypes.c_int32),
         ("entries", ctypes.c_int64), ("replica_entries", ctypes.c_int64),
         ("max_list", ctypes.c_int64), ("hbm_bytes", ctypes.c_int64), ("device", ctypes.c_int32),
-        ("max_rerank_n", ctypes.c_int32),
+        ("max_rerank_n", ctypes.c_int32), ("raw_tier", ctypes.c_int32),
+        ("page_bytes", ctypes.c_int32), ("pages", ctypes.c_int64), ("host_bytes", ctypes.c_int64),
     ]
+
+
+class LoadCfg(ctypes.Structure):
+    _fields_ = [("raw_tier", ctypes.c_int32), ("page_bytes", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4)]
+    _fields_ = [("ms", ctypes.c_double * 6), ("launches", ctypes.c_int64 * 6)]
 
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int64), ("split", ctypes.c_int32), ("tried", ctypes.c_int32),
-                ("ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("list_major", ctypes.c_int32),
+                ("lm_alpha", ctypes.c_int32), ("lm_tile", ctypes.c_int32),
+                ("lm_blocks", ctypes.c_int32)]
 
 
 class ServerCfg(ctypes.Structure):
@@ -65,7 +72,7 @@ class ServerStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-STAGES = ("probe", "lut", "scan", "merge_rerank")
+STAGES = ("probe", "lut", "scan", "merge_rerank", "list_major", "lm_worklist")
 
 _lib = None
 
@@ -81,6 +88,10 @@ def lib():
         P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         L.ann_last_error.restype = ctypes.c_char_p
         L.ann_load_index.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(P)]
+        L.ann_load_index_ex.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(LoadCfg),
+                                        ctypes.POINTER(P)]
+        L.ann_search_pages.argtypes = [P, P, i64, P, i32, i32, i32, i32, ctypes.c_double, i32,
+                                       P, P, P, P, P]
         L.ann_index_info.argtypes = [P, ctypes.POINTER(IndexDesc)]
         L.ann_free_index.argtypes = [P]
         L.ann_free_index.restype = None
@@ -118,7 +129,8 @@ def lib():
                   "ann_get_profile", "ann_set_option", "ann_get_option", "ann_server_start",
                   "ann_server_submit", "ann_server_poll", "ann_server_get_stats",
                   "ann_server_stop", "ann_graph_create", "ann_graph_launch", "ann_autotune",
-                  "ann_search_heuristic"):
+                  "ann_search_heuristic", "ann_load_index_ex",
+                  "ann_search_pages"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -141,9 +153,12 @@ def _stream(device, stream):
 class Index:
     """A loaded index on one GPU (see ann_load_index)."""
 
-    def __init__(self, path: str, device: int = 0):
+    def __init__(self, path: str, device: int = 0, raw_tier: int = 0, page_bytes: int = 0):
+        """raw_tier 1: raw vectors on pages of page_bytes in pinned host memory."""
         h = ctypes.c_void_p()
-        _check(lib().ann_load_index(path.encode(), int(device), ctypes.byref(h)))
+        cfg = LoadCfg(int(raw_tier), int(page_bytes))
+        _check(lib().ann_load_index_ex(path.encode(), int(device), ctypes.byref(cfg),
+                                       ctypes.byref(h)))
         self._h = h
         self.device = torch.device("cuda", int(device))
         d = IndexDesc()
@@ -203,6 +218,23 @@ class Index:
                                           int(batch_size), float(eps), int(beta), _ptr(ids),
                                           _ptr(d), _ptr(rr), _stream(self.device, stream)))
         return ids, d, rr
+
+    def search_pages(self, queries, nprobe, k: int, rerank_n: int, batch_size: int = 0,
+                     eps: float = 0.0, beta: int = 1, stream=None):
+        """Steps 1-8 from host-memory pages (raw_tier 1): (ids, dists, re-ranked
+        counts int32 [nq], pages read int32 [nq]).  batch_size 0: fixed re-rank,
+        else Alg. 1 with (batch_size, eps, beta)."""
+        q = self._queries(queries)
+        nq = q.shape[0]
+        npt, npmax = self._nprobe(nprobe, nq)
+        ids = torch.empty((nq, k), dtype=torch.int64, device=self.device)
+        d = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        rr = torch.empty((nq,), dtype=torch.int32, device=self.device)
+        pr = torch.empty((nq,), dtype=torch.int32, device=self.device)
+        _check(lib().ann_search_pages(self._h, _ptr(q), nq, _ptr(npt), npmax, k, rerank_n,
+                                      int(batch_size), float(eps), int(beta), _ptr(ids), _ptr(d),
+                                      _ptr(rr), _ptr(pr), _stream(self.device, stream)))
+        return ids, d, rr, pr
 
     def search_topn(self, queries, nprobe, rerank_n: int, stream=None, walked: bool = False):
         """Steps 1-7: (ids int32 [nq, n], ADC distances float32 [nq, n], candidates int64 [nq]),
@@ -271,6 +303,11 @@ class Index:
     OPT_SCAN_SPLIT = 2
     OPT_LUT_F16 = 3
     OPT_SCAN_ORDER = 4
+    OPT_LIST_MAJOR = 5
+    OPT_LM_ALPHA = 6
+    OPT_LM_TILE = 7
+    OPT_LM_BLOCKS = 8
+    OPT_LM_CAP = 9
 
     def set_option(self, option: int, value: int):
         _check(lib().ann_set_option(self._h, int(option), int(value)))
@@ -324,13 +361,19 @@ class Graph:
 
 
 def autotune(index, Q, nprobe, k: int, rerank_n: int, reps: int = 3) -> dict:
-    """Pick and set the scan work split for this batch (ann_autotune)."""
+    """Pick and set the batched form's options for this batch (ann_autotune): the
+    per-query scan's work split and, on integer-grid indexes, whether to run
+    list-major and with which alpha / rows per item / persistent blocks."""
     Q = Q.contiguous()
     np_t, np_max = _nprobe_args(index, Q, nprobe)
     r = TuneResult()
     _check(lib().ann_autotune(index._h, _ptr(Q), Q.shape[0], _ptr(np_t), np_max, int(k),
                               int(rerank_n), int(reps), ctypes.byref(r)))
-    return {"tile": r.tile, "split": r.split, "tried": r.tried, "ms": r.ms}
+    out = {"tile": r.tile, "split": r.split, "tried": r.tried, "ms": r.ms,
+           "list_major": r.list_major}
+    if r.list_major:
+        out.update(lm_alpha=r.lm_alpha, lm_tile=r.lm_tile, lm_blocks=r.lm_blocks)
+    return out
 
 
 # -- served form (ann_server_*) ---------------------------------------------------------

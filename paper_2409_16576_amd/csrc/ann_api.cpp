@@ -59,8 +59,9 @@ namespace {
 // after the stream work of its previous user has completed (event order).
 struct Workspace {
   Work w;
+  void* lm_buf = nullptr;  // the list-major pass's buffers (carved per call)
   size_t cap_qc = 0, cap_np = 0, cap_nlist = 0, cap_keys = 0, cap_items = 0, cap_lut = 0,
-         cap_cand = 0;
+         cap_cand = 0, cap_lm = 0;
   std::vector<void*> allocs;
   hipEvent_t done = nullptr;
   bool recorded = false;
@@ -69,7 +70,8 @@ struct Workspace {
     for (void* p : allocs) (void)hipFree(p);
     allocs.clear();
     w = Work{};
-    cap_qc = cap_np = cap_nlist = cap_keys = cap_items = cap_lut = cap_cand = 0;
+    lm_buf = nullptr;
+    cap_qc = cap_np = cap_nlist = cap_keys = cap_items = cap_lut = cap_cand = cap_lm = 0;
   }
   ~Workspace() {
     if (recorded) (void)hipEventSynchronize(done);
@@ -79,7 +81,7 @@ struct Workspace {
 };
 
 struct Need {
-  size_t qc, np, nlist, keys, items, lut, cand;
+  size_t qc, np, nlist, keys, items, lut, cand, lm = 0;
 };
 
 }  // namespace
@@ -102,6 +104,13 @@ struct ann_index {
   int64_t opt_split = 16;
   int64_t opt_lut16 = 0;
   int64_t opt_order = 0;
+  int64_t opt_lmajor = 0;  // list-major pass for large batches (integer-grid indexes)
+  int64_t opt_lm_alpha = 2;
+  int64_t opt_lm_tile = 4096;
+  int64_t opt_lm_blocks = 0;
+  int64_t opt_lm_cap = 0;
+  int num_cu = 256;
+  void* host_pages = nullptr;  // host-memory raw tier (pinned), freed with the index
   // stage timing
   bool profiling = false;
   std::mutex prof_mu;
@@ -117,6 +126,7 @@ struct ann_index {
     }
     for (auto e : spare_events) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
+    if (host_pages) (void)hipHostFree(host_pages);
   }
 };
 
@@ -147,12 +157,13 @@ ann_status ws_alloc(Workspace* ws, size_t bytes, void** out) {
 ann_status ws_ensure(Workspace* ws, const Need& n) {
   if (ws->cap_qc >= n.qc && ws->cap_np >= n.np && ws->cap_nlist >= n.nlist &&
       ws->cap_keys >= n.keys && ws->cap_items >= n.items && ws->cap_lut >= n.lut &&
-      ws->cap_cand >= n.cand)
+      ws->cap_cand >= n.cand && ws->cap_lm >= n.lm)
     return ANN_OK;
   if (ws->recorded) HIP_TRY(hipEventSynchronize(ws->done));
   Need g{std::max(n.qc, ws->cap_qc), std::max(n.np, ws->cap_np), std::max(n.nlist, ws->cap_nlist),
          std::max(n.keys, ws->cap_keys), std::max(n.items, ws->cap_items),
-         std::max(n.lut, ws->cap_lut), std::max(n.cand, ws->cap_cand)};
+         std::max(n.lut, ws->cap_lut), std::max(n.cand, ws->cap_cand),
+         std::max(n.lm, ws->cap_lm)};
   ws->release_memory();
   Work& w = ws->w;
   ann_status s;
@@ -171,9 +182,10 @@ ann_status ws_ensure(Workspace* ws, const Need& n) {
   WS(w.pcount, g.items * 4);
   WS(w.pscan, g.items * 8);
   WS(w.cand, g.cand * 4);
+  if (g.lm) WS(ws->lm_buf, g.lm);
 #undef WS
   ws->cap_qc = g.qc; ws->cap_np = g.np; ws->cap_nlist = g.nlist; ws->cap_keys = g.keys;
-  ws->cap_items = g.items; ws->cap_lut = g.lut; ws->cap_cand = g.cand;
+  ws->cap_items = g.items; ws->cap_lut = g.lut; ws->cap_cand = g.cand; ws->cap_lm = g.lm;
   return ANN_OK;
 }
 
@@ -303,6 +315,54 @@ int chunk_queries(const DevIndex& d, int64_t nq) {
   return (int)std::max<size_t>(qc, 1);
 }
 
+// The list-major pass's buffers for a chunk of qc queries, carved from one
+// 256-aligned block (sizes grow with every argument, so a block sized for
+// larger arguments also holds smaller ones).
+template <class F>
+void lm_layout(const DevIndex& d, int qc, int np_max, int cap2, F&& take) {
+  take(0, (size_t)qc * 4);                          // walkp
+  take(1, (size_t)qc * 8);                          // thr
+  take(2, (size_t)qc * 4);                          // cnt2
+  take(3, (size_t)qc * cap2 * 8);                   // out2
+  take(4, (size_t)qc);                              // flag
+  take(5, (size_t)d.nlist * 4);                     // lcnt
+  take(6, (size_t)d.nlist * 4);                     // lfill
+  take(7, (size_t)(d.nlist + 1) * 4);               // loff
+  take(8, (size_t)(d.nlist + 1) * 4);               // ioff
+  take(9, (size_t)qc * np_max * 4);                 // invq
+  take(10, (size_t)16);                             // ctr
+}
+
+size_t lm_bytes(const DevIndex& d, int qc, int np_max, int cap2) {
+  size_t t = 0;
+  lm_layout(d, qc, np_max, cap2,
+            [&](int, size_t b) { t += align_up_sz(std::max<size_t>(b, 16), 256); });
+  return t;
+}
+
+LmWork lm_carve(const DevIndex& d, int qc, int np_max, int cap2, void* base) {
+  LmWork w;
+  char* p = static_cast<char*>(base);
+  void* ptr[11];
+  lm_layout(d, qc, np_max, cap2, [&](int i, size_t b) {
+    ptr[i] = p;
+    p += align_up_sz(std::max<size_t>(b, 16), 256);
+  });
+  w.walkp = static_cast<int32_t*>(ptr[0]);
+  w.thr = static_cast<unsigned long long*>(ptr[1]);
+  w.cnt2 = static_cast<int32_t*>(ptr[2]);
+  w.out2 = static_cast<uint64_t*>(ptr[3]);
+  w.flag = static_cast<uint8_t*>(ptr[4]);
+  w.lcnt = static_cast<int32_t*>(ptr[5]);
+  w.lfill = static_cast<int32_t*>(ptr[6]);
+  w.loff = static_cast<int32_t*>(ptr[7]);
+  w.ioff = static_cast<int32_t*>(ptr[8]);
+  w.invq = static_cast<int32_t*>(ptr[9]);
+  w.ctr = static_cast<int32_t*>(ptr[10]);
+  w.cap2 = cap2;
+  return w;
+}
+
 Need need_for(const DevIndex& d, int qc, int np_max, int n, int smax) {
   Need r;
   r.qc = (size_t)qc;
@@ -347,9 +407,84 @@ ann_status check_lds(ann_index* ix, int np_max, int n) {
 
 extern "C" const char* ann_last_error(void) { return g_err.c_str(); }
 
+// Raw vectors on pages (Sec. 4.3, optimized storage layout).  Vectors are
+// bucketed by nearest list; a bucket's whole pages are laid out first (bucket
+// order, ascending ID); the remainders are packed onto shared pages: each new
+// page starts with the largest remainder left and keeps adding the largest
+// one that still fits its free slots (equal sizes: lower bucket first).
+extern "C" int64_t ann_page_layout(const int32_t* bucket_of, int64_t n, int32_t nbuckets,
+                                   int32_t row_bytes, int32_t page_bytes, int32_t* page,
+                                   int32_t* slot) {
+  if (!bucket_of || !page || !slot || n < 0 || nbuckets < 1 || row_bytes < 1 ||
+      page_bytes < row_bytes) {
+    fail(ANN_EINVAL, "page layout: bad arguments");
+    return -1;
+  }
+  const int per = page_bytes / row_bytes;
+  std::vector<std::vector<int32_t>> members(nbuckets);
+  for (int64_t v = 0; v < n; ++v) {
+    if (bucket_of[v] < 0 || bucket_of[v] >= nbuckets) {
+      fail(ANN_EINVAL, "page layout: bucket out of range");
+      return -1;
+    }
+    members[bucket_of[v]].push_back((int32_t)v);
+  }
+  int64_t next_page = 0;
+  for (int b = 0; b < nbuckets; ++b) {
+    const size_t whole = members[b].size() / per * per;
+    for (size_t i = 0; i < whole; ++i) {
+      page[members[b][i]] = (int32_t)(next_page + (int64_t)(i / per));
+      slot[members[b][i]] = (int32_t)(i % per);
+    }
+    next_page += (int64_t)(whole / per);
+  }
+  // remainders by size: for each size, the buckets that have it, ascending
+  std::vector<std::vector<int>> by_size(per);
+  std::vector<size_t> taken(per, 0);
+  int64_t left = 0;
+  for (int b = 0; b < nbuckets; ++b) {
+    const int r = (int)(members[b].size() % per);
+    if (r) {
+      by_size[r].push_back(b);
+      ++left;
+    }
+  }
+  auto largest_fitting = [&](int room) {
+    for (int r = std::min(room, per - 1); r > 0; --r)
+      if (taken[r] < by_size[r].size()) return r;
+    return 0;
+  };
+  while (left > 0) {
+    int room = per, filled = 0;
+    for (int r; (r = largest_fitting(room)) > 0;) {
+      const int b = by_size[r][taken[r]++];
+      const size_t base = members[b].size() - r;
+      for (int i = 0; i < r; ++i) {
+        page[members[b][base + i]] = (int32_t)next_page;
+        slot[members[b][base + i]] = filled + i;
+      }
+      filled += r;
+      room -= r;
+      --left;
+    }
+    ++next_page;
+  }
+  return next_page;
+}
+
 extern "C" ann_status ann_load_index(const char* path, int device, ann_index** out) {
+  return ann_load_index_ex(path, device, nullptr, out);
+}
+
+extern "C" ann_status ann_load_index_ex(const char* path, int device, const ann_load_cfg* cfg,
+                                        ann_index** out) {
   if (!path || !out) return fail(ANN_EINVAL, "NULL argument");
   *out = nullptr;
+  const int raw_tier = cfg ? cfg->raw_tier : 0;
+  const int page_bytes = cfg && cfg->page_bytes ? cfg->page_bytes : 4096;
+  if (raw_tier != 0 && raw_tier != 1) return fail(ANN_EINVAL, "raw_tier must be 0 or 1");
+  if (raw_tier && (page_bytes < 16 || page_bytes % 16 != 0 || page_bytes > 65536))
+    return fail(ANN_EINVAL, "page_bytes must be a multiple of 16 in [16, 65536]");
   FILE* f = std::fopen(path, "rb");
   if (!f) return fail(ANN_EIO, "cannot open %s", path);
   std::fseek(f, 0, SEEK_END);
@@ -527,6 +662,7 @@ extern "C" ann_status ann_load_index(const char* path, int device, ann_index** o
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return fail(ANN_EDEVICE, "device %d not available", device);
   HIP_TRY(hipSetDevice(device));
+  HIP_TRY(hipDeviceGetAttribute(&ix->num_cu, hipDeviceAttributeMultiprocessorCount, device));
   DevIndex& d = ix->d;
   d.dtype = dtype; d.dim = dim; d.nlist = nlist; d.M = M; d.row_bytes = row_bytes; d.dsub = dsub;
   d.R = R; d.int_grid = int_grid ? 1 : 0; d.n = (int64_t)n;
@@ -535,8 +671,36 @@ extern "C" ann_status ann_load_index(const char* path, int device, ann_index** o
   const uint8_t* pv = nullptr;
   const int2* prep = nullptr;
   if ((s = dev_upload(ix.get(), codes_rows.data(), codes_rows.size(), &pc)) != ANN_OK) return s;
-  // raw vectors stay in external-ID order: the re-rank reads them by ID
-  if ((s = dev_upload(ix.get(), vecs, (size_t)n * dim * es, &pv)) != ANN_OK) return s;
+  if (!raw_tier) {
+    // raw vectors stay in external-ID order: the re-rank reads them by ID
+    if ((s = dev_upload(ix.get(), vecs, (size_t)n * dim * es, &pv)) != ANN_OK) return s;
+  } else {
+    // host-memory raw tier: pages of pinned host memory, bucketed by nearest list
+    const int rowb = dim * es;
+    if (rowb > page_bytes) return fail(ANN_EINVAL, "a raw vector (%d bytes) exceeds a page", rowb);
+    std::vector<int32_t> vpage(n), vslot(n);
+    const int64_t npages = ann_page_layout(primary.data(), (int64_t)n, nlist, rowb, page_bytes,
+                                           vpage.data(), vslot.data());
+    if (npages < 0) return ANN_EINVAL;
+    const size_t hbytes = std::max<size_t>((size_t)npages * page_bytes, 16);
+    if (hipHostMalloc(&ix->host_pages, hbytes, hipHostMallocMapped) != hipSuccess) {
+      ix->host_pages = nullptr;
+      return fail(ANN_ENOMEM, "hipHostMalloc of %zu bytes (raw pages) failed", hbytes);
+    }
+    uint8_t* hp = static_cast<uint8_t*>(ix->host_pages);
+    std::memset(hp, 0, hbytes);
+    for (uint64_t v = 0; v < n; ++v)
+      std::memcpy(hp + (size_t)vpage[v] * page_bytes + (size_t)vslot[v] * rowb,
+                  vecs + v * (size_t)rowb, rowb);
+    void* dp = nullptr;
+    HIP_TRY(hipHostGetDevicePointer(&dp, ix->host_pages, 0));
+    d.hpages = static_cast<const uint8_t*>(dp);
+    d.page_bytes = page_bytes;
+    if ((s = dev_upload(ix.get(), vpage.data(), vpage.size(), &d.vpage)) != ANN_OK) return s;
+    if ((s = dev_upload(ix.get(), vslot.data(), vslot.size(), &d.vslot)) != ANN_OK) return s;
+    ix->desc.host_bytes = (int64_t)hbytes;
+    ix->desc.pages = npages;
+  }
   d.codes = pc;
   d.vecs = pv;
   if ((s = dev_upload(ix.get(), row2ext.data(), row2ext.size(), &d.row2ext)) != ANN_OK) return s;
@@ -571,13 +735,20 @@ extern "C" ann_status ann_load_index(const char* path, int device, ann_index** o
     }
     if ((s = dev_upload(ix.get(), c8.data(), c8.size(), &d.cent8)) != ANN_OK) return s;
     if ((s = dev_upload(ix.get(), cn.data(), cn.size(), &d.cnorm8)) != ANN_OK) return s;
+    // the codebooks shifted the same way (decoding for the list-major scan),
+    // padded to a multiple of 16 bytes
+    std::vector<int8_t> b8(((size_t)M * ksub * dsub + 15) / 16 * 16, 0);
+    for (size_t i = 0; i < (size_t)M * ksub * dsub; ++i) b8[i] = (int8_t)((int)cb[i] - d.shift8);
+    if ((s = dev_upload(ix.get(), b8.data(), b8.size(), &d.cb8)) != ANN_OK) return s;
   }
 
   ann_index_desc& ds = ix->desc;
   ds.n = (int64_t)n; ds.dim = dim; ds.dtype = dtype; ds.nlist = nlist; ds.m = M; ds.ksub = ksub;
   ds.dsub = dsub; ds.r = R; ds.int_grid = d.int_grid; ds.entries = (int64_t)E;
   ds.replica_entries = (int64_t)rep.size(); ds.max_list = max_list; ds.device = device;
-  ds.max_rerank_n = kMaxRerank;
+  ds.max_rerank_n = raw_tier ? kHostMaxRerank : kMaxRerank;
+  ds.raw_tier = raw_tier;
+  ds.page_bytes = raw_tier ? page_bytes : 0;
   *out = ix.release();
   return ANN_OK;
 }
@@ -597,7 +768,8 @@ struct Heur {
   int batch = 0;
   double eps = 0.0;
   int beta = 1;
-  int32_t* reranked = nullptr;  // [nq] candidates re-ranked, or NULL
+  int32_t* reranked = nullptr;    // [nq] candidates re-ranked, or NULL
+  int32_t* page_reads = nullptr;  // [nq] raw pages read (host-memory raw tier), or NULL
 };
 
 // Steps 1-8 (or 1-7 with topn_ids) for qc <= chunk_queries(...) queries, on
@@ -617,14 +789,26 @@ ann_status run_chunk(ann_index* ix, Work& w, const float* q, int qc, const int32
     StageMark m(ix, 0, st);
     HIP_TRY(launch_probe(d, q, nprobe, np_max, qc, w, nullptr, w.lists, st));
   }
-  {
+  if (w.lm.walkp && lmajor_cap(ix, n) > 0) {
+    // batched form: per-query part, list-major pass, per-query selection;
+    // stages: per-query scans 2, the persistent launch 4, the rest 5
+    LmCfg lc;
+    lc.alpha = (int)ix->opt_lm_alpha;
+    lc.tile_rows = (int)ix->opt_lm_tile;
+    lc.blocks = (int)ix->opt_lm_blocks;
+    static const int stage_of[kLmPhases] = {5, 2, 5, 4, 5, 2};
+    for (int ph = 0; ph < kLmPhases; ++ph) {
+      StageMark m(ix, stage_of[ph], st);
+      HIP_TRY(launch_lmajor(d, q, c, w, w.lm, lc, ix->num_cu, ph, st));
+    }
+  } else {
     StageMark m(ix, 2, st);  // steps 1, 3, 5, 6, 7: the table is built inside the scan
     HIP_TRY(launch_scan(d, w.lists, w.np_eff, q, c, w, st));
   }
   {
     StageMark m(ix, 3, st);
     HIP_TRY(launch_merge(d, q, c, w, topn_ids, topn_adc, ncand, nwalk, out_ids, out_d, h.reranked,
-                         st));
+                         h.page_reads, st));
   }
   return ANN_OK;
 }
@@ -637,18 +821,26 @@ ann_status run_pipeline(ann_index* ix, const float* Q, int64_t nq, const int32_t
   ann_status s;
   if ((s = check_lds(ix, np_max, n)) != ANN_OK) return s;
   const DevIndex& d = ix->d;
+  if (d.hpages && out_ids && n > kHostMaxRerank)
+    return fail(ANN_EINVAL, "rerank_n must be <= %d with the host-memory raw tier", kHostMaxRerank);
   const int qc_max = chunk_queries(d, nq);
   const LaunchCfg c0 = cfg_for(qc_max, np_max, n, k, ix->opt_tile, ix->opt_split);
   Workspace* ws = nullptr;
-  if ((s = ws_acquire(ix, need_for(d, qc_max, np_max, n, c0.smax), st, &ws)) != ANN_OK) return s;
+  Need need = need_for(d, qc_max, np_max, n, c0.smax);
+  const int cap2 = lmajor_cap(ix, n);
+  if (cap2) need.lm = lm_bytes(d, qc_max, np_max, cap2);
+  if ((s = ws_acquire(ix, need, st, &ws)) != ANN_OK) return s;
   WsGuard guard{ix, ws, st};
+  Work w = ws->w;
+  if (cap2) w.lm = lm_carve(d, qc_max, np_max, cap2, ws->lm_buf);
   for (int64_t q0 = 0; q0 < nq; q0 += qc_max) {
     const int qc = (int)std::min<int64_t>(qc_max, nq - q0);
-    s = run_chunk(ix, ws->w, Q + q0 * d.dim, qc, nprobe ? nprobe + q0 : nullptr, np_max, k, n,
+    s = run_chunk(ix, w, Q + q0 * d.dim, qc, nprobe ? nprobe + q0 : nullptr, np_max, k, n,
                   out_ids ? out_ids + q0 * k : nullptr, out_d ? out_d + q0 * k : nullptr,
                   topn_ids ? topn_ids + q0 * n : nullptr, topn_adc ? topn_adc + q0 * n : nullptr,
                   ncand ? ncand + q0 : nullptr, st,
-                  Heur{h.batch, h.eps, h.beta, h.reranked ? h.reranked + q0 : nullptr},
+                  Heur{h.batch, h.eps, h.beta, h.reranked ? h.reranked + q0 : nullptr,
+                       h.page_reads ? h.page_reads + q0 : nullptr},
                   nwalk ? nwalk + q0 : nullptr);
     if (s != ANN_OK) return s;
   }
@@ -663,15 +855,16 @@ ann_status run_pipeline(ann_index* ix, const float* Q, int64_t nq, const int32_t
 const DevIndex& ann::index_dev(const ann_index* ix) { return ix->d; }
 int ann::index_device(const ann_index* ix) { return ix->device; }
 
-size_t ann::work_bytes(const DevIndex& d, int qc, int np_max, int n) {
+size_t ann::work_bytes(const DevIndex& d, int qc, int np_max, int n, int lm_cap2) {
   const int smax = cfg_for(qc, np_max, n, 1, 65536, 16).smax;
   const Need g = need_for(d, qc, np_max, n, smax);
   auto a = [](size_t b) { return align_up_sz(std::max<size_t>(b, 16), 256); };
   return a(g.qc * g.nlist * 4) + a(g.qc * g.np * 4) + a(g.qc * 4) + a(g.qc * 8) + a(g.qc * 4) +
-         a(g.keys * 8) + a(g.items * 4) + a(g.items * 8);
+         a(g.keys * 8) + a(g.items * 4) + a(g.items * 8) +
+         (lm_cap2 > 0 ? lm_bytes(d, qc, np_max, lm_cap2) : 0);
 }
 
-Work ann::work_carve(const DevIndex& d, int qc, int np_max, int n, void* base) {
+Work ann::work_carve(const DevIndex& d, int qc, int np_max, int n, void* base, int lm_cap2) {
   const int smax = cfg_for(qc, np_max, n, 1, 65536, 16).smax;
   const Need g = need_for(d, qc, np_max, n, smax);
   char* p = static_cast<char*>(base);
@@ -689,13 +882,21 @@ Work ann::work_carve(const DevIndex& d, int qc, int np_max, int n, void* base) {
   w.pkeys = static_cast<uint64_t*>(take(g.keys * 8));
   w.pcount = static_cast<int32_t*>(take(g.items * 4));
   w.pscan = static_cast<int32_t*>(take(g.items * 8));
+  if (lm_cap2 > 0) w.lm = lm_carve(d, qc, np_max, lm_cap2, p);
   return w;
+}
+
+int ann::lmajor_cap(const ann_index* ix, int n) {
+  if (!ix->opt_lmajor || !lmajor_supported(ix->d)) return 0;
+  return ix->opt_lm_cap > 0 ? (int)ix->opt_lm_cap : lmajor_cap2(n);
 }
 
 int ann::search_on(ann_index* ix, Work& w, const float* d_q, int qc, const int32_t* d_nprobe,
                    int np_max, int k, int n, int64_t* d_ids, float* d_dists, hipStream_t st) {
   ann_status s = check_lds(ix, np_max, n);
   if (s != ANN_OK) return s;
+  if (ix->d.hpages && n > kHostMaxRerank)
+    return fail(ANN_EINVAL, "rerank_n must be <= %d with the host-memory raw tier", kHostMaxRerank);
   return run_chunk(ix, w, d_q, qc, d_nprobe, np_max, k, n, d_ids, d_dists, nullptr, nullptr,
                    nullptr, st);
 }
@@ -714,6 +915,11 @@ int ann::get_opt(const ann_index* ix, int option, int64_t* v) {
     case ANN_OPT_SCAN_SPLIT: *v = ix->opt_split; return ANN_OK;
     case ANN_OPT_LUT_F16: *v = ix->opt_lut16; return ANN_OK;
     case ANN_OPT_SCAN_ORDER: *v = ix->opt_order; return ANN_OK;
+    case ANN_OPT_LIST_MAJOR: *v = ix->opt_lmajor; return ANN_OK;
+    case ANN_OPT_LM_ALPHA: *v = ix->opt_lm_alpha; return ANN_OK;
+    case ANN_OPT_LM_TILE: *v = ix->opt_lm_tile; return ANN_OK;
+    case ANN_OPT_LM_BLOCKS: *v = ix->opt_lm_blocks; return ANN_OK;
+    case ANN_OPT_LM_CAP: *v = ix->opt_lm_cap; return ANN_OK;
     default: return ANN_EINVAL;
   }
 }
@@ -757,6 +963,36 @@ extern "C" ann_status ann_search_heuristic(ann_index* ix, const float* d_queries
   h.eps = eps;
   h.beta = beta;
   h.reranked = d_out_reranked;
+  return run_pipeline(ix, d_queries, nq, d_nprobe, nprobe_max, k, rerank_n, d_out_ids,
+                      d_out_dists, nullptr, nullptr, nullptr, (hipStream_t)stream, h);
+}
+
+extern "C" ann_status ann_search_pages(ann_index* ix, const float* d_queries, int64_t nq,
+                                       const int32_t* d_nprobe, int32_t nprobe_max, int32_t k,
+                                       int32_t rerank_n, int32_t batch_size, double eps,
+                                       int32_t beta, int64_t* d_out_ids, float* d_out_dists,
+                                       int32_t* d_out_reranked, int32_t* d_out_page_reads,
+                                       void* stream) {
+  ann_status s = validate_args(ix, d_queries, nq, nprobe_max);
+  if (s != ANN_OK) return s;
+  if (!ix->d.hpages)
+    return fail(ANN_EUNSUPPORTED, "the index keeps its raw vectors in HBM (no pages to count)");
+  if (k < 1) return fail(ANN_EINVAL, "k must be >= 1");
+  if (batch_size > 0 && k > 64)
+    return fail(ANN_EINVAL, "k must be in [1, 64] for the heuristic re-rank");
+  if (rerank_n < k || rerank_n > kHostMaxRerank)
+    return fail(ANN_EINVAL, "rerank_n must be in [k, %d]", kHostMaxRerank);
+  if (batch_size < 0) return fail(ANN_EINVAL, "batch_size must be >= 0");
+  if (batch_size > 0 && beta < 1) return fail(ANN_EINVAL, "beta must be >= 1");
+  if (batch_size > 0 && !(eps >= 0.0)) return fail(ANN_EINVAL, "eps must be >= 0");
+  if (nq > 0 && (!d_out_ids || !d_out_dists)) return fail(ANN_EINVAL, "output pointer is NULL");
+  if (nq == 0) return ANN_OK;
+  Heur h;
+  h.batch = batch_size;
+  h.eps = eps;
+  h.beta = beta;
+  h.reranked = d_out_reranked;
+  h.page_reads = d_out_page_reads;
   return run_pipeline(ix, d_queries, nq, d_nprobe, nprobe_max, k, rerank_n, d_out_ids,
                       d_out_dists, nullptr, nullptr, nullptr, (hipStream_t)stream, h);
 }
@@ -846,6 +1082,9 @@ extern "C" ann_status ann_rerank(ann_index* ix, const float* d_queries, int64_t 
   if (k < 1 || n < k || n > kMaxRerank) return fail(ANN_EINVAL, "need 1 <= k <= n <= %d", kMaxRerank);
   if (nq > 0 && (!d_queries || !d_cand_ids || !d_out_ids || !d_out_dists))
     return fail(ANN_EINVAL, "NULL pointer");
+  if (ix->d.hpages)
+    return fail(ANN_EUNSUPPORTED, "ann_rerank reads raw vectors from HBM; this index keeps them "
+                                  "in host memory (use ann_search_pages)");
   HIP_TRY(hipSetDevice(ix->device));
   const int64_t step = 1 << 20;
   for (int64_t q0 = 0; q0 < nq; q0 += step) {
@@ -902,6 +1141,28 @@ extern "C" ann_status ann_set_option(ann_index* ix, int option, int64_t value) {
       if (value != 0 && value != 1) return fail(ANN_EINVAL, "scan order must be 0 or 1");
       ix->opt_order = value;
       return ANN_OK;
+    case ANN_OPT_LIST_MAJOR:
+      if (value != 0 && value != 1) return fail(ANN_EINVAL, "list-major must be 0 or 1");
+      ix->opt_lmajor = value;
+      return ANN_OK;
+    case ANN_OPT_LM_ALPHA:
+      if (value < 1 || value > 64) return fail(ANN_EINVAL, "list-major alpha must be in [1, 64]");
+      ix->opt_lm_alpha = value;
+      return ANN_OK;
+    case ANN_OPT_LM_TILE:
+      if (value < 64 || value > (int64_t)1 << 24)
+        return fail(ANN_EINVAL, "list-major tile must be in [64, 2^24] rows");
+      ix->opt_lm_tile = value;
+      return ANN_OK;
+    case ANN_OPT_LM_BLOCKS:
+      if (value < 0 || value > 65536) return fail(ANN_EINVAL, "list-major blocks must be in [0, 65536]");
+      ix->opt_lm_blocks = value;
+      return ANN_OK;
+    case ANN_OPT_LM_CAP:
+      if (value < 0 || value > (1 << 20))
+        return fail(ANN_EINVAL, "list-major capacity must be in [0, 2^20] keys");
+      ix->opt_lm_cap = value;
+      return ANN_OK;
     default:
       return fail(ANN_EINVAL, "unknown option %d", option);
   }
@@ -909,11 +1170,8 @@ extern "C" ann_status ann_set_option(ann_index* ix, int option, int64_t value) {
 
 extern "C" ann_status ann_get_option(ann_index* ix, int option, int64_t* value) {
   if (!ix || !value) return fail(ANN_EINVAL, "NULL argument");
+  if (get_opt(ix, option, value) == ANN_OK) return ANN_OK;
   switch (option) {
-    case ANN_OPT_SCAN_TILE: *value = ix->opt_tile; return ANN_OK;
-    case ANN_OPT_SCAN_SPLIT: *value = ix->opt_split; return ANN_OK;
-    case ANN_OPT_LUT_F16: *value = ix->opt_lut16; return ANN_OK;
-    case ANN_OPT_SCAN_ORDER: *value = ix->opt_order; return ANN_OK;
     default: return fail(ANN_EINVAL, "unknown option %d", option);
   }
 }

@@ -50,9 +50,10 @@ ann_status enqueue_search(ann_index* ix, void* work, const float* q, int64_t nq,
                           float* dists, hipStream_t st) {
   const DevIndex& d = index_dev(ix);
   const int chunk = max_chunk(d);
+  const int lm_cap2 = lmajor_cap(ix, n);
   for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
     const int qc = (int)std::min<int64_t>(chunk, nq - q0);
-    Work w = work_carve(d, qc, np_max, n, work);
+    Work w = work_carve(d, qc, np_max, n, work, lm_cap2);
     const int s = search_on(ix, w, q + q0 * d.dim, qc, nprobe ? nprobe + q0 : nullptr, np_max, k,
                             n, ids + q0 * k, dists + q0 * k, st);
     if (s != ANN_OK) return (ann_status)s;
@@ -90,7 +91,8 @@ extern "C" ann_status ann_graph_create(ann_index* ix, const float* d_queries, in
   const int chunk = (int)std::min<int64_t>(nq, max_chunk(d));
   std::unique_ptr<ann_graph> g(new ann_graph());
   g->ix = ix;
-  if ((e = hipMalloc(&g->work, work_bytes(d, chunk, nprobe_max, rerank_n))) != hipSuccess)
+  if ((e = hipMalloc(&g->work, work_bytes(d, chunk, nprobe_max, rerank_n,
+                                           lmajor_cap(ix, rerank_n)))) != hipSuccess)
     return err(ANN_ENOMEM, "graph working memory", e);
   if ((e = hipEventCreateWithFlags(&g->last, hipEventDisableTiming)) != hipSuccess)
     return err(ANN_EDEVICE, "hipEventCreate", e);
@@ -142,20 +144,13 @@ extern "C" ann_status ann_autotune(ann_index* ix, const float* d_queries, int64_
   if (s != ANN_OK) return s;
   hipError_t e = hipSetDevice(index_device(ix));
   if (e != hipSuccess) return err(ANN_EDEVICE, "hipSetDevice", e);
-  int64_t tile0 = 0, split0 = 0;
-  get_opt(ix, ANN_OPT_SCAN_TILE, &tile0);
-  get_opt(ix, ANN_OPT_SCAN_SPLIT, &split0);
+  // the options this search may change, restored on error
+  const int opts[] = {ANN_OPT_SCAN_TILE, ANN_OPT_SCAN_SPLIT, ANN_OPT_LIST_MAJOR, ANN_OPT_LM_ALPHA,
+                      ANN_OPT_LM_TILE, ANN_OPT_LM_BLOCKS};
+  int64_t saved[6];
+  for (int i = 0; i < 6; ++i) get_opt(ix, opts[i], &saved[i]);
   hipStream_t st = nullptr;
   hipEvent_t a = nullptr, b = nullptr;
-  std::vector<std::pair<int64_t, int>> cand;
-  for (int64_t tile : {4096LL, 8192LL, 16384LL, 32768LL, 65536LL, 131072LL, 1LL << 30})
-    for (int split : {1, 2, 4, 8, 16}) {
-      if (tile == (1LL << 30) && split > 1) continue;  // one item per query whatever the split
-      cand.push_back({tile, split});
-    }
-  ann_tune_result best{};
-  best.ms = -1.0;
-  int tried = 0;
   auto cleanup = [&]() {
     if (st) (void)hipStreamSynchronize(st);
     if (ids) (void)hipFree(ids);
@@ -171,37 +166,86 @@ extern "C" ann_status ann_autotune(ann_index* ix, const float* d_queries, int64_
     cleanup();
     return err(ANN_ENOMEM, "autotune buffers", e);
   }
-  for (auto [tile, split] : cand) {
-    ann_set_option(ix, ANN_OPT_SCAN_TILE, tile);
-    ann_set_option(ix, ANN_OPT_SCAN_SPLIT, split);
+  // median of `reps` timed searches after one warm-up, with the options set
+  auto time_it = [&](double* med) -> ann_status {
     std::vector<float> t;
-    for (int r = 0; r <= reps && s == ANN_OK; ++r) {  // r = 0: warm-up
+    for (int r = 0; r <= reps; ++r) {  // r = 0: warm-up
       (void)hipEventRecord(a, st);
-      s = ann_search(ix, d_queries, nq, d_nprobe, nprobe_max, k, rerank_n, ids, dists, st);
+      ann_status s2 = ann_search(ix, d_queries, nq, d_nprobe, nprobe_max, k, rerank_n, ids, dists, st);
+      if (s2 != ANN_OK) return s2;
       (void)hipEventRecord(b, st);
-      if ((e = hipEventSynchronize(b)) != hipSuccess) s = err(ANN_EDEVICE, "autotune run", e);
+      if ((e = hipEventSynchronize(b)) != hipSuccess) return err(ANN_EDEVICE, "autotune run", e);
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, a, b);
       if (r > 0) t.push_back(ms);
     }
-    if (s != ANN_OK) break;
     std::sort(t.begin(), t.end());
-    const double med = t[t.size() / 2];
-    ++tried;
-    if (best.ms < 0 || med < best.ms) {
-      best.tile = tile;
-      best.split = split;
-      best.ms = med;
+    *med = t[t.size() / 2];
+    return ANN_OK;
+  };
+  ann_tune_result best{};
+  best.ms = -1.0;
+  int tried = 0;
+  // 1. the per-query scan's work split
+  ann_set_option(ix, ANN_OPT_LIST_MAJOR, 0);
+  for (int64_t tile : {4096LL, 8192LL, 16384LL, 32768LL, 65536LL, 131072LL, 1LL << 30}) {
+    for (int split : {1, 2, 4, 8, 16}) {
+      if (tile == (1LL << 30) && split > 1) continue;  // one item per query whatever the split
+      ann_set_option(ix, ANN_OPT_SCAN_TILE, tile);
+      ann_set_option(ix, ANN_OPT_SCAN_SPLIT, split);
+      double med = 0;
+      if ((s = time_it(&med)) != ANN_OK) break;
+      ++tried;
+      if (best.ms < 0 || med < best.ms) {
+        best.tile = tile;
+        best.split = split;
+        best.ms = med;
+      }
+    }
+    if (s != ANN_OK) break;
+  }
+  // 2. list-major (integer-grid indexes): its split of each query, rows per
+  //    work item and number of persistent blocks, with the best split above
+  if (s == ANN_OK && lmajor_supported(index_dev(ix))) {
+    {
+      ann_set_option(ix, ANN_OPT_SCAN_TILE, best.tile);
+      ann_set_option(ix, ANN_OPT_SCAN_SPLIT, best.split);
+      ann_set_option(ix, ANN_OPT_LIST_MAJOR, 1);
+      int cu = 256;
+      (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, index_device(ix));
+      const int64_t ncu = std::max(1, cu);
+      for (int alpha : {1, 2, 4, 8})
+        for (int rows : {1024, 4096, 16384})
+          for (int64_t blocks : {2 * ncu, 4 * ncu, 8 * ncu}) {
+            ann_set_option(ix, ANN_OPT_LM_ALPHA, alpha);
+            ann_set_option(ix, ANN_OPT_LM_TILE, rows);
+            ann_set_option(ix, ANN_OPT_LM_BLOCKS, blocks);
+            double med = 0;
+            if ((s = time_it(&med)) != ANN_OK) break;
+            ++tried;
+            if (med < best.ms) {
+              best.list_major = 1;
+              best.lm_alpha = alpha;
+              best.lm_tile = rows;
+              best.lm_blocks = (int32_t)blocks;
+              best.ms = med;
+            }
+          }
     }
   }
   cleanup();
   if (s != ANN_OK) {
-    ann_set_option(ix, ANN_OPT_SCAN_TILE, tile0);
-    ann_set_option(ix, ANN_OPT_SCAN_SPLIT, split0);
+    for (int i = 0; i < 6; ++i) ann_set_option(ix, opts[i], saved[i]);
     return s;
   }
   ann_set_option(ix, ANN_OPT_SCAN_TILE, best.tile);
   ann_set_option(ix, ANN_OPT_SCAN_SPLIT, best.split);
+  ann_set_option(ix, ANN_OPT_LIST_MAJOR, best.list_major);
+  if (best.list_major) {
+    ann_set_option(ix, ANN_OPT_LM_ALPHA, best.lm_alpha);
+    ann_set_option(ix, ANN_OPT_LM_TILE, best.lm_tile);
+    ann_set_option(ix, ANN_OPT_LM_BLOCKS, best.lm_blocks);
+  }
   best.tried = tried;
   *out = best;
   return ANN_OK;

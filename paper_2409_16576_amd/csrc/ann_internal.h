@@ -45,11 +45,42 @@ struct DevIndex {
   const int32_t* cnorm8;      // [nlist] sum of squares of the shifted centroid
   int dim_pad;                // dim rounded up to 64
   int shift8;                 // 128 for uint8, 0 for int8
+  const int8_t* cb8;          // [M, 256, dsub] codebooks shifted to int8 (16-byte padded)
   // replica entries of each list grouped by their vector's first list: group s
   // of list l (s in [lseg[l], lseg[l+1])) is {first list, rep begin, rep end, 0}
   const int4* segs;
   const int32_t* lseg;        // [nlist + 1]
   int max_segs;               // most groups of one list
+  // host-memory raw tier (vecs is then null): the raw vectors on pages in
+  // pinned host memory (device-accessible address), laid out by ann_page_layout
+  const uint8_t* hpages;      // [pages, page_bytes]
+  const int32_t* vpage;       // [n] page of each vector (by external ID)
+  const int32_t* vslot;       // [n] its position on the page
+  int page_bytes;
+};
+
+// Working buffers of the list-major pass of the batched form (integer-grid
+// indexes; all null when the pass is not used).
+struct LmWork {
+  int32_t* walkp = nullptr;           // [qc] first probed slot left to the list-major pass
+  unsigned long long* thr = nullptr;  // [qc] bound of each query's n-th smallest key
+  int32_t* cnt2 = nullptr;            // [qc] keys the list-major pass appended
+  uint64_t* out2 = nullptr;           // [qc, cap2] those keys
+  uint8_t* flag = nullptr;            // [qc] overflowed: searched by the per-query scan
+  int32_t* lcnt = nullptr;            // [nlist] queries per list
+  int32_t* lfill = nullptr;           // [nlist]
+  int32_t* loff = nullptr;            // [nlist + 1]
+  int32_t* ioff = nullptr;            // [nlist + 1] work items per list (prefix)
+  int32_t* invq = nullptr;            // [qc * np_max] queries by list
+  int32_t* ctr = nullptr;             // [4] work items, next item
+  int cap2 = 0;
+};
+
+// Tuning of the list-major pass (never changes results).
+struct LmCfg {
+  int alpha = 2;          // the per-query part walks leading lists up to alpha * n rows
+  int tile_rows = 4096;   // first-list rows per work item
+  int blocks = 0;         // persistent blocks (0: 4 per compute unit)
 };
 
 // Per-call working buffers (one block of the memory pool).
@@ -64,6 +95,7 @@ struct Work {
   int32_t* pcount = nullptr;    // [qc, smax]
   int32_t* pscan = nullptr;     // [qc, smax, 2] candidates scored, entries walked per item
   int32_t* cand = nullptr;      // [qc, n] (rerank-only entry point)
+  LmWork lm;                    // list-major pass (batched form)
 };
 
 struct LaunchCfg {
@@ -92,9 +124,22 @@ hipError_t launch_scan(const DevIndex& ix, const int32_t* lists, const int32_t* 
 hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const float* lut, int qc,
                              int np_max, int64_t capacity, int32_t* out_ids, float* out_adc,
                              int64_t* out_count, Work& w, hipStream_t st);
+// page_reads (host-memory raw tier only, may be null): pages read per query
 hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,
                         int32_t* topn_ids, float* topn_adc, int64_t* ncand, int64_t* nwalk,
-                        int64_t* out_ids, float* out_dists, int32_t* reranked, hipStream_t st);
+                        int64_t* out_ids, float* out_dists, int32_t* reranked,
+                        int32_t* page_reads, hipStream_t st);
+constexpr int kHostMaxRerank = 2048;  // largest rerank_n with the host-memory raw tier
+// Batched form on integer-grid indexes: after launch_probe, in place of
+// launch_scan (same outputs for launch_merge, one item per query).
+bool lmajor_supported(const DevIndex& ix);
+int lmajor_cap2(int n);
+// Phases, in order: 0 split and counters, 1 per-query part, 2 work list,
+// 3 persistent list-major launch, 4 per-query selection, 5 overflow fallback.
+constexpr int kLmPhases = 6;
+hipError_t launch_lmajor(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,
+                         const LmWork& lw, const LmCfg& lc, int num_cu, int phase,
+                         hipStream_t st);
 hipError_t launch_rerank_only(const DevIndex& ix, const float* q, const int32_t* cand, int qc,
                               int n, int k, int64_t* out_ids, float* out_dists, hipStream_t st);
 
@@ -102,8 +147,13 @@ hipError_t launch_rerank_only(const DevIndex& ix, const float* q, const int32_t*
 // chunk of queries on caller-carved working buffers (no allocation).
 const DevIndex& index_dev(const ann_index* ix);
 int index_device(const ann_index* ix);
-size_t work_bytes(const DevIndex& d, int qc, int np_max, int n);  // 256-aligned total
-Work work_carve(const DevIndex& d, int qc, int np_max, int n, void* base);
+// lm_cap2 > 0: include the list-major pass's buffers with that many keys per
+// query (the pass runs only when they are there)
+size_t work_bytes(const DevIndex& d, int qc, int np_max, int n, int lm_cap2 = 0);  // 256-aligned
+Work work_carve(const DevIndex& d, int qc, int np_max, int n, void* base, int lm_cap2 = 0);
+// list-major keys per query for this index's options, 0 when the pass is off
+// (option unset or the index not supported)
+int lmajor_cap(const ann_index* ix, int n);
 int search_on(ann_index* ix, Work& w, const float* d_q, int qc, const int32_t* d_nprobe,
               int np_max, int k, int n, int64_t* d_ids, float* d_dists, hipStream_t st);
 int max_chunk(const DevIndex& d);  // most queries one search_on call may take

@@ -803,12 +803,24 @@ __device__ __forceinline__ int scan_compact(uint64_t* s_buf, int* s_wsum, SelScr
 // back to the n best whenever it holds more than n.
 constexpr uint32_t kRunReplica = 0x80000000u;  // run start flag: replica-entry run
 
+// Splitting a query's entries between the per-query scan and the list-major
+// pass of the batched form (all null: the whole query here).
+//   walkp    [qc] first-list rows are walked only for probed slots < walkp[q]
+//            (replica entries of every probed list are always walked here)
+//   active   [qc] nonzero: scan this query; zero: the block does nothing
+//   thr_out  [qc] atomically lowered to each item's n-th smallest key
+struct ScanSplit {
+  const int32_t* walkp = nullptr;
+  const uint8_t* active = nullptr;
+  unsigned long long* thr_out = nullptr;
+};
+
 // Runs of up to 64 probed lists laid out by one wave (lane p: list p): run
 // starts in s_rstart, exclusive entry offsets in s_pre[0..nruns], and
 // s_pre[nruns] = the query's entries; *s_nruns = nruns.
 __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_list, int np,
-                          const uint32_t* s_bits, int segmented, int max_runs, uint32_t* s_rstart,
-                          int32_t* s_pre, int* s_nruns) {
+                          int walk_np, const uint32_t* s_bits, int segmented, int max_runs,
+                          uint32_t* s_rstart, int32_t* s_pre, int* s_nruns) {
   const int lane = threadIdx.x & 63;
   int cnt = 0, l = 0, s0 = 0, s1 = 0;
   if (lane < np) {
@@ -833,7 +845,9 @@ __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_l
   if (lane < np) {
     const int off = incl - cnt;
     s_rstart[off] = (uint32_t)ix.pstart[l];
-    s_pre[off] = ix.pstart[l + 1] - ix.pstart[l];  // entry counts first
+    // entry counts first; the first-list rows of slots >= walk_np are left to
+    // the list-major pass (an empty run)
+    s_pre[off] = lane < walk_np ? ix.pstart[l + 1] - ix.pstart[l] : 0;
     int r = off + 1;
     if (seg) {
       for (int s = s0; s < s1; ++s) {
@@ -871,7 +885,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     int32_t* __restrict__ sq, int smax, int tile, int segmented, int max_runs, int n, int cap,
     uint64_t* __restrict__ pkeys, int32_t* __restrict__ pcount, int32_t* __restrict__ pscan,
     const int32_t* __restrict__ perm, int64_t t_capacity, int32_t* __restrict__ t_ids, float* __restrict__ t_adc,
-    unsigned long long* __restrict__ t_count) {
+    unsigned long long* __restrict__ t_count, ScanSplit sp) {
   // Block -> (query, item).  Blocks are dispatched round-robin over the 8
   // XCDs (each with its own L2): block b runs on XCD b % 8.  With a locality
   // order, XCD x takes the contiguous share x of the ordered queries, so the
@@ -890,6 +904,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     q = (slot / smax) * 8 + xcd;
     if (q >= qc) return;
   }
+  if (sp.active && !sp.active[q]) return;  // only the flagged queries (block-uniform)
   const int tid = threadIdx.x;
   const int M = ix.M;
 
@@ -916,6 +931,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   if (use_bits)
     for (int i = tid; i < nwords; i += kScanBlock) s_bits[i] = 0u;
   const int np = np_eff[q];
+  const int walk_np = sp.walkp ? min(np, sp.walkp[q]) : np;  // slots whose first-list rows are walked
   for (int p = tid; p < np; p += kScanBlock) s_list[p] = lists[(size_t)q * np_max + p];
   if (tid == 0) {
     mc->thr = ~0ull;
@@ -992,7 +1008,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   const bool wave_setup = np <= 64;
   if (wave_setup) {
     if (tid < 64) {
-      runs_wave(ix, s_list, np, s_bits, segmented, max_runs, s_rstart, s_pre,
+      runs_wave(ix, s_list, np, walk_np, s_bits, segmented, max_runs, s_rstart, s_pre,
                 &s_wsum[kScanBlock / 64]);
     } else {
       build_table(tid - 64, kScanBlock - 64);
@@ -1034,7 +1050,8 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     const int off = nruns + block_excl_scan(cnt, s_wsum);
     if (p < np) {
       s_rstart[off] = (uint32_t)ix.pstart[l];
-      s_pre[off] = ix.pstart[l + 1] - ix.pstart[l];  // entry count, turned into offsets below
+      // entry count, turned into offsets below (empty past walk_np, as in runs_wave)
+      s_pre[off] = p < walk_np ? ix.pstart[l + 1] - ix.pstart[l] : 0;
       int r = off + 1;
       if (seg) {
         for (int s = ix.lseg[l]; s < ix.lseg[l + 1]; ++s) {
@@ -1222,6 +1239,23 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
       pcount[(size_t)q * smax + j] = cnt;
       pscan[2 * ((size_t)q * smax + j)] = mc->scanned;
       pscan[2 * ((size_t)q * smax + j) + 1] = e1 - e0;  // entries walked
+    }
+    if (sp.thr_out && cnt == n) {  // block-uniform
+      // this item's n-th smallest key (the largest it keeps) bounds the
+      // query's n-th smallest key from above
+      uint64_t mx = 0;
+      for (int i = tid; i < cnt; i += kScanBlock) mx = s_buf[i] > mx ? s_buf[i] : mx;
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) {
+        const uint64_t o = __shfl_xor(mx, d, 64);
+        mx = o > mx ? o : mx;
+      }
+      __syncthreads();
+      if (tid == 0) mc->thr = 0;
+      __syncthreads();
+      if (lane == 0) atomicMax(reinterpret_cast<unsigned long long*>(&mc->thr), (unsigned long long)mx);
+      __syncthreads();
+      if (tid == 0) atomicMin(&sp.thr_out[q], (unsigned long long)mc->thr);
     }
   }
 }
@@ -1453,14 +1487,134 @@ __device__ void exact_keys(const DevIndex& ix, const float* s_q, const uint64_t*
   }
 }
 
+// Host-memory raw tier (Sec. 4.3): the raw vectors lie on pages in pinned
+// host memory, bucketed by nearest list.  A query's candidates are scored a
+// page at a time: a page is read whole (over PCIe, into the reading wave's
+// LDS buffer) the first time one of the candidates being re-ranked lies on
+// it, and every candidate of the query on that page is scored from that one
+// read -- so requests for one page within a mini-batch are merged, and a
+// later mini-batch finds its candidates on already-read pages scored (the
+// page buffer across mini-batches).  Pages read = distinct pages of the
+// candidates re-ranked, counted in the mini-batch that first needs them.
+struct PageScratch {
+  uint64_t* pg;         // [P] (page << 32 | candidate index), ascending
+  int32_t* first;       // [P] candidate i: start of its page's run in pg if i is
+                        //     the run's lowest index, else -1
+  int32_t* list;        // [P] runs to read now
+  uint64_t* ex;         // [P] exact key of each candidate once scored
+  unsigned char* buf;   // [waves, page_bytes] one page per wave
+  int* cnt;
+};
+
+// Layout (base 16-byte aligned): pg, ex, first, list, cnt, then the page
+// buffers at a 16-byte aligned offset.
+__host__ __device__ inline size_t page_scratch_head(int P) {
+  return align_up((size_t)P * (8 + 8 + 4 + 4) + 16, 16);
+}
+
+__host__ __device__ inline size_t page_scratch_bytes(int P, int waves, int page_bytes) {
+  return page_scratch_head(P) + (size_t)waves * page_bytes;
+}
+
+__device__ inline PageScratch page_scratch(unsigned char* base, int P) {
+  PageScratch ps;
+  ps.pg = reinterpret_cast<uint64_t*>(base);
+  ps.ex = ps.pg + P;
+  ps.first = reinterpret_cast<int32_t*>(ps.ex + P);
+  ps.list = ps.first + P;
+  ps.cnt = ps.list + P;
+  ps.buf = base + page_scratch_head(P);
+  return ps;
+}
+
+// Runs of candidates s_top[0..nn) by page.  Ends with a barrier.
+__device__ void pages_prepare(const DevIndex& ix, const uint64_t* s_top, int nn, int P,
+                              const PageScratch& ps) {
+  for (int i = threadIdx.x; i < P; i += blockDim.x)
+    ps.pg[i] = i < nn ? ((uint64_t)(uint32_t)ix.vpage[(uint32_t)s_top[i]] << 32) | (uint32_t)i
+                      : ~0ull;
+  __syncthreads();
+  block_bitonic(ps.pg, P);
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) ps.first[i] = -1;
+  __syncthreads();
+  for (int j = threadIdx.x; j < nn; j += blockDim.x)
+    if (j == 0 || (ps.pg[j] >> 32) != (ps.pg[j - 1] >> 32)) ps.first[(uint32_t)ps.pg[j]] = j;
+  __syncthreads();
+}
+
+// Exact squared distance of a raw row held in LDS (same arithmetic and order
+// as exact_row).
+__device__ __forceinline__ float exact_row_lds(const DevIndex& ix, const float* __restrict__ s_q,
+                                               const unsigned char* row) {
+  const int D = ix.dim;
+  if (ix.dtype == F32) {
+    const float* x = reinterpret_cast<const float*>(row);
+    double acc = 0.0;
+    for (int t = 0; t < D; ++t) {
+      const double u = (double)s_q[t] - (double)x[t];
+      const double sq = u * u;
+      acc = acc + sq;
+    }
+    return (float)acc;
+  }
+  int acc = 0;
+  for (int t = 0; t < D; ++t) {
+    const int xv = ix.dtype == U8 ? (int)row[t] : (int)(int8_t)row[t];
+    const int u = (int)s_q[t] - xv;
+    acc += u * u;
+  }
+  return (float)acc;
+}
+
+// Read the pages first needed by candidates [c0, c1) and score every
+// candidate on them.  Returns the pages read (the same in every thread).
+__device__ int pages_read(const DevIndex& ix, const float* s_q, const uint64_t* s_top, int nn,
+                          int c0, int c1, const PageScratch& ps) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  if (tid == 0) *ps.cnt = 0;
+  __syncthreads();
+  for (int i0 = c0; i0 < c1; i0 += blockDim.x) {  // uniform trip count
+    const int i = i0 + tid;
+    const bool take = i < c1 && ps.first[i] >= 0;
+    const int pos = wave_append(take, ps.cnt);
+    if (take) ps.list[pos] = ps.first[i];
+  }
+  __syncthreads();
+  const int nr = *ps.cnt;
+  const int row_bytes = ix.dim * (ix.dtype == F32 ? 4 : 1);
+  unsigned char* mine = ps.buf + (size_t)wv * ix.page_bytes;
+  for (int r0 = 0; r0 < nr; r0 += nw) {  // uniform trip count: one page per wave and round
+    const int r = r0 + wv;
+    uint64_t page = 0;
+    int j0 = 0;
+    if (r < nr) {
+      j0 = ps.list[r];
+      page = ps.pg[j0] >> 32;
+      const uint4* src = reinterpret_cast<const uint4*>(ix.hpages + page * (uint64_t)ix.page_bytes);
+      for (int t = lane; t < ix.page_bytes / 16; t += 64) reinterpret_cast<uint4*>(mine)[t] = src[t];
+    }
+    __syncthreads();  // the round's pages are in LDS
+    if (r < nr) {
+      for (int j = j0 + lane; j < nn && (ps.pg[j] >> 32) == page; j += 64) {
+        const uint32_t ci = (uint32_t)ps.pg[j];
+        const uint32_t id = (uint32_t)s_top[ci];
+        const float e = exact_row_lds(ix, s_q, mine + (size_t)ix.vslot[id] * row_bytes);
+        ps.ex[ci] = ((uint64_t)ord32(e) << 32) | id;
+      }
+    }
+    __syncthreads();  // before the next round overwrites the buffers
+  }
+  return nr;
+}
+
 // Re-rank s_top[0..nn) (external IDs in the low halves) by exact distance
 // and write the top-k, sorted.  s_key2 holds
 // P >= nn keys; s_top is reused for the result (it needs
 // max(128, pow2_at_least(min(k, nn))) slots).
 __device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_top, int nn,
                              uint64_t* s_key2, int P, int k, int64_t* out_ids, float* out_d,
-                             SelScratch* ss, int* s_cnt) {
-  exact_keys(ix, s_q, s_top, nn, s_key2, P);
+                             SelScratch* ss, int* s_cnt, bool keys_ready = false) {
+  if (!keys_ready) exact_keys(ix, s_q, s_top, nn, s_key2, P);
   __syncthreads();
   const int kk = min(k, nn);
   const int lane = threadIdx.x & 63;
@@ -1548,16 +1702,24 @@ __device__ void rerank_write(const DevIndex& ix, const float* s_q, uint64_t* s_t
 __device__ void rerank_heuristic(const DevIndex& ix, const float* s_q, uint64_t* s_top, int nn,
                                  uint64_t* s_key2, uint64_t* s_best, uint64_t* s_cand,
                                  int* s_misc, SelScratch* ss, int k, int hb, double eps, int beta,
-                                 int64_t* out_ids, float* out_d, int32_t* reranked) {
+                                 int64_t* out_ids, float* out_d, int32_t* reranked,
+                                 const PageScratch* ps = nullptr, int* page_reads = nullptr) {
   constexpr int kU = 256;  // merge set: the previous best and at most kU - cur entrants
   const int tid = threadIdx.x;
-  int cur = 0, stable = 0, done = 0;
+  int cur = 0, stable = 0, done = 0, preads = 0;
   bool stop = false;
-  const int per = hb * max(1, 1024 / hb);  // candidates gathered per chunk
+  // candidates gathered per chunk; from host pages one mini-batch at a time
+  // (a page is read only when a mini-batch that is re-ranked needs it)
+  const int per = ps ? hb : hb * max(1, 1024 / hb);
   for (int c0 = 0; c0 < nn && !stop; c0 += per) {
     const int cn = min(per, nn - c0);
     __syncthreads();  // the previous chunk's exact keys have been read
-    exact_keys(ix, s_q, s_top + c0, cn, s_key2, cn);
+    if (ps) {
+      preads += pages_read(ix, s_q, s_top, nn, c0, c0 + cn, *ps);
+      for (int i = tid; i < cn; i += blockDim.x) s_key2[i] = ps->ex[c0 + i];
+    } else {
+      exact_keys(ix, s_q, s_top + c0, cn, s_key2, cn);
+    }
     __syncthreads();
     // s_top[c0..c0+cn) has been read: it holds the entrants of each mini-batch
     uint64_t* s_in = s_top + c0;
@@ -1631,6 +1793,7 @@ __device__ void rerank_heuristic(const DevIndex& ix, const float* s_q, uint64_t*
     out_d[t] = v ? unord32((uint32_t)(s_best[t] >> 32)) : INFINITY;
   }
   if (tid == 0 && reranked) *reranked = done;
+  if (tid == 0 && page_reads) *page_reads = preads;
 }
 
 struct MergeLayout {
@@ -1654,15 +1817,17 @@ __host__ __device__ inline MergeLayout merge_layout(int smax, int n, int dim) {
 }
 
 // HEUR: step 8 by the heuristic re-ranking (a kernel of its own, so the
-// plain form's registers are not sized for it).
-template <int BS, bool HEUR>
+// plain form's registers are not sized for it).  HOSTP: the raw vectors are
+// read from host-memory pages (page scratch after the merge layout).
+template <int BS, bool HEUR, bool HOSTP = false>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_merge(
     DevIndex ix, const float* __restrict__ Q, int qc, const int32_t* __restrict__ sq, int smax,
     int n, int k, const uint64_t* __restrict__ pkeys, const int32_t* __restrict__ pcount,
     const int32_t* __restrict__ pscan, int32_t* __restrict__ topn_ids, float* __restrict__ topn_adc,
     int64_t* __restrict__ ncand, int64_t* __restrict__ nwalk, int64_t* __restrict__ out_ids,
     float* __restrict__ out_dists,
-    int hb, double h_eps, int h_beta, int32_t* __restrict__ reranked) {
+    int hb, double h_eps, int h_beta, int32_t* __restrict__ reranked,
+    int32_t* __restrict__ page_reads) {
   extern __shared__ __align__(16) unsigned char smem[];
   const MergeLayout L = merge_layout(smax, n, ix.dim);
   uint64_t* s_keys = reinterpret_cast<uint64_t*>(smem + L.keys);
@@ -1739,7 +1904,29 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(8, 8))) void
     }
   }
   if (!out_ids) return;
-  if constexpr (HEUR) {  // heuristic re-ranking: candidates in ascending ADC order
+  if constexpr (HOSTP) {
+    const PageScratch ps = page_scratch(smem + L.total, P);
+    if constexpr (HEUR) {
+      if (!topn_ids) block_bitonic(s_top, P);
+      __syncthreads();  // s_key2 aliases s_keys
+      pages_prepare(ix, s_top, nn, P, ps);
+      int preads = 0;
+      rerank_heuristic(ix, s_q, s_top, nn, s_key2, reinterpret_cast<uint64_t*>(smem + L.best),
+                       s_cand, s_cnt + 18, ss, k, hb, h_eps, h_beta, out_ids + (size_t)q * k,
+                       out_dists + (size_t)q * k, reranked ? reranked + q : nullptr, &ps,
+                       &preads);
+      if (tid == 0 && page_reads) page_reads[q] = preads;
+    } else {  // fixed re-rank: one mini-batch of all nn candidates
+      __syncthreads();  // s_key2 aliases s_keys
+      pages_prepare(ix, s_top, nn, P, ps);
+      const int preads = pages_read(ix, s_q, s_top, nn, 0, nn, ps);
+      for (int i = tid; i < P; i += BS) s_key2[i] = i < nn ? ps.ex[i] : ~0ull;
+      if (tid == 0 && page_reads) page_reads[q] = preads;
+      if (tid == 0 && reranked) reranked[q] = nn;
+      rerank_write(ix, s_q, s_top, nn, s_key2, P, k, out_ids + (size_t)q * k,
+                   out_dists + (size_t)q * k, ss, s_cnt, true);
+    }
+  } else if constexpr (HEUR) {  // heuristic re-ranking: candidates in ascending ADC order
     if (!topn_ids) block_bitonic(s_top, P);  // (already sorted when the top-n was written)
     __syncthreads();  // s_key2 aliases s_keys
     rerank_heuristic(ix, s_q, s_top, nn, s_key2, reinterpret_cast<uint64_t*>(smem + L.best),
@@ -2119,7 +2306,7 @@ hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t
                          int smax, int tile, int n, int cap, uint64_t* pkeys, int32_t* pcount,
                          int32_t* pscan, const int32_t* perm, bool trace, bool lut16,
                          int64_t t_capacity, int32_t* t_ids, float* t_adc, int64_t* t_count,
-                         hipStream_t st) {
+                         ScanSplit sp, hipStream_t st) {
   const int seg = scan_segmented(ix, np_max) ? 1 : 0;
   const int max_runs = scan_runs(ix, np_max);
   const ScanLayout L = scan_layout(ix.M, ix.nlist, ix.R, np_max, max_runs, cap, 0);
@@ -2132,7 +2319,7 @@ hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t
     hipLaunchKernelGGL(kern, grid, dim3(kScanBlock), L.total, st, ix, lists, np_eff, np_max, qc,
                        Q, lut, sq, smax, tile, seg, max_runs, n, cap, pkeys, pcount, pscan,
                        perm, t_capacity, t_ids, t_adc,
-                       reinterpret_cast<unsigned long long*>(t_count));
+                       reinterpret_cast<unsigned long long*>(t_count), sp);
   } else {
     auto kern = lut16 ? k_scan<W, false, true> : k_scan<W, false, false>;
     if (L.total > 65536)
@@ -2140,7 +2327,7 @@ hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t
     hipLaunchKernelGGL(kern, grid, dim3(kScanBlock), L.total, st, ix, lists, np_eff, np_max, qc,
                        Q, lut, sq, smax, tile, seg, max_runs, n, cap, pkeys, pcount, pscan,
                        perm, t_capacity, t_ids, t_adc,
-                       reinterpret_cast<unsigned long long*>(t_count));
+                       reinterpret_cast<unsigned long long*>(t_count), sp);
   }
   return hipGetLastError();
 }
@@ -2148,7 +2335,7 @@ hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t
 using ScanFn = hipError_t (*)(const DevIndex&, const int32_t*, const int32_t*, int, int,
                               const float*, const float*, int32_t*, int, int, int, int, uint64_t*,
                               int32_t*, int32_t*, const int32_t*, bool, bool, int64_t, int32_t*,
-                              float*, int64_t*, hipStream_t);
+                              float*, int64_t*, ScanSplit, hipStream_t);
 
 template <int... Ws>
 constexpr ScanFn scan_table_entry(int w, std::integer_sequence<int, Ws...>) {
@@ -2159,6 +2346,442 @@ constexpr ScanFn scan_table_entry(int w, std::integer_sequence<int, Ws...>) {
 
 ScanFn scan_fn(int W) {
   return scan_table_entry(W, std::make_integer_sequence<int, kMaxM / 4>{});
+}
+
+// ---------------------------------------------------------------------------
+// Batched form, list-major pass (integer-grid indexes).
+//
+// The per-query scan reads a list's code rows once for every query probing
+// it.  In a large batch each list is probed by many queries, so here the
+// chunk's (query, probed list) pairs are inverted into per-list groups of up
+// to 16 queries, and a work item is (list, group, tile of the list's
+// first-list rows).  One persistent launch pulls items from a device counter;
+// an item reads each code row of its tile once, decodes it through the int8
+// codebook in LDS, and scores it for the whole group on the int8 matrix
+// cores:
+//   Eq. 1 sum = ||q - dec(v)||^2 = ||q'||^2 + ||dec'(v)||^2 - 2 q'.dec'(v)
+// (' = shifted to int8 as for the probe).  On an integer-grid index every
+// term is an exact integer below 2^24, so the float32 value is bit-identical
+// to the per-query table sum.
+//
+// The split of a query's entries: the per-query scan takes the first-list
+// rows of its leading probed lists (until alpha * n rows) and the replica
+// entries of all its probed lists (the ownership test needs the whole probe
+// set); the list-major pass takes the first-list rows of the other probed
+// lists, which are kept for every query (a vector's first list owns it).
+// The per-query scan's n-th smallest key bounds the query's n-th smallest key
+// from above, so the list-major pass keeps only keys below it, appended to
+// the query's output area; a final per-query selection takes the n smallest
+// of both parts.  A query whose area overflows is searched again by the plain
+// per-query scan.  Every step is exact, so results equal the plain form's.
+
+constexpr int kLmG = 16;       // queries per group (rows of the MFMA tile)
+constexpr int kLmBlock = 256;  // threads per list-major block (4 waves)
+constexpr int kLmU = 2;        // 16-row tiles per wave with loads in flight together
+
+struct LmArgs {
+  const int32_t* loff;   // [nlist + 1] start of each list's queries in invq
+  const int32_t* ioff;   // [nlist + 1] start of each list's work items
+  const int32_t* lcnt;   // [nlist] queries per list
+  const int32_t* invq;   // queries by list
+  const unsigned long long* thr;  // [qc] key bound per query
+  int32_t* cnt2;         // [qc] keys appended (may exceed cap2: overflow)
+  uint64_t* out2;        // [qc, cap2]
+  int cap2;
+  int32_t* ctr;          // [0] work items, [1] next item
+  int tile_rows;
+};
+
+// Per query: the first probed slot whose first-list rows go to the
+// list-major pass (the leading slots hold >= need rows, or all slots).
+__global__ void k_lm_prep(DevIndex ix, const int32_t* __restrict__ lists,
+                          const int32_t* __restrict__ np_eff, int np_max, int qc, int64_t need,
+                          int32_t* __restrict__ walkp, unsigned long long* __restrict__ thr,
+                          int32_t* __restrict__ cnt2, uint8_t* __restrict__ flag,
+                          int32_t* __restrict__ lcnt, int32_t* __restrict__ lfill,
+                          int32_t* __restrict__ ctr) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ix.nlist) {
+    lcnt[i] = 0;
+    lfill[i] = 0;
+  }
+  if (i < 4) ctr[i] = 0;
+  if (i < qc) {
+    const int np = np_eff[i];
+    int P = np;
+    int64_t acc = 0;
+    for (int p = 0; p < np; ++p) {
+      const int l = lists[(size_t)i * np_max + p];
+      acc += ix.pstart[l + 1] - ix.pstart[l];
+      if (acc >= need) {
+        P = p + 1;
+        break;
+      }
+    }
+    walkp[i] = P;
+    thr[i] = ~0ull;
+    cnt2[i] = 0;
+    flag[i] = 0;
+  }
+}
+
+// (query, slot) pairs of the list-major pass: count per list, then fill.
+__device__ __forceinline__ int lm_pair_list(const DevIndex& ix, const int32_t* lists,
+                                            const int32_t* np_eff, const int32_t* walkp,
+                                            int np_max, int qc, int i, int* q_out) {
+  const int q = i / np_max, p = i % np_max;
+  if (q >= qc || p >= np_eff[q] || p < walkp[q]) return -1;
+  const int l = lists[(size_t)q * np_max + p];
+  if (ix.pstart[l + 1] == ix.pstart[l]) return -1;
+  *q_out = q;
+  return l;
+}
+
+__global__ void k_lm_count(DevIndex ix, const int32_t* __restrict__ lists,
+                           const int32_t* __restrict__ np_eff, const int32_t* __restrict__ walkp,
+                           int np_max, int qc, int32_t* __restrict__ lcnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int q;
+  const int l = lm_pair_list(ix, lists, np_eff, walkp, np_max, qc, i, &q);
+  if (l >= 0) atomicAdd(&lcnt[l], 1);
+}
+
+__global__ void k_lm_fill(DevIndex ix, const int32_t* __restrict__ lists,
+                          const int32_t* __restrict__ np_eff, const int32_t* __restrict__ walkp,
+                          int np_max, int qc, const int32_t* __restrict__ loff,
+                          int32_t* __restrict__ lfill, int32_t* __restrict__ invq) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int q;
+  const int l = lm_pair_list(ix, lists, np_eff, walkp, np_max, qc, i, &q);
+  if (l >= 0) invq[loff[l] + atomicAdd(&lfill[l], 1)] = q;
+}
+
+// One block: per-list query offsets and work-item offsets (exclusive prefix
+// sums; each thread sums a contiguous run of lists), and the item count.
+__global__ __launch_bounds__(1024) void k_lm_offsets(DevIndex ix, const int32_t* __restrict__ lcnt,
+                                                     int tile_rows, int32_t* __restrict__ loff,
+                                                     int32_t* __restrict__ ioff,
+                                                     int32_t* __restrict__ ctr) {
+  __shared__ int s_a[17], s_b[17];
+  const int tid = threadIdx.x;
+  const int ch = (ix.nlist + 1023) / 1024;
+  const int l0 = min(ix.nlist, tid * ch), l1 = min(ix.nlist, l0 + ch);
+  auto items = [&](int l, int c) {
+    if (c == 0) return 0;
+    const int len = ix.pstart[l + 1] - ix.pstart[l];
+    return ((c + kLmG - 1) / kLmG) * ((len + tile_rows - 1) / tile_rows);
+  };
+  int sa = 0, sb = 0;
+  for (int l = l0; l < l1; ++l) {
+    const int c = lcnt[l];
+    sa += c;
+    sb += items(l, c);
+  }
+  int a = block_excl_scan(sa, s_a);
+  int b = block_excl_scan(sb, s_b);
+  for (int l = l0; l < l1; ++l) {
+    const int c = lcnt[l];
+    loff[l] = a;
+    ioff[l] = b;
+    a += c;
+    b += items(l, c);
+  }
+  if (tid == 1023) {
+    loff[ix.nlist] = a;
+    ioff[ix.nlist] = b;
+    ctr[0] = b;
+  }
+}
+
+// Decoded bytes [kb, kb + 16) of a code row (kb a multiple of 16): codes
+// kb/DS .. (kb+16)/DS - 1, each replaced by its DS-byte int8 codeword; codes
+// past M (row padding) decode to zero.
+template <int DS>
+__device__ __forceinline__ v4i_t lm_decode(const DevIndex& ix, const int8_t* __restrict__ s_cb,
+                                           const uint8_t* __restrict__ crow, int kb) {
+  constexpr int NC = 16 / DS;  // codes per lane and chunk
+  const int m0 = kb / DS;
+  uint32_t cw[(NC + 3) / 4];
+#pragma unroll
+  for (int i = 0; i < (NC + 3) / 4; ++i) {
+    const int off = (m0 & ~3) + 4 * i;
+    cw[i] = off < ix.row_bytes ? *reinterpret_cast<const uint32_t*>(crow + off) : 0u;
+  }
+  auto code = [&](int j) -> uint32_t {  // code byte m0 + j
+    const int b = (m0 & 3) + j;
+    return (cw[b >> 2] >> (8 * (b & 3))) & 255u;
+  };
+  v4i_t out;
+  if constexpr (DS == 1) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = m0 + 4 * d + j;
+        const uint32_t v = m < ix.M ? (uint8_t)s_cb[m * kKsub + code(4 * d + j)] : 0u;
+        w |= v << (8 * j);
+      }
+      out[d] = (int)w;
+    }
+  } else if constexpr (DS == 2) {
+    const uint16_t* cb = reinterpret_cast<const uint16_t*>(s_cb);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int m = m0 + 2 * d;
+      const uint32_t lo = m < ix.M ? cb[m * kKsub + code(2 * d)] : 0u;
+      const uint32_t hi = m + 1 < ix.M ? cb[(m + 1) * kKsub + code(2 * d + 1)] : 0u;
+      out[d] = (int)(lo | (hi << 16));
+    }
+  } else if constexpr (DS == 4) {
+    const uint32_t* cb = reinterpret_cast<const uint32_t*>(s_cb);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int m = m0 + d;
+      out[d] = m < ix.M ? (int)cb[m * kKsub + code(d)] : 0;
+    }
+  } else {  // DS == 8
+    const uint2* cb = reinterpret_cast<const uint2*>(s_cb);
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int m = m0 + d;
+      const uint2 v = m < ix.M ? cb[m * kKsub + code(d)] : make_uint2(0u, 0u);
+      out[2 * d] = (int)v.x;
+      out[2 * d + 1] = (int)v.y;
+    }
+  }
+  return out;
+}
+
+__device__ __forceinline__ int sq_bytes(v4i_t v, int acc) {
+  acc = __builtin_amdgcn_sdot4(v[0], v[0], acc, false);
+  acc = __builtin_amdgcn_sdot4(v[1], v[1], acc, false);
+  acc = __builtin_amdgcn_sdot4(v[2], v[2], acc, false);
+  return __builtin_amdgcn_sdot4(v[3], v[3], acc, false);
+}
+
+// The persistent list-major kernel.  KC = dim_pad / 64 (K chunks of one
+// MFMA), DS = dsub.  Wave w of a block takes 16-row tiles w, w + 4, ... of
+// the item, kLmU of them per round with their code loads in flight together.
+// Lane (r, g) (r = lane % 16, g = lane / 16) holds query row r's and
+// candidate r's bytes [16g, 16g + 16) of each K chunk, and after the MFMA the
+// products of queries 4g..4g+3 with candidate r.
+template <int KC, int DS>
+__global__ __launch_bounds__(kLmBlock) void k_lm_mfma(DevIndex ix, const float* __restrict__ Q,
+                                                      LmArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int Dp = KC * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int cb_bytes = (ix.M * kKsub * DS + 15) / 16 * 16;
+  int8_t* s_cb = reinterpret_cast<int8_t*>(smem);
+  int8_t* s_q8 = reinterpret_cast<int8_t*>(smem + cb_bytes);  // [16][Dp]
+  unsigned long long* s_thr =
+      reinterpret_cast<unsigned long long*>(smem + cb_bytes + kLmG * Dp);  // [16]
+  int* s_qid = reinterpret_cast<int*>(s_thr + kLmG);                      // [16]
+  int* s_it = s_qid + kLmG;  // item, queries, first row, end row, first query slot
+  for (int i = tid; i < cb_bytes / 16; i += kLmBlock)
+    reinterpret_cast<int4*>(s_cb)[i] = reinterpret_cast<const int4*>(ix.cb8)[i];
+  const int nitems = a.ctr[0];
+  for (;;) {
+    if (tid == 0) {
+      const int it = atomicAdd(&a.ctr[1], 1);
+      s_it[0] = it;
+      if (it < nitems) {
+        int lo = 0, hi = ix.nlist - 1;  // the list: largest l with ioff[l] <= it
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (a.ioff[mid] <= it) lo = mid;
+          else hi = mid - 1;
+        }
+        const int l = lo, local = it - a.ioff[l], nql = a.lcnt[l];
+        const int ng = (nql + kLmG - 1) / kLmG;
+        const int grp = local % ng, tile = local / ng;  // groups of one tile adjacent
+        const int r0 = ix.pstart[l] + tile * a.tile_rows;
+        s_it[1] = min(kLmG, nql - grp * kLmG);
+        s_it[2] = r0;
+        s_it[3] = min(ix.pstart[l + 1], r0 + a.tile_rows);
+        s_it[4] = a.loff[l] + grp * kLmG;
+      }
+    }
+    __syncthreads();
+    if (s_it[0] >= nitems) break;  // block-uniform
+    const int gcnt = s_it[1], row0 = s_it[2], row1 = s_it[3], qbase = s_it[4];
+    if (tid < kLmG) {
+      const int qid = tid < gcnt ? a.invq[qbase + tid] : -1;
+      s_qid[tid] = qid;
+      s_thr[tid] = qid >= 0 ? a.thr[qid] : 0ull;
+    }
+    __syncthreads();
+    for (int i = tid; i < kLmG * Dp; i += kLmBlock) {  // queries as shifted int8, zero-padded
+      const int qi = i / Dp, t = i % Dp, qid = s_qid[qi];
+      int v = 0;
+      if (qid >= 0 && t < ix.dim)
+        v = (int)conv_query(Q[(size_t)qid * ix.dim + t], ix.dtype) - ix.shift8;
+      s_q8[i] = (int8_t)v;
+    }
+    __syncthreads();
+    v4i_t fa[KC];
+    int qn_r = 0;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      fa[kc] = *reinterpret_cast<const v4i_t*>(s_q8 + r16 * Dp + kc * 64 + 16 * g);
+      qn_r = sq_bytes(fa[kc], qn_r);
+    }
+    qn_r += __shfl_xor(qn_r, 16, 64);
+    qn_r += __shfl_xor(qn_r, 32, 64);  // ||q'||^2 of query row r16
+    int qn[4], qid[4];
+    unsigned long long th[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      qn[r] = __shfl(qn_r, 4 * g + r, 64);
+      qid[r] = s_qid[4 * g + r];
+      th[r] = s_thr[4 * g + r];
+    }
+    constexpr int kStep = 16 * (kLmBlock / 64);
+    for (int base = row0 + 16 * wv; base < row1; base += kStep * kLmU) {
+      v4i_t fb[kLmU][KC];
+      int rn[kLmU];
+#pragma unroll
+      for (int u = 0; u < kLmU; ++u) {  // every code load of the round first
+        const int row = base + u * kStep + r16;
+        const uint8_t* crow = ix.codes + (size_t)(row < row1 ? row : row0) * ix.row_bytes;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) fb[u][kc] = lm_decode<DS>(ix, s_cb, crow, kc * 64 + 16 * g);
+      }
+#pragma unroll
+      for (int u = 0; u < kLmU; ++u) {
+        const int row = base + u * kStep + r16;
+        const bool rv = row < row1;
+        rn[u] = 0;
+        v4i_t acc = v4i_t{0, 0, 0, 0};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+          rn[u] = sq_bytes(fb[u][kc], rn[u]);
+          acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[kc], fb[u][kc], acc, 0, 0, 0);
+        }
+        int rnu = rn[u];
+        rnu += __shfl_xor(rnu, 16, 64);
+        rnu += __shfl_xor(rnu, 32, 64);  // ||dec'||^2 of candidate r16
+        uint32_t ext = 0;
+        bool have_ext = false;
+        bool pass[4];
+        uint64_t key[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          pass[r] = false;
+          key[r] = 0;
+          if (rv && qid[r] >= 0) {
+            const float d = (float)(qn[r] + rnu - 2 * acc[r]);  // exact integer
+            const uint32_t h = ord32(d);
+            if (h <= (uint32_t)(th[r] >> 32)) {
+              if (!have_ext) {
+                ext = (uint32_t)ix.row2ext[row];
+                have_ext = true;
+              }
+              key[r] = ((uint64_t)h << 32) | ext;
+              pass[r] = key[r] < th[r];
+            }
+          }
+        }
+        // append: one atomic per (query, 16-lane group holding it)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint64_t m = __ballot(pass[r]);
+          if (m) {  // wave-uniform
+            const uint32_t seg = (uint32_t)(m >> (16 * g)) & 0xffffu;
+            const int leader = seg ? 16 * g + __ffs(seg) - 1 : lane;
+            int pos0 = 0;
+            if (pass[r] && lane == leader) pos0 = atomicAdd(&a.cnt2[qid[r]], __popc(seg));
+            pos0 = __shfl(pos0, leader, 64);
+            if (pass[r]) {
+              const int pos = pos0 + __popc(seg & ((1u << (lane - 16 * g)) - 1u));
+              if (pos < a.cap2) a.out2[(size_t)qid[r] * a.cap2 + pos] = key[r];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();  // the next item restages the queries
+  }
+}
+
+// Per query: the n smallest of the per-query scan's item keys and the
+// list-major keys, into item 0 (sq = 1), with the work counts; a query whose
+// list-major area overflowed is flagged for a full per-query scan instead.
+__global__ __launch_bounds__(kBlock) void k_lm_select(
+    DevIndex ix, const int32_t* __restrict__ lists, const int32_t* __restrict__ np_eff,
+    int np_max, const int32_t* __restrict__ walkp, int smax, int n, uint64_t* __restrict__ pkeys,
+    int32_t* __restrict__ pcount, int32_t* __restrict__ pscan, int32_t* __restrict__ sq,
+    const int32_t* __restrict__ cnt2, const uint64_t* __restrict__ out2, int cap2,
+    uint8_t* __restrict__ flag) {
+  extern __shared__ __align__(16) uint64_t s_top[];  // [n]
+  __shared__ SelScratch ss;
+  __shared__ int s_off[17];
+  __shared__ int s_cnt, s_sc, s_sw;
+  const int q = blockIdx.x, tid = threadIdx.x;
+  const int c2 = cnt2[q];
+  if (c2 > cap2) {
+    if (tid == 0) flag[q] = 1;
+    return;
+  }
+  const int S = sq[q];
+  const size_t it0 = (size_t)q * smax;
+  if (tid < 64) {
+    int c = 0, sc = 0, sw = 0;
+    if (tid < S) {
+      c = pcount[it0 + tid];
+      sc = pscan[2 * (it0 + tid)];
+      sw = pscan[2 * (it0 + tid) + 1];
+    }
+    const int incl = (int)wave_incl_scan((uint32_t)c);
+    if (tid < S) s_off[tid] = incl - c;
+    if (tid == S - 1) s_off[S] = incl;
+    const int np = np_eff[q];
+    for (int p = min(np, walkp[q]) + tid; p < np; p += 64) {  // rows of the list-major part
+      const int l = lists[(size_t)q * np_max + p];
+      const int r = ix.pstart[l + 1] - ix.pstart[l];
+      sc += r;
+      sw += r;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+      sc += __shfl_xor(sc, d, 64);
+      sw += __shfl_xor(sw, d, 64);
+    }
+    if (tid == 0) {
+      s_sc = sc;
+      s_sw = sw;
+      s_cnt = 0;
+    }
+  }
+  __syncthreads();
+  const int t1 = s_off[S], total = t1 + c2;
+  auto get = [&](int i) -> uint64_t {
+    if (i < t1) {
+      int j = 0;
+      while (j + 1 < S && s_off[j + 1] <= i) ++j;
+      return pkeys[(it0 + j) * n + (i - s_off[j])];
+    }
+    return out2[(size_t)q * cap2 + (i - t1)];
+  };
+  const uint64_t K = total > n ? block_kth(get, total, n, &ss) : ~0ull;
+  for (int i = tid; i < total; i += kBlock) {
+    const uint64_t k = get(i);
+    if (k <= K) {
+      const int pos = atomicAdd(&s_cnt, 1);
+      if (pos < n) s_top[pos] = k;
+    }
+  }
+  __syncthreads();  // every read of item 0 is done
+  const int cnt = min(s_cnt, n);
+  for (int i = tid; i < cnt; i += kBlock) pkeys[it0 * n + i] = s_top[i];
+  if (tid == 0) {
+    pcount[it0] = cnt;
+    pscan[2 * it0] = s_sc;
+    pscan[2 * it0 + 1] = s_sw;
+    sq[q] = 1;
+  }
 }
 
 }  // namespace
@@ -2259,7 +2882,7 @@ hipError_t launch_scan(const DevIndex& ix, const int32_t* lists, const int32_t* 
   }
   return scan_fn(W)(ix, lists, np_eff, c.np_max, c.qc, q, nullptr, w.sq, c.smax, c.tile, c.n, cap,
                     w.pkeys, w.pcount, w.pscan, perm, false, c.lut16, 0, nullptr, nullptr, nullptr,
-                    st);
+                    ScanSplit{}, st);
 }
 
 hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const float* lut, int qc,
@@ -2273,20 +2896,33 @@ hipError_t launch_scan_trace(const DevIndex& ix, const int32_t* lists, const flo
   const int W = (ix.M + 3) / 4;
   return scan_fn(W)(ix, lists, w.np_eff, np_max, qc, nullptr, lut, w.sq, smax, tile, 1, 1, nullptr,
                     nullptr, nullptr, nullptr, true, false, capacity, out_ids, out_adc, out_count,
-                    st);
+                    ScanSplit{}, st);
 }
 
 hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,
                         int32_t* topn_ids, float* topn_adc, int64_t* ncand, int64_t* nwalk,
-                        int64_t* out_ids, float* out_dists, int32_t* reranked, hipStream_t st) {
+                        int64_t* out_ids, float* out_dists, int32_t* reranked,
+                        int32_t* page_reads, hipStream_t st) {
   if (c.qc <= 0) return hipSuccess;
   const MergeLayout L = merge_layout(c.smax, c.n, ix.dim);
+  const bool heur = c.hb > 0 && out_ids;
+  if (ix.hpages && out_ids) {
+    // raw vectors in host memory: 256-thread blocks, a page buffer per wave
+    const size_t lds = L.total + page_scratch_bytes(pow2_at_least(c.n), 256 / 64, ix.page_bytes);
+    auto kern = heur ? k_merge<256, true, true> : k_merge<256, false, true>;
+    if (lds > 65536)
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+    hipLaunchKernelGGL(kern, dim3(c.qc), dim3(256), lds, st, ix, q, c.qc, w.sq, c.smax, c.n, c.k,
+                       w.pkeys, w.pcount, w.pscan, topn_ids, topn_adc, ncand, nwalk, out_ids,
+                       out_dists, c.hb, c.h_eps, c.h_beta, reranked, page_reads);
+    return hipGetLastError();
+  }
   // More threads only pay off when there are many candidates to re-rank.
   // Then four 512-thread blocks per CU, where their LDS fits, beat two of
   // 1024: while one block sits in its barrier-bound selection and sort, the
   // others' row gathers keep memory busy (rerank_n 600: 0.34 -> 0.26 ms;
   // heuristic rerank_n 2000: 1.73 -> 1.25 ms).
-  const bool heur = c.hb > 0 && out_ids;
   const int bs = c.n <= 512 ? 256 : 4 * L.total <= (size_t)kLdsPerCu ? 512 : kMergeBlock;
   auto kern = heur ? (bs == 256   ? k_merge<256, true>
                       : bs == 512 ? k_merge<512, true>
@@ -2298,7 +2934,7 @@ hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, 
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.total);
   hipLaunchKernelGGL(kern, dim3(c.qc), dim3(bs), L.total, st, ix, q, c.qc, w.sq, c.smax,
                      c.n, c.k, w.pkeys, w.pcount, w.pscan, topn_ids, topn_adc, ncand, nwalk, out_ids,
-                     out_dists, c.hb, c.h_eps, c.h_beta, reranked);
+                     out_dists, c.hb, c.h_eps, c.h_beta, reranked, nullptr);
   return hipGetLastError();
 }
 
@@ -2315,6 +2951,105 @@ hipError_t launch_rerank_only(const DevIndex& ix, const float* q, const int32_t*
   hipLaunchKernelGGL(kern, dim3(qc), dim3(big ? kMergeBlock : 256), lds, st, ix, q, cand, n, k, out_ids,
                      out_dists);
   return hipGetLastError();
+}
+
+}  // namespace ann
+
+namespace ann {
+
+// ---------------------------------------------------------------------------
+// Batched form: the list-major pass (see k_lm_mfma).
+
+bool lmajor_supported(const DevIndex& ix) {
+  return ix.int_grid && ix.cb8 && ix.cent8 &&
+         (ix.dsub == 1 || ix.dsub == 2 || ix.dsub == 4 || ix.dsub == 8) && ix.dim_pad <= 256 &&
+         (size_t)ix.M * kKsub * ix.dsub <= 64 * 1024;
+}
+
+int lmajor_cap2(int n) { return std::min(32768, std::max(4096, 16 * n)); }
+
+namespace {
+
+using LmFn = void (*)(DevIndex, const float*, LmArgs);
+
+template <int KC>
+LmFn lm_kernel_ds(int ds) {
+  switch (ds) {
+    case 1: return k_lm_mfma<KC, 1>;
+    case 2: return k_lm_mfma<KC, 2>;
+    case 4: return k_lm_mfma<KC, 4>;
+    default: return k_lm_mfma<KC, 8>;
+  }
+}
+
+LmFn lm_kernel(const DevIndex& ix) {
+  switch (ix.dim_pad / 64) {
+    case 1: return lm_kernel_ds<1>(ix.dsub);
+    case 2: return lm_kernel_ds<2>(ix.dsub);
+    case 3: return lm_kernel_ds<3>(ix.dsub);
+    default: return lm_kernel_ds<4>(ix.dsub);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_lmajor(const DevIndex& ix, const float* q, const LaunchCfg& c, Work& w,
+                         const LmWork& lw, const LmCfg& lc, int num_cu, int phase,
+                         hipStream_t st) {
+  if (c.qc <= 0) return hipSuccess;
+  const int W = (ix.M + 3) / 4;
+  const int cap = scan_cap(ix, c.np_max, c.n, c.lut16);
+  const int pairs = c.qc * c.np_max;
+  const dim3 gp((pairs + 255) / 256);
+  switch (phase) {
+    case 0: {  // which slots each query leaves to the list-major pass; counters
+      const int nprep = std::max({c.qc, ix.nlist, 4});
+      hipLaunchKernelGGL(k_lm_prep, dim3((nprep + 255) / 256), dim3(256), 0, st, ix, w.lists,
+                         w.np_eff, c.np_max, c.qc, (int64_t)lc.alpha * c.n, lw.walkp, lw.thr,
+                         lw.cnt2, lw.flag, lw.lcnt, lw.lfill, lw.ctr);
+      return hipGetLastError();
+    }
+    case 1:  // per-query part: leading lists' first-list rows, every replica entry
+      return scan_fn(W)(ix, w.lists, w.np_eff, c.np_max, c.qc, q, nullptr, w.sq, c.smax, c.tile,
+                        c.n, cap, w.pkeys, w.pcount, w.pscan, nullptr, false, c.lut16, 0, nullptr,
+                        nullptr, nullptr, ScanSplit{lw.walkp, nullptr, lw.thr}, st);
+    case 2:  // the work list
+      hipLaunchKernelGGL(k_lm_count, gp, dim3(256), 0, st, ix, w.lists, w.np_eff, lw.walkp,
+                         c.np_max, c.qc, lw.lcnt);
+      hipLaunchKernelGGL(k_lm_offsets, dim3(1), dim3(1024), 0, st, ix, lw.lcnt, lc.tile_rows,
+                         lw.loff, lw.ioff, lw.ctr);
+      hipLaunchKernelGGL(k_lm_fill, gp, dim3(256), 0, st, ix, w.lists, w.np_eff, lw.walkp,
+                         c.np_max, c.qc, lw.loff, lw.lfill, lw.invq);
+      return hipGetLastError();
+    case 3: {  // the persistent list-major launch
+      const int KC = ix.dim_pad / 64;
+      const size_t cb_bytes = ((size_t)ix.M * kKsub * ix.dsub + 15) / 16 * 16;
+      const size_t lds = cb_bytes + (size_t)kLmG * KC * 64 + kLmG * 8 + kLmG * 4 + 8 * 4;
+      const LmFn kern = lm_kernel(ix);
+      if (lds > 65536)
+        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+      const int blocks = lc.blocks > 0 ? lc.blocks : 4 * std::max(1, num_cu);
+      LmArgs a{lw.loff, lw.ioff, lw.lcnt, lw.invq, lw.thr, lw.cnt2, lw.out2, lw.cap2, lw.ctr,
+               lc.tile_rows};
+      hipLaunchKernelGGL(kern, dim3(blocks), dim3(kLmBlock), lds, st, ix, q, a);
+      return hipGetLastError();
+    }
+    case 4: {  // both parts' n best per query
+      const size_t lds_sel = (size_t)c.n * 8;
+      if (lds_sel > 65536)
+        (void)hipFuncSetAttribute((const void*)k_lm_select,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_sel);
+      hipLaunchKernelGGL(k_lm_select, dim3(c.qc), dim3(kBlock), lds_sel, st, ix, w.lists,
+                         w.np_eff, c.np_max, lw.walkp, c.smax, c.n, w.pkeys, w.pcount, w.pscan,
+                         w.sq, lw.cnt2, lw.out2, lw.cap2, lw.flag);
+      return hipGetLastError();
+    }
+    default:  // queries whose list-major output overflowed: the whole query per query
+      return scan_fn(W)(ix, w.lists, w.np_eff, c.np_max, c.qc, q, nullptr, w.sq, c.smax, c.tile,
+                        c.n, cap, w.pkeys, w.pcount, w.pscan, nullptr, false, c.lut16, 0, nullptr,
+                        nullptr, nullptr, ScanSplit{nullptr, lw.flag, nullptr}, st);
+  }
 }
 
 }  // namespace ann

@@ -36,12 +36,12 @@ class IndexDesc(ctypes.Structure):
         ("page_bytes", ctypes.c_int32), ("pages", ctypes.c_int64), ("host_bytes", ctypes.c_int64),
     ]
 
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
 
 class LoadCfg(ctypes.Structure):
     _fields_ = [("raw_tier", ctypes.c_int32), ("page_bytes", ctypes.c_int32)]
-
-    def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Profile(ctypes.Structure):

@@ -71,3 +71,31 @@ def test_header_compiles_and_links_for_plain_callers(tmp_path, lang):
     assert r.returncode == 0, r.stdout + r.stderr
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the C header's sizes and
+    field offsets (a struct that drifts from the header corrupts calls)."""
+    from paper_2409_16576_amd import ann
+    pairs = {"ann_index_desc": ann.IndexDesc, "ann_tune_result": ann.TuneResult,
+             "ann_profile": ann.Profile, "ann_load_cfg": ann.LoadCfg,
+             "ann_server_cfg": ann.ServerCfg, "ann_server_stats": ann.ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ann.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "sizes.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sizes"
+    r = subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = dict(ln.split() for ln in subprocess.run([str(exe)], capture_output=True,
+                                                   text=True).stdout.splitlines())
+    for cname, py in pairs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+    assert ann.IndexDesc().as_dict()["raw_tier"] == 0

@@ -152,6 +152,30 @@ ann_status ann_search(ann_index* ix, const float* d_queries, int64_t nq, const i
                       float* d_out_dists, void* stream);
 
 /*
+ * ann_search for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same steps, arguments, results and errors as ann_search, but the working
+ * buffers come from one fixed device array of ann_noalloc_scratch_bytes()
+ * bytes (128 MiB) per device, set up when an index is first loaded on that
+ * device and held until the process ends.  The call allocates and frees
+ * nothing and records no timing events; a batch whose working buffers exceed
+ * the array is searched in chunks that fit, one after another on `stream`.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (different streams, or threads without ordering) race and may
+ * return wrong results; calls ordered on one stream are safe.  The array
+ * keeps the last call's contents; nothing in it needs to start at zero.
+ * Errors: as ann_search; ANN_EINVAL also when a single query needs more
+ * working memory than the array holds.
+ */
+ann_status ann_search_noalloc(ann_index* ix, const float* d_queries, int64_t nq,
+                              const int32_t* d_nprobe, int32_t nprobe_max, int32_t k,
+                              int32_t rerank_n, int64_t* d_out_ids, float* d_out_dists,
+                              void* stream);
+
+/* Size in bytes of the per-device array ann_search_noalloc works in. */
+size_t ann_noalloc_scratch_bytes(void);
+
+/*
  * Steps 1-8 with step 8 by the heuristic re-ranking of Alg. 1 (change rate
  * of Eq. 3) instead of a fixed number of exact distances.  The rerank_n
  * candidates of step 7 are taken in ascending (ADC distance, id) order in

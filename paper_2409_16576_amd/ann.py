@@ -96,6 +96,9 @@ def lib():
         L.ann_free_index.argtypes = [P]
         L.ann_free_index.restype = None
         L.ann_search.argtypes = [P, P, i64, P, i32, i32, i32, P, P, P]
+        L.ann_search_noalloc.argtypes = [P, P, i64, P, i32, i32, i32, P, P, P]
+        L.ann_noalloc_scratch_bytes.argtypes = []
+        L.ann_noalloc_scratch_bytes.restype = ctypes.c_size_t
         L.ann_search_topn.argtypes = [P, P, i64, P, i32, i32, P, P, P, P, P]
         L.ann_probe.argtypes = [P, P, i64, P, i32, P, P, P]
         L.ann_lut.argtypes = [P, P, i64, P, P]
@@ -129,7 +132,7 @@ def lib():
                   "ann_get_profile", "ann_set_option", "ann_get_option", "ann_server_start",
                   "ann_server_submit", "ann_server_poll", "ann_server_get_stats",
                   "ann_server_stop", "ann_graph_create", "ann_graph_launch", "ann_autotune",
-                  "ann_search_heuristic", "ann_load_index_ex",
+                  "ann_search_heuristic", "ann_search_noalloc", "ann_load_index_ex",
                   "ann_search_pages"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -203,6 +206,21 @@ class Index:
         d = torch.empty((nq, k), dtype=torch.float32, device=self.device)
         _check(lib().ann_search(self._h, _ptr(q), nq, _ptr(npt), npmax, k, rerank_n, _ptr(ids),
                                 _ptr(d), _stream(self.device, stream)))
+        return ids, d
+
+    def search_noalloc(self, queries, nprobe, k: int, rerank_n: int, out=None, stream=None):
+        """ann_search_noalloc: the same search on the library's fixed per-device
+        scratch array (no device allocation in the library).  `out` may give
+        preallocated (ids, dists) tensors."""
+        q = self._queries(queries)
+        nq = q.shape[0]
+        npt, npmax = self._nprobe(nprobe, nq)
+        if out is None:
+            out = (torch.empty((nq, k), dtype=torch.int64, device=self.device),
+                   torch.empty((nq, k), dtype=torch.float32, device=self.device))
+        ids, d = out
+        _check(lib().ann_search_noalloc(self._h, _ptr(q), nq, _ptr(npt), npmax, k, rerank_n,
+                                        _ptr(ids), _ptr(d), _stream(self.device, stream)))
         return ids, d
 
     def search_heuristic(self, queries, nprobe, k: int, rerank_n: int, batch_size: int,

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIBANN = os.path.join(HERE, "libann.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["ann_kernels.hip", "ann_api.cpp", "ann_diff.hip", "ann_server.cpp", "ann_batch.cpp"]
+SOURCES = ["ann_kernels.hip", "ann_api.cpp", "ann_diff.hip", "ann_server.cpp", "ann_batch.cpp",
+           "ann_noalloc.cpp"]
 
 # Packed FP32 instructions are disabled for all device code (they are not
 # needed here and some of their forms are unreliable on the test machines).

@@ -662,6 +662,7 @@ extern "C" ann_status ann_load_index_ex(const char* path, int device, const ann_
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return fail(ANN_EDEVICE, "device %d not available", device);
   HIP_TRY(hipSetDevice(device));
+  if (noalloc_setup(device) != ANN_OK) return ANN_EDEVICE;  // message already set
   HIP_TRY(hipDeviceGetAttribute(&ix->num_cu, hipDeviceAttributeMultiprocessorCount, device));
   DevIndex& d = ix->d;
   d.dtype = dtype; d.dim = dim; d.nlist = nlist; d.M = M; d.row_bytes = row_bytes; d.dsub = dsub;

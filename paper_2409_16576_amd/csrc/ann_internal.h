@@ -161,6 +161,10 @@ bool set_capturing(bool on);       // this thread records no stage events (graph
                                    // no-alloc calls); returns the previous setting
 int get_opt(const ann_index* ix, int option, int64_t* v);
 
+// Allocation-free search (ann_noalloc.cpp): looks up this device's scratch
+// array once (the device must be current); called at index load.
+int noalloc_setup(int device);
+
 // Records the thread's last error message (ann_last_error) and returns s.
 int set_error(int s, const char* fmt, ...);
 

@@ -2377,7 +2377,7 @@ ScanFn scan_fn(int W) {
 
 constexpr int kLmG = 16;       // queries per group (rows of the MFMA tile)
 constexpr int kLmBlock = 256;  // threads per list-major block (4 waves)
-constexpr int kLmU = 2;        // 16-row tiles per wave with loads in flight together
+constexpr int kLmU = 4;        // 16-row tiles per wave with loads in flight together
 
 struct LmArgs {
   const int32_t* loff;   // [nlist + 1] start of each list's queries in invq
@@ -2493,63 +2493,59 @@ __global__ __launch_bounds__(1024) void k_lm_offsets(DevIndex ix, const int32_t*
   }
 }
 
-// Decoded bytes [kb, kb + 16) of a code row (kb a multiple of 16): codes
-// kb/DS .. (kb+16)/DS - 1, each replaced by its DS-byte int8 codeword; codes
-// past M (row padding) decode to zero.
+// The code dwords a lane needs for K chunk kc of a row: codes (kc*64 + 16g)/DS
+// onward, 16/DS of them.  Offsets past the row (padding subspaces) are
+// clamped to the row's first dword: those codes look up the zero codewords
+// of the padded LDS codebook whatever their value.
 template <int DS>
-__device__ __forceinline__ v4i_t lm_decode(const DevIndex& ix, const int8_t* __restrict__ s_cb,
-                                           const uint8_t* __restrict__ crow, int kb) {
-  constexpr int NC = 16 / DS;  // codes per lane and chunk
-  const int m0 = kb / DS;
-  uint32_t cw[(NC + 3) / 4];
-#pragma unroll
-  for (int i = 0; i < (NC + 3) / 4; ++i) {
-    const int off = (m0 & ~3) + 4 * i;
-    cw[i] = off < ix.row_bytes ? *reinterpret_cast<const uint32_t*>(crow + off) : 0u;
-  }
-  auto code = [&](int j) -> uint32_t {  // code byte m0 + j
-    const int b = (m0 & 3) + j;
-    return (cw[b >> 2] >> (8 * (b & 3))) & 255u;
+struct LmCodes {
+  static constexpr int NC = 16 / DS;            // codes per lane and chunk
+  static constexpr int ND = NC >= 4 ? NC / 4 : 1;  // code dwords per lane and chunk
+};
+
+// Decoded bytes [kb, kb + 16) from the code dwords w (first code at byte
+// b0 of w[0]); cb: this lane's LDS codebook base for the chunk (subspace
+// kb / DS).  Padded subspaces are all-zero codewords.
+template <int DS>
+__device__ __forceinline__ v4i_t lm_decode(const unsigned char* __restrict__ cb,
+                                           const uint32_t (&w)[LmCodes<DS>::ND], int b0) {
+  constexpr int NC = LmCodes<DS>::NC;
+  constexpr int kSub = kKsub * DS;  // bytes per subspace
+  auto code = [&](int j) -> uint32_t {  // byte j of the lane's codes
+    const int b = (DS == 8 ? b0 : 0) + j;
+    return (w[b >> 2] >> (8 * (b & 3))) & 255u;
   };
   v4i_t out;
   if constexpr (DS == 1) {
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-      uint32_t w = 0;
+      uint32_t v = 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int m = m0 + 4 * d + j;
-        const uint32_t v = m < ix.M ? (uint8_t)s_cb[m * kKsub + code(4 * d + j)] : 0u;
-        w |= v << (8 * j);
-      }
-      out[d] = (int)w;
+      for (int j = 0; j < 4; ++j)
+        v |= (uint32_t)cb[(4 * d + j) * kSub + code(4 * d + j)] << (8 * j);
+      out[d] = (int)v;
     }
   } else if constexpr (DS == 2) {
-    const uint16_t* cb = reinterpret_cast<const uint16_t*>(s_cb);
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-      const int m = m0 + 2 * d;
-      const uint32_t lo = m < ix.M ? cb[m * kKsub + code(2 * d)] : 0u;
-      const uint32_t hi = m + 1 < ix.M ? cb[(m + 1) * kKsub + code(2 * d + 1)] : 0u;
+      const uint32_t lo = *reinterpret_cast<const uint16_t*>(cb + (2 * d) * kSub + 2 * code(2 * d));
+      const uint32_t hi =
+          *reinterpret_cast<const uint16_t*>(cb + (2 * d + 1) * kSub + 2 * code(2 * d + 1));
       out[d] = (int)(lo | (hi << 16));
     }
   } else if constexpr (DS == 4) {
-    const uint32_t* cb = reinterpret_cast<const uint32_t*>(s_cb);
 #pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const int m = m0 + d;
-      out[d] = m < ix.M ? (int)cb[m * kKsub + code(d)] : 0;
-    }
+    for (int d = 0; d < 4; ++d)
+      out[d] = *reinterpret_cast<const int*>(cb + d * kSub + 4 * code(d));
   } else {  // DS == 8
-    const uint2* cb = reinterpret_cast<const uint2*>(s_cb);
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
-      const int m = m0 + d;
-      const uint2 v = m < ix.M ? cb[m * kKsub + code(d)] : make_uint2(0u, 0u);
+      const uint2 v = *reinterpret_cast<const uint2*>(cb + d * kSub + 8 * code(d));
       out[2 * d] = (int)v.x;
       out[2 * d + 1] = (int)v.y;
     }
   }
+  (void)NC;
   return out;
 }
 
@@ -2560,28 +2556,53 @@ __device__ __forceinline__ int sq_bytes(v4i_t v, int acc) {
   return __builtin_amdgcn_sdot4(v[3], v[3], acc, false);
 }
 
+// LDS codebook bytes of the list-major kernel: dim_pad / dsub subspaces (the
+// ones past M all zero), 256 codewords of dsub bytes each.
+__host__ __device__ inline int lm_cb_bytes(int dim_pad) { return dim_pad * kKsub; }
+
 // The persistent list-major kernel.  KC = dim_pad / 64 (K chunks of one
 // MFMA), DS = dsub.  Wave w of a block takes 16-row tiles w, w + 4, ... of
-// the item, kLmU of them per round with their code loads in flight together.
-// Lane (r, g) (r = lane % 16, g = lane / 16) holds query row r's and
-// candidate r's bytes [16g, 16g + 16) of each K chunk, and after the MFMA the
-// products of queries 4g..4g+3 with candidate r.
+// the item, kLmU of them per round with all their loads (code dwords and
+// external IDs) in flight together.  Lane (r, g) (r = lane % 16, g =
+// lane / 16) holds query row r's and candidate r's bytes [16g, 16g + 16) of
+// each K chunk, and after the MFMA the products of queries 4g..4g+3 with
+// candidate r.
 template <int KC, int DS>
 __global__ __launch_bounds__(kLmBlock) void k_lm_mfma(DevIndex ix, const float* __restrict__ Q,
                                                       LmArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int Dp = KC * 64;
+  constexpr int ND = LmCodes<DS>::ND;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, g = lane >> 4;
-  const int cb_bytes = (ix.M * kKsub * DS + 15) / 16 * 16;
-  int8_t* s_cb = reinterpret_cast<int8_t*>(smem);
+  constexpr int cb_bytes = Dp * kKsub;
+  unsigned char* s_cb = smem;
   int8_t* s_q8 = reinterpret_cast<int8_t*>(smem + cb_bytes);  // [16][Dp]
   unsigned long long* s_thr =
       reinterpret_cast<unsigned long long*>(smem + cb_bytes + kLmG * Dp);  // [16]
   int* s_qid = reinterpret_cast<int*>(s_thr + kLmG);                      // [16]
   int* s_it = s_qid + kLmG;  // item, queries, first row, end row, first query slot
-  for (int i = tid; i < cb_bytes / 16; i += kLmBlock)
-    reinterpret_cast<int4*>(s_cb)[i] = reinterpret_cast<const int4*>(ix.cb8)[i];
+  {  // codebook, zero-padded to dim_pad / DS subspaces
+    const int real16 = (ix.M * kKsub * DS + 15) / 16;
+    for (int i = tid; i < cb_bytes / 16; i += kLmBlock)
+      reinterpret_cast<int4*>(s_cb)[i] =
+          i < real16 ? reinterpret_cast<const int4*>(ix.cb8)[i] : int4{0, 0, 0, 0};
+  }
+  // per lane and chunk: code dword offsets in a row, LDS codebook base
+  int coff[KC][ND];
+  int b0[KC];
+  const unsigned char* cbk[KC];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) {
+    const int m0 = (kc * 64 + 16 * g) / DS;
+    b0[kc] = m0 & 3;
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      const int off = (m0 & ~3) + 4 * i;
+      coff[kc][i] = off < ix.row_bytes ? off : 0;
+    }
+    cbk[kc] = s_cb + m0 * kKsub * DS;
+  }
   const int nitems = a.ctr[0];
   for (;;) {
     if (tid == 0) {
@@ -2610,7 +2631,7 @@ __global__ __launch_bounds__(kLmBlock) void k_lm_mfma(DevIndex ix, const float* 
     if (tid < kLmG) {
       const int qid = tid < gcnt ? a.invq[qbase + tid] : -1;
       s_qid[tid] = qid;
-      s_thr[tid] = qid >= 0 ? a.thr[qid] : 0ull;
+      s_thr[tid] = qid >= 0 ? a.thr[qid] : 0ull;  // 0: an empty row never passes
     }
     __syncthreads();
     for (int i = tid; i < kLmG * Dp; i += kLmBlock) {  // queries as shifted int8, zero-padded
@@ -2632,71 +2653,75 @@ __global__ __launch_bounds__(kLmBlock) void k_lm_mfma(DevIndex ix, const float* 
     qn_r += __shfl_xor(qn_r, 32, 64);  // ||q'||^2 of query row r16
     int qn[4], qid[4];
     unsigned long long th[4];
+    uint32_t th_hi[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       qn[r] = __shfl(qn_r, 4 * g + r, 64);
       qid[r] = s_qid[4 * g + r];
       th[r] = s_thr[4 * g + r];
+      th_hi[r] = (uint32_t)(th[r] >> 32);
     }
     constexpr int kStep = 16 * (kLmBlock / 64);
     for (int base = row0 + 16 * wv; base < row1; base += kStep * kLmU) {
-      v4i_t fb[kLmU][KC];
-      int rn[kLmU];
+      uint32_t cw[kLmU][KC][ND];
+      uint32_t ext[kLmU];
+      int rr[kLmU];
 #pragma unroll
-      for (int u = 0; u < kLmU; ++u) {  // every code load of the round first
+      for (int u = 0; u < kLmU; ++u) {  // every load of the round first, external IDs leading
         const int row = base + u * kStep + r16;
-        const uint8_t* crow = ix.codes + (size_t)(row < row1 ? row : row0) * ix.row_bytes;
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc) fb[u][kc] = lm_decode<DS>(ix, s_cb, crow, kc * 64 + 16 * g);
+        rr[u] = row < row1 ? row : row0;
+        ext[u] = (uint32_t)ix.row2ext[rr[u]];
       }
 #pragma unroll
       for (int u = 0; u < kLmU; ++u) {
+        const unsigned char* crow = ix.codes + (size_t)rr[u] * ix.row_bytes;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+          for (int i = 0; i < ND; ++i)
+            cw[u][kc][i] = *reinterpret_cast<const uint32_t*>(crow + coff[kc][i]);
+      }
+      // the IDs are used only when a key may pass; keep their loads here (in
+      // flight with the codes) rather than issued late on that rare path
+#pragma unroll
+      for (int u = 0; u < kLmU; ++u) asm volatile("" ::"v"(ext[u]));
+#pragma unroll
+      for (int u = 0; u < kLmU; ++u) {
         const int row = base + u * kStep + r16;
-        const bool rv = row < row1;
-        rn[u] = 0;
+        int rn = 0;
         v4i_t acc = v4i_t{0, 0, 0, 0};
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
-          rn[u] = sq_bytes(fb[u][kc], rn[u]);
-          acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[kc], fb[u][kc], acc, 0, 0, 0);
+          const v4i_t fb = lm_decode<DS>(cbk[kc], cw[u][kc], b0[kc]);
+          rn = sq_bytes(fb, rn);
+          acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[kc], fb, acc, 0, 0, 0);
         }
-        int rnu = rn[u];
-        rnu += __shfl_xor(rnu, 16, 64);
-        rnu += __shfl_xor(rnu, 32, 64);  // ||dec'||^2 of candidate r16
-        uint32_t ext = 0;
-        bool have_ext = false;
-        bool pass[4];
-        uint64_t key[4];
+        rn += __shfl_xor(rn, 16, 64);
+        rn += __shfl_xor(rn, 32, 64);  // ||dec'||^2 of candidate r16
+        // d >= 0 is an exact integer: its order-preserving bits are bits | 2^31
+        uint32_t h[4];
+        bool c = false;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          pass[r] = false;
-          key[r] = 0;
-          if (rv && qid[r] >= 0) {
-            const float d = (float)(qn[r] + rnu - 2 * acc[r]);  // exact integer
-            const uint32_t h = ord32(d);
-            if (h <= (uint32_t)(th[r] >> 32)) {
-              if (!have_ext) {
-                ext = (uint32_t)ix.row2ext[row];
-                have_ext = true;
-              }
-              key[r] = ((uint64_t)h << 32) | ext;
-              pass[r] = key[r] < th[r];
-            }
-          }
+          h[r] = __float_as_uint((float)(qn[r] + rn - 2 * acc[r])) | 0x80000000u;
+          c = c || h[r] <= th_hi[r];
         }
-        // append: one atomic per (query, 16-lane group holding it)
+        if (__ballot(c) == 0) continue;  // wave-uniform: no key can pass
+        const bool rv = row < row1;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const uint64_t m = __ballot(pass[r]);
-          if (m) {  // wave-uniform
+          const uint64_t key = ((uint64_t)h[r] << 32) | ext[u];
+          const bool pass = rv && key < th[r];
+          const uint64_t m = __ballot(pass);
+          if (m) {  // wave-uniform; append: one atomic per (query, 16-lane group)
             const uint32_t seg = (uint32_t)(m >> (16 * g)) & 0xffffu;
             const int leader = seg ? 16 * g + __ffs(seg) - 1 : lane;
             int pos0 = 0;
-            if (pass[r] && lane == leader) pos0 = atomicAdd(&a.cnt2[qid[r]], __popc(seg));
+            if (pass && lane == leader) pos0 = atomicAdd(&a.cnt2[qid[r]], __popc(seg));
             pos0 = __shfl(pos0, leader, 64);
-            if (pass[r]) {
+            if (pass) {
               const int pos = pos0 + __popc(seg & ((1u << (lane - 16 * g)) - 1u));
-              if (pos < a.cap2) a.out2[(size_t)qid[r] * a.cap2 + pos] = key[r];
+              if (pos < a.cap2) a.out2[(size_t)qid[r] * a.cap2 + pos] = key;
             }
           }
         }
@@ -3022,9 +3047,8 @@ hipError_t launch_lmajor(const DevIndex& ix, const float* q, const LaunchCfg& c,
                          c.np_max, c.qc, lw.loff, lw.lfill, lw.invq);
       return hipGetLastError();
     case 3: {  // the persistent list-major launch
-      const int KC = ix.dim_pad / 64;
-      const size_t cb_bytes = ((size_t)ix.M * kKsub * ix.dsub + 15) / 16 * 16;
-      const size_t lds = cb_bytes + (size_t)kLmG * KC * 64 + kLmG * 8 + kLmG * 4 + 8 * 4;
+      const size_t lds = (size_t)lm_cb_bytes(ix.dim_pad) + (size_t)kLmG * ix.dim_pad + kLmG * 8 +
+                         kLmG * 4 + 8 * 4;
       const LmFn kern = lm_kernel(ix);
       if (lds > 65536)
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,

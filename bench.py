@@ -112,7 +112,8 @@ def parse():
                     help="batched form: this work split instead of the autotuner's")
     ap.add_argument("--tile", type=int, default=65536, help="with --split: entries per item")
     ap.add_argument("--lm", default="",
-                    help="with --split: list-major alpha,rows,blocks instead of per-query only")
+                    help="with --split: list-major alpha,rows,blocks[,min_rows] instead of "
+                         "per-query only")
     ap.add_argument("--build-only", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
@@ -417,7 +418,7 @@ def main():
     # tuning options (none changes results): the index's defaults for the
     # plain form, the autotuner's choice for the batched form
     OPTS = (g.OPT_SCAN_TILE, g.OPT_SCAN_SPLIT, g.OPT_LIST_MAJOR, g.OPT_LM_ALPHA, g.OPT_LM_TILE,
-            g.OPT_LM_BLOCKS)
+            g.OPT_LM_BLOCKS, g.OPT_LM_MIN_ROWS)
 
     def get_opts():
         return {o: g.get_option(o) for o in OPTS}
@@ -438,11 +439,13 @@ def main():
             tuned = {"tile": args.tile, "split": args.split, "tried": 0, "ms": 0.0,
                      "list_major": 0}
             if args.lm:
-                la, lt, lb = (int(x) for x in args.lm.split(","))
+                la, lt, lb, *lmin = (int(x) for x in args.lm.split(","))
+                lmin = lmin[0] if lmin else 0
                 for o, v in ((g.OPT_LIST_MAJOR, 1), (g.OPT_LM_ALPHA, la), (g.OPT_LM_TILE, lt),
-                             (g.OPT_LM_BLOCKS, lb)):
+                             (g.OPT_LM_BLOCKS, lb), (g.OPT_LM_MIN_ROWS, lmin)):
                     g.set_option(o, v)
-                tuned.update(list_major=1, lm_alpha=la, lm_tile=lt, lm_blocks=lb)
+                tuned.update(list_major=1, lm_alpha=la, lm_tile=lt, lm_blocks=lb,
+                             lm_min_rows=lmin)
         else:
             tuned = ann.autotune(g, Q, nprobe_arg, k, n, reps=2)
         log(f"autotuned: {tuned}")
@@ -518,7 +521,8 @@ def main():
     if lm_on:
         # the list-major pass's work, from the probe lists and the same split
         # rule the kernels apply (first-list rows of each query's leading lists
-        # until alpha * n rows stay with the per-query scan)
+        # until alpha * n rows stay with the per-query scan, and those of lists
+        # shorter than min_rows)
         alpha = batched_opts[g.OPT_LM_ALPHA]
         npv = valid.sum(1)
         plen = np.where(valid, primary[lsafe], 0)
@@ -527,9 +531,11 @@ def main():
         first = np.where(reach.any(1), reach.argmax(1) + 1, lists.shape[1])
         walkp = np.minimum(first, npv)
         slot = np.arange(lists.shape[1])[None, :]
-        in2 = valid & (slot >= walkp[:, None]) & (slot < npv[:, None]) & (plen > 0)
+        min_rows = batched_opts[g.OPT_LM_MIN_ROWS]
+        in2 = valid & (slot >= walkp[:, None]) & (plen > 0) & (plen >= min_rows)
         cnt_l = np.bincount(lists[in2], minlength=len(primary))
-        groups = (cnt_l + 15) // 16
+        G = 16 if g.desc["int_grid"] else (8 if args.lut16 else 4)
+        groups = (cnt_l + G - 1) // G
         lm = {"pairs_per_step": int((plen * in2).sum()),
               "rows_distinct_per_step": int(primary[cnt_l > 0].sum()),
               "rows_read_per_step": int((groups * primary).sum()),
@@ -550,7 +556,9 @@ def main():
     else:
         # each probed list's code rows read once (M bytes a row)
         alg_bytes = lm["rows_distinct_per_step"] * M
-        kname = "k_lm_mfma (list-major decode + int8 MFMA Eq. 1 + threshold)"
+        kname = ("k_lm_mfma (list-major decode + int8 MFMA Eq. 1 + threshold)"
+                 if g.desc["int_grid"] else
+                 "k_lm_lut (list-major Eq. 1 by interleaved LDS tables + threshold)")
         extra = dict(lm)
     # bytes per launch / average launch time = bytes per step / kernel time per step
     achieved = alg_bytes / (st_ms[kern] / 1e3) / 1e9

@@ -285,7 +285,7 @@ ann_status ann_rerank(ann_index* ix, const float* d_queries, int64_t nq, const i
  * Stages: 0 probe (distances + selection), 1 distance table, 2 per-query
  * scan (planning + fused gather/dedup/Eq. 1/top-n), 3 merge + exact re-rank,
  * 4 the list-major launch (ANN_OPT_LIST_MAJOR), 5 the list-major pass's
- * bookkeeping (split, work list, per-query selection).
+ * bookkeeping (split, work list, per-query selection, overflow fallback).
  */
 typedef struct {
   double ms[6];
@@ -309,19 +309,25 @@ ann_status ann_get_profile(ann_index* ix, ann_profile* out, int reset);
  *                       (default): input order.  Measured on the uint8 10M
  *                       workload the ordered scan was slower (2.32 vs 2.11
  *                       ms), so it stays off unless chosen.
- * Batched form on integer-grid indexes (no effect on any result):
+ * Batched form, list-major (no effect on any result):
  *   ANN_OPT_LIST_MAJOR  1: searches run list-major -- the (query, probed
  *                       list) pairs of a chunk are inverted into per-list
- *                       groups of up to 16 queries, and one persistent launch
- *                       reads each probed list's code rows once per group,
- *                       decodes them and scores the group on the int8 matrix
- *                       cores (Eq. 1 equals ||q - decoded||^2 exactly there);
- *                       the replica entries and a few leading lists per query
- *                       stay with the per-query scan, which also bounds each
- *                       query's top-n.  0 (default): per-query scan only.
- *                       Applies to ann_search, ann_search_heuristic,
- *                       ann_search_topn and graphs created while it is set;
- *                       ignored on float indexes.
+ *                       groups of queries, and one persistent launch reads
+ *                       each probed list's code rows once per group.  On
+ *                       integer-grid indexes a group is up to 16 queries: the
+ *                       rows are decoded and scored on the int8 matrix cores
+ *                       (Eq. 1 equals ||q - decoded||^2 exactly there); on
+ *                       float indexes it is 4 queries (8 with
+ *                       ANN_OPT_LUT_F16) whose distance tables sit in LDS
+ *                       side by side.  The replica entries, a few leading
+ *                       lists per query and lists shorter than
+ *                       ANN_OPT_LM_MIN_ROWS stay with the per-query scan,
+ *                       which also bounds each query's top-n.  0 (default):
+ *                       per-query scan only.  Applies to ann_search,
+ *                       ann_search_heuristic, ann_search_topn and graphs
+ *                       created while it is set; ignored where the index
+ *                       is not supported (float indexes with more than 36
+ *                       subspaces).
  *   ANN_OPT_LM_ALPHA    the per-query part walks the first-list rows of the
  *                       leading probed lists until alpha * rerank_n rows, in
  *                       [1, 64] (default 2)
@@ -331,6 +337,8 @@ ann_status ann_get_profile(ann_index* ix, ann_profile* out, int reset);
  *   ANN_OPT_LM_CAP      list-major keys kept per query before it falls back
  *                       to the per-query scan, in [0, 2^20] (default 0:
  *                       min(32768, max(4096, 16 * rerank_n)))
+ *   ANN_OPT_LM_MIN_ROWS lists with fewer first-list rows are scanned per
+ *                       query, in [0, 2^30] (default 0)
  * Numeric variant (changes results, deterministically):
  *   ANN_OPT_LUT_F16     1: the distance table of Eq. 1 is held in binary16 --
  *                       each float32 entry rounded to the nearest binary16,
@@ -351,7 +359,8 @@ enum {
   ANN_OPT_LM_ALPHA = 6,
   ANN_OPT_LM_TILE = 7,
   ANN_OPT_LM_BLOCKS = 8,
-  ANN_OPT_LM_CAP = 9
+  ANN_OPT_LM_CAP = 9,
+  ANN_OPT_LM_MIN_ROWS = 10
 };
 ann_status ann_set_option(ann_index* ix, int option, int64_t value);
 ann_status ann_get_option(ann_index* ix, int option, int64_t* value);
@@ -382,10 +391,12 @@ void ann_graph_free(ann_graph* g); /* waits for its last launch; NULL is a no-op
  * queries for each candidate, `reps` timed runs each after one warm-up, and
  * keeps the one with the lowest median time, setting its options on the
  * index.  Candidates: first the per-query scan's work split (tile in {4096 ..
- * 131072, 2^30}, split in {1, 2, 4, 8, 16}, ANN_OPT_LIST_MAJOR 0); then, on
- * integer-grid indexes, the list-major form with the best split (alpha in
+ * 131072, 2^30}, split in {1, 2, 4, 8, 16}, ANN_OPT_LIST_MAJOR 0); then the
+ * list-major form with the best split: on integer-grid indexes alpha in
  * {1, 2, 4, 8}, rows per work item in {1024, 4096, 16384}, persistent blocks
- * in {2, 4, 8} per compute unit).  No option changes results.  Synchronous;
+ * in {2, 4, 8} per compute unit; on float indexes alpha in {1, 2, 8},
+ * shortest list taken in {0, 2048, 16384} rows, rows per item 16384 or
+ * whole lists, one block per compute unit.  No option changes results.  Synchronous;
  * allocates temporary outputs.  Errors: as ann_search, ANN_EINVAL for reps
  * outside [1, 100].
  */
@@ -398,6 +409,7 @@ typedef struct {
   int32_t lm_alpha;    /* ANN_OPT_LM_ALPHA */
   int32_t lm_tile;     /* ANN_OPT_LM_TILE */
   int32_t lm_blocks;   /* ANN_OPT_LM_BLOCKS */
+  int32_t lm_min_rows; /* ANN_OPT_LM_MIN_ROWS */
 } ann_tune_result;
 ann_status ann_autotune(ann_index* ix, const float* d_queries, int64_t nq, const int32_t* d_nprobe,
                         int32_t nprobe_max, int32_t k, int32_t rerank_n, int32_t reps,

@@ -52,7 +52,7 @@ class TuneResult(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int64), ("split", ctypes.c_int32), ("tried", ctypes.c_int32),
                 ("ms", ctypes.c_double), ("list_major", ctypes.c_int32),
                 ("lm_alpha", ctypes.c_int32), ("lm_tile", ctypes.c_int32),
-                ("lm_blocks", ctypes.c_int32)]
+                ("lm_blocks", ctypes.c_int32), ("lm_min_rows", ctypes.c_int32)]
 
 
 class ServerCfg(ctypes.Structure):
@@ -326,6 +326,7 @@ class Index:
     OPT_LM_TILE = 7
     OPT_LM_BLOCKS = 8
     OPT_LM_CAP = 9
+    OPT_LM_MIN_ROWS = 10
 
     def set_option(self, option: int, value: int):
         _check(lib().ann_set_option(self._h, int(option), int(value)))
@@ -390,7 +391,8 @@ def autotune(index, Q, nprobe, k: int, rerank_n: int, reps: int = 3) -> dict:
     out = {"tile": r.tile, "split": r.split, "tried": r.tried, "ms": r.ms,
            "list_major": r.list_major}
     if r.list_major:
-        out.update(lm_alpha=r.lm_alpha, lm_tile=r.lm_tile, lm_blocks=r.lm_blocks)
+        out.update(lm_alpha=r.lm_alpha, lm_tile=r.lm_tile, lm_blocks=r.lm_blocks,
+                   lm_min_rows=r.lm_min_rows)
     return out
 
 

@@ -109,6 +109,7 @@ struct ann_index {
   int64_t opt_lm_tile = 4096;
   int64_t opt_lm_blocks = 0;
   int64_t opt_lm_cap = 0;
+  int64_t opt_lm_min_rows = 0;
   int num_cu = 256;
   void* host_pages = nullptr;  // host-memory raw tier (pinned), freed with the index
   // stage timing
@@ -331,6 +332,7 @@ void lm_layout(const DevIndex& d, int qc, int np_max, int cap2, F&& take) {
   take(8, (size_t)(d.nlist + 1) * 4);               // ioff
   take(9, (size_t)qc * np_max * 4);                 // invq
   take(10, (size_t)16);                             // ctr
+  take(11, lmajor_mfma(d) ? 0 : (size_t)qc * d.M * kKsub * 4);  // lut (float indexes)
 }
 
 size_t lm_bytes(const DevIndex& d, int qc, int np_max, int cap2) {
@@ -343,7 +345,7 @@ size_t lm_bytes(const DevIndex& d, int qc, int np_max, int cap2) {
 LmWork lm_carve(const DevIndex& d, int qc, int np_max, int cap2, void* base) {
   LmWork w;
   char* p = static_cast<char*>(base);
-  void* ptr[11];
+  void* ptr[12];
   lm_layout(d, qc, np_max, cap2, [&](int i, size_t b) {
     ptr[i] = p;
     p += align_up_sz(std::max<size_t>(b, 16), 256);
@@ -359,6 +361,7 @@ LmWork lm_carve(const DevIndex& d, int qc, int np_max, int cap2, void* base) {
   w.ioff = static_cast<int32_t*>(ptr[8]);
   w.invq = static_cast<int32_t*>(ptr[9]);
   w.ctr = static_cast<int32_t*>(ptr[10]);
+  w.lut = lmajor_mfma(d) ? nullptr : static_cast<float*>(ptr[11]);
   w.cap2 = cap2;
   return w;
 }
@@ -790,14 +793,16 @@ ann_status run_chunk(ann_index* ix, Work& w, const float* q, int qc, const int32
     StageMark m(ix, 0, st);
     HIP_TRY(launch_probe(d, q, nprobe, np_max, qc, w, nullptr, w.lists, st));
   }
-  if (w.lm.walkp && lmajor_cap(ix, n) > 0) {
+  if (w.lm.thr && lmajor_cap(ix, n) > 0) {
     // batched form: per-query part, list-major pass, per-query selection;
-    // stages: per-query scans 2, the persistent launch 4, the rest 5
+    // stages: per-query part 2, the persistent launch 4, the rest (split,
+    // work list, selection, overflow fallback) 5
     LmCfg lc;
     lc.alpha = (int)ix->opt_lm_alpha;
     lc.tile_rows = (int)ix->opt_lm_tile;
     lc.blocks = (int)ix->opt_lm_blocks;
-    static const int stage_of[kLmPhases] = {5, 2, 5, 4, 5, 2};
+    lc.min_rows = (int)ix->opt_lm_min_rows;
+    static const int stage_of[kLmPhases] = {5, 2, 5, 4, 5, 5};
     for (int ph = 0; ph < kLmPhases; ++ph) {
       StageMark m(ix, stage_of[ph], st);
       HIP_TRY(launch_lmajor(d, q, c, w, w.lm, lc, ix->num_cu, ph, st));
@@ -921,6 +926,7 @@ int ann::get_opt(const ann_index* ix, int option, int64_t* v) {
     case ANN_OPT_LM_TILE: *v = ix->opt_lm_tile; return ANN_OK;
     case ANN_OPT_LM_BLOCKS: *v = ix->opt_lm_blocks; return ANN_OK;
     case ANN_OPT_LM_CAP: *v = ix->opt_lm_cap; return ANN_OK;
+    case ANN_OPT_LM_MIN_ROWS: *v = ix->opt_lm_min_rows; return ANN_OK;
     default: return ANN_EINVAL;
   }
 }
@@ -1163,6 +1169,11 @@ extern "C" ann_status ann_set_option(ann_index* ix, int option, int64_t value) {
       if (value < 0 || value > (1 << 20))
         return fail(ANN_EINVAL, "list-major capacity must be in [0, 2^20] keys");
       ix->opt_lm_cap = value;
+      return ANN_OK;
+    case ANN_OPT_LM_MIN_ROWS:
+      if (value < 0 || value > (1 << 30))
+        return fail(ANN_EINVAL, "list-major minimum rows must be in [0, 2^30]");
+      ix->opt_lm_min_rows = value;
       return ANN_OK;
     default:
       return fail(ANN_EINVAL, "unknown option %d", option);

@@ -146,9 +146,10 @@ extern "C" ann_status ann_autotune(ann_index* ix, const float* d_queries, int64_
   if (e != hipSuccess) return err(ANN_EDEVICE, "hipSetDevice", e);
   // the options this search may change, restored on error
   const int opts[] = {ANN_OPT_SCAN_TILE, ANN_OPT_SCAN_SPLIT, ANN_OPT_LIST_MAJOR, ANN_OPT_LM_ALPHA,
-                      ANN_OPT_LM_TILE, ANN_OPT_LM_BLOCKS};
-  int64_t saved[6];
-  for (int i = 0; i < 6; ++i) get_opt(ix, opts[i], &saved[i]);
+                      ANN_OPT_LM_TILE, ANN_OPT_LM_BLOCKS, ANN_OPT_LM_MIN_ROWS};
+  constexpr int kOpts = 7;
+  int64_t saved[kOpts];
+  for (int i = 0; i < kOpts; ++i) get_opt(ix, opts[i], &saved[i]);
   hipStream_t st = nullptr;
   hipEvent_t a = nullptr, b = nullptr;
   auto cleanup = [&]() {
@@ -204,38 +205,50 @@ extern "C" ann_status ann_autotune(ann_index* ix, const float* d_queries, int64_
     }
     if (s != ANN_OK) break;
   }
-  // 2. list-major (integer-grid indexes): its split of each query, rows per
-  //    work item and number of persistent blocks, with the best split above
+  // 2. list-major: its split of each query (alpha, shortest list taken),
+  //    rows per work item and persistent blocks, with the best split above
   if (s == ANN_OK && lmajor_supported(index_dev(ix))) {
-    {
-      ann_set_option(ix, ANN_OPT_SCAN_TILE, best.tile);
-      ann_set_option(ix, ANN_OPT_SCAN_SPLIT, best.split);
-      ann_set_option(ix, ANN_OPT_LIST_MAJOR, 1);
-      int cu = 256;
-      (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, index_device(ix));
-      const int64_t ncu = std::max(1, cu);
+    ann_set_option(ix, ANN_OPT_SCAN_TILE, best.tile);
+    ann_set_option(ix, ANN_OPT_SCAN_SPLIT, best.split);
+    ann_set_option(ix, ANN_OPT_LIST_MAJOR, 1);
+    int cu = 256;
+    (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, index_device(ix));
+    const int64_t ncu = std::max(1, cu);
+    struct LmCand {
+      int alpha, rows, min_rows;
+      int64_t blocks;
+    };
+    std::vector<LmCand> lm;
+    if (lmajor_mfma(index_dev(ix))) {  // int8 MFMA groups of 16 (several blocks per CU fit)
       for (int alpha : {1, 2, 4, 8})
         for (int rows : {1024, 4096, 16384})
-          for (int64_t blocks : {2 * ncu, 4 * ncu, 8 * ncu}) {
-            ann_set_option(ix, ANN_OPT_LM_ALPHA, alpha);
-            ann_set_option(ix, ANN_OPT_LM_TILE, rows);
-            ann_set_option(ix, ANN_OPT_LM_BLOCKS, blocks);
-            double med = 0;
-            if ((s = time_it(&med)) != ANN_OK) break;
-            ++tried;
-            if (med < best.ms) {
-              best.list_major = 1;
-              best.lm_alpha = alpha;
-              best.lm_tile = rows;
-              best.lm_blocks = (int32_t)blocks;
-              best.ms = med;
-            }
-          }
+          for (int64_t blocks : {2 * ncu, 4 * ncu, 8 * ncu}) lm.push_back({alpha, rows, 0, blocks});
+    } else {  // tables in LDS: one block per CU; short lists stay per query
+      for (int alpha : {1, 2, 8})
+        for (int min_rows : {0, 2048, 16384})
+          for (int rows : {16384, 1 << 24}) lm.push_back({alpha, rows, min_rows, ncu});
+    }
+    for (const LmCand& cd : lm) {
+      ann_set_option(ix, ANN_OPT_LM_ALPHA, cd.alpha);
+      ann_set_option(ix, ANN_OPT_LM_TILE, cd.rows);
+      ann_set_option(ix, ANN_OPT_LM_BLOCKS, cd.blocks);
+      ann_set_option(ix, ANN_OPT_LM_MIN_ROWS, cd.min_rows);
+      double med = 0;
+      if ((s = time_it(&med)) != ANN_OK) break;
+      ++tried;
+      if (med < best.ms) {
+        best.list_major = 1;
+        best.lm_alpha = cd.alpha;
+        best.lm_tile = cd.rows;
+        best.lm_blocks = (int32_t)cd.blocks;
+        best.lm_min_rows = cd.min_rows;
+        best.ms = med;
+      }
     }
   }
   cleanup();
   if (s != ANN_OK) {
-    for (int i = 0; i < 6; ++i) ann_set_option(ix, opts[i], saved[i]);
+    for (int i = 0; i < kOpts; ++i) ann_set_option(ix, opts[i], saved[i]);
     return s;
   }
   ann_set_option(ix, ANN_OPT_SCAN_TILE, best.tile);
@@ -245,6 +258,7 @@ extern "C" ann_status ann_autotune(ann_index* ix, const float* d_queries, int64_
     ann_set_option(ix, ANN_OPT_LM_ALPHA, best.lm_alpha);
     ann_set_option(ix, ANN_OPT_LM_TILE, best.lm_tile);
     ann_set_option(ix, ANN_OPT_LM_BLOCKS, best.lm_blocks);
+    ann_set_option(ix, ANN_OPT_LM_MIN_ROWS, best.lm_min_rows);
   }
   best.tried = tried;
   *out = best;

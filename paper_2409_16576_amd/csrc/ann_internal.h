@@ -73,6 +73,7 @@ struct LmWork {
   int32_t* ioff = nullptr;            // [nlist + 1] work items per list (prefix)
   int32_t* invq = nullptr;            // [qc * np_max] queries by list
   int32_t* ctr = nullptr;             // [4] work items, next item
+  float* lut = nullptr;               // [qc, M, 256] distance tables (float indexes)
   int cap2 = 0;
 };
 
@@ -80,7 +81,8 @@ struct LmWork {
 struct LmCfg {
   int alpha = 2;          // the per-query part walks leading lists up to alpha * n rows
   int tile_rows = 4096;   // first-list rows per work item
-  int blocks = 0;         // persistent blocks (0: 4 per compute unit)
+  int blocks = 0;         // persistent blocks (0: per compute unit, 4 (MFMA) or 1 (tables))
+  int min_rows = 0;       // lists with fewer first-list rows stay with the per-query part
 };
 
 // Per-call working buffers (one block of the memory pool).
@@ -133,6 +135,7 @@ constexpr int kHostMaxRerank = 2048;  // largest rerank_n with the host-memory r
 // Batched form on integer-grid indexes: after launch_probe, in place of
 // launch_scan (same outputs for launch_merge, one item per query).
 bool lmajor_supported(const DevIndex& ix);
+bool lmajor_mfma(const DevIndex& ix);  // integer-grid form (else table lookups)
 int lmajor_cap2(int n);
 // Phases, in order: 0 split and counters, 1 per-query part, 2 work list,
 // 3 persistent list-major launch, 4 per-query selection, 5 overflow fallback.

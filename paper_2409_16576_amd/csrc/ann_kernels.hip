@@ -804,23 +804,31 @@ __device__ __forceinline__ int scan_compact(uint64_t* s_buf, int* s_wsum, SelScr
 constexpr uint32_t kRunReplica = 0x80000000u;  // run start flag: replica-entry run
 
 // Splitting a query's entries between the per-query scan and the list-major
-// pass of the batched form (all null: the whole query here).
-//   walkp    [qc] first-list rows are walked only for probed slots < walkp[q]
-//            (replica entries of every probed list are always walked here)
+// pass of the batched form (defaults: the whole query here).
+//   walkp    [qc] probed slots >= walkp[q] leave the first-list rows of their
+//            lists (those with at least min_rows of them) to the list-major
+//            pass; replica entries of every probed list are walked here
 //   active   [qc] nonzero: scan this query; zero: the block does nothing
 //   thr_out  [qc] atomically lowered to each item's n-th smallest key
 struct ScanSplit {
   const int32_t* walkp = nullptr;
   const uint8_t* active = nullptr;
   unsigned long long* thr_out = nullptr;
+  int min_rows = 0;
 };
+
+// Whether probed slot p of a query (list with `rows` first-list rows) leaves
+// those rows to the list-major pass.
+__host__ __device__ inline bool lm_slot(int p, int walkp, int rows, int min_rows) {
+  return p >= walkp && rows > 0 && rows >= min_rows;
+}
 
 // Runs of up to 64 probed lists laid out by one wave (lane p: list p): run
 // starts in s_rstart, exclusive entry offsets in s_pre[0..nruns], and
 // s_pre[nruns] = the query's entries; *s_nruns = nruns.
 __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_list, int np,
-                          int walk_np, const uint32_t* s_bits, int segmented, int max_runs,
-                          uint32_t* s_rstart, int32_t* s_pre, int* s_nruns) {
+                          int walk_np, int min_rows, const uint32_t* s_bits, int segmented,
+                          int max_runs, uint32_t* s_rstart, int32_t* s_pre, int* s_nruns) {
   const int lane = threadIdx.x & 63;
   int cnt = 0, l = 0, s0 = 0, s1 = 0;
   if (lane < np) {
@@ -845,9 +853,10 @@ __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_l
   if (lane < np) {
     const int off = incl - cnt;
     s_rstart[off] = (uint32_t)ix.pstart[l];
-    // entry counts first; the first-list rows of slots >= walk_np are left to
-    // the list-major pass (an empty run)
-    s_pre[off] = lane < walk_np ? ix.pstart[l + 1] - ix.pstart[l] : 0;
+    // entry counts first; first-list rows left to the list-major pass make an
+    // empty run
+    const int rows = ix.pstart[l + 1] - ix.pstart[l];
+    s_pre[off] = lm_slot(lane, walk_np, rows, min_rows) ? 0 : rows;
     int r = off + 1;
     if (seg) {
       for (int s = s0; s < s1; ++s) {
@@ -931,7 +940,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   if (use_bits)
     for (int i = tid; i < nwords; i += kScanBlock) s_bits[i] = 0u;
   const int np = np_eff[q];
-  const int walk_np = sp.walkp ? min(np, sp.walkp[q]) : np;  // slots whose first-list rows are walked
+  const int walk_np = sp.walkp ? min(np, sp.walkp[q]) : np;  // slots walked whole
   for (int p = tid; p < np; p += kScanBlock) s_list[p] = lists[(size_t)q * np_max + p];
   if (tid == 0) {
     mc->thr = ~0ull;
@@ -1008,8 +1017,8 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   const bool wave_setup = np <= 64;
   if (wave_setup) {
     if (tid < 64) {
-      runs_wave(ix, s_list, np, walk_np, s_bits, segmented, max_runs, s_rstart, s_pre,
-                &s_wsum[kScanBlock / 64]);
+      runs_wave(ix, s_list, np, walk_np, sp.min_rows, s_bits, segmented, max_runs, s_rstart,
+                s_pre, &s_wsum[kScanBlock / 64]);
     } else {
       build_table(tid - 64, kScanBlock - 64);
     }
@@ -1050,8 +1059,10 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     const int off = nruns + block_excl_scan(cnt, s_wsum);
     if (p < np) {
       s_rstart[off] = (uint32_t)ix.pstart[l];
-      // entry count, turned into offsets below (empty past walk_np, as in runs_wave)
-      s_pre[off] = p < walk_np ? ix.pstart[l + 1] - ix.pstart[l] : 0;
+      // entry count, turned into offsets below (empty when left to the
+      // list-major pass, as in runs_wave)
+      const int rows = ix.pstart[l + 1] - ix.pstart[l];
+      s_pre[off] = lm_slot(p, walk_np, rows, sp.min_rows) ? 0 : rows;
       int r = off + 1;
       if (seg) {
         for (int s = ix.lseg[l]; s < ix.lseg[l + 1]; ++s) {
@@ -2390,10 +2401,12 @@ struct LmArgs {
   int cap2;
   int32_t* ctr;          // [0] work items, [1] next item
   int tile_rows;
+  int group;             // queries per group
 };
 
-// Per query: the first probed slot whose first-list rows go to the
-// list-major pass (the leading slots hold >= need rows, or all slots).
+// Per query: the first probed slot whose first-list rows may go to the
+// list-major pass (the leading slots hold >= need rows, or all slots); its
+// bound (none yet) and counters; per-list counters; the item counters.
 __global__ void k_lm_prep(DevIndex ix, const int32_t* __restrict__ lists,
                           const int32_t* __restrict__ np_eff, int np_max, int qc, int64_t need,
                           int32_t* __restrict__ walkp, unsigned long long* __restrict__ thr,
@@ -2428,38 +2441,39 @@ __global__ void k_lm_prep(DevIndex ix, const int32_t* __restrict__ lists,
 // (query, slot) pairs of the list-major pass: count per list, then fill.
 __device__ __forceinline__ int lm_pair_list(const DevIndex& ix, const int32_t* lists,
                                             const int32_t* np_eff, const int32_t* walkp,
-                                            int np_max, int qc, int i, int* q_out) {
+                                            int np_max, int qc, int min_rows, int i, int* q_out) {
   const int q = i / np_max, p = i % np_max;
-  if (q >= qc || p >= np_eff[q] || p < walkp[q]) return -1;
+  if (q >= qc || p >= np_eff[q]) return -1;
   const int l = lists[(size_t)q * np_max + p];
-  if (ix.pstart[l + 1] == ix.pstart[l]) return -1;
+  if (!lm_slot(p, walkp[q], ix.pstart[l + 1] - ix.pstart[l], min_rows)) return -1;
   *q_out = q;
   return l;
 }
 
 __global__ void k_lm_count(DevIndex ix, const int32_t* __restrict__ lists,
                            const int32_t* __restrict__ np_eff, const int32_t* __restrict__ walkp,
-                           int np_max, int qc, int32_t* __restrict__ lcnt) {
+                           int np_max, int qc, int min_rows, int32_t* __restrict__ lcnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int q;
-  const int l = lm_pair_list(ix, lists, np_eff, walkp, np_max, qc, i, &q);
+  const int l = lm_pair_list(ix, lists, np_eff, walkp, np_max, qc, min_rows, i, &q);
   if (l >= 0) atomicAdd(&lcnt[l], 1);
 }
 
 __global__ void k_lm_fill(DevIndex ix, const int32_t* __restrict__ lists,
                           const int32_t* __restrict__ np_eff, const int32_t* __restrict__ walkp,
-                          int np_max, int qc, const int32_t* __restrict__ loff,
+                          int np_max, int qc, int min_rows, const int32_t* __restrict__ loff,
                           int32_t* __restrict__ lfill, int32_t* __restrict__ invq) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int q;
-  const int l = lm_pair_list(ix, lists, np_eff, walkp, np_max, qc, i, &q);
+  const int l = lm_pair_list(ix, lists, np_eff, walkp, np_max, qc, min_rows, i, &q);
   if (l >= 0) invq[loff[l] + atomicAdd(&lfill[l], 1)] = q;
 }
 
 // One block: per-list query offsets and work-item offsets (exclusive prefix
 // sums; each thread sums a contiguous run of lists), and the item count.
 __global__ __launch_bounds__(1024) void k_lm_offsets(DevIndex ix, const int32_t* __restrict__ lcnt,
-                                                     int tile_rows, int32_t* __restrict__ loff,
+                                                     int tile_rows, int group,
+                                                     int32_t* __restrict__ loff,
                                                      int32_t* __restrict__ ioff,
                                                      int32_t* __restrict__ ctr) {
   __shared__ int s_a[17], s_b[17];
@@ -2469,7 +2483,7 @@ __global__ __launch_bounds__(1024) void k_lm_offsets(DevIndex ix, const int32_t*
   auto items = [&](int l, int c) {
     if (c == 0) return 0;
     const int len = ix.pstart[l + 1] - ix.pstart[l];
-    return ((c + kLmG - 1) / kLmG) * ((len + tile_rows - 1) / tile_rows);
+    return ((c + group - 1) / group) * ((len + tile_rows - 1) / tile_rows);
   };
   int sa = 0, sb = 0;
   for (int l = l0; l < l1; ++l) {
@@ -2491,6 +2505,27 @@ __global__ __launch_bounds__(1024) void k_lm_offsets(DevIndex ix, const int32_t*
     ioff[ix.nlist] = b;
     ctr[0] = b;
   }
+}
+
+// Work item `it`: its list (largest l with ioff[l] <= it), query group and
+// row tile -> s_it[1..4] = queries in the group, first row, end row, first
+// slot of the group in invq.  Groups of one tile are adjacent items.
+__device__ __forceinline__ void lm_item(const DevIndex& ix, const LmArgs& a, int it, int G,
+                                        int* s_it) {
+  int lo = 0, hi = ix.nlist - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.ioff[mid] <= it) lo = mid;
+    else hi = mid - 1;
+  }
+  const int l = lo, local = it - a.ioff[l], nql = a.lcnt[l];
+  const int ng = (nql + G - 1) / G;
+  const int grp = local % ng, tile = local / ng;
+  const int r0 = ix.pstart[l] + tile * a.tile_rows;
+  s_it[1] = min(G, nql - grp * G);
+  s_it[2] = r0;
+  s_it[3] = min(ix.pstart[l + 1], r0 + a.tile_rows);
+  s_it[4] = a.loff[l] + grp * G;
 }
 
 // The code dwords a lane needs for K chunk kc of a row: codes (kc*64 + 16g)/DS
@@ -2609,20 +2644,7 @@ __global__ __launch_bounds__(kLmBlock) void k_lm_mfma(DevIndex ix, const float* 
       const int it = atomicAdd(&a.ctr[1], 1);
       s_it[0] = it;
       if (it < nitems) {
-        int lo = 0, hi = ix.nlist - 1;  // the list: largest l with ioff[l] <= it
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (a.ioff[mid] <= it) lo = mid;
-          else hi = mid - 1;
-        }
-        const int l = lo, local = it - a.ioff[l], nql = a.lcnt[l];
-        const int ng = (nql + kLmG - 1) / kLmG;
-        const int grp = local % ng, tile = local / ng;  // groups of one tile adjacent
-        const int r0 = ix.pstart[l] + tile * a.tile_rows;
-        s_it[1] = min(kLmG, nql - grp * kLmG);
-        s_it[2] = r0;
-        s_it[3] = min(ix.pstart[l + 1], r0 + a.tile_rows);
-        s_it[4] = a.loff[l] + grp * kLmG;
+        lm_item(ix, a, it, kLmG, s_it);
       }
     }
     __syncthreads();
@@ -2731,12 +2753,153 @@ __global__ __launch_bounds__(kLmBlock) void k_lm_mfma(DevIndex ix, const float* 
   }
 }
 
+// The persistent list-major kernel for float indexes: Eq. 1 by table
+// lookups, as in the per-query scan.  The group's G distance tables (taken
+// from the chunk's table buffer) are staged in LDS interleaved by query --
+// entry (m, j) of the G queries is one 16-byte word: G = 4 float32 entries,
+// or G = 8 binary16 entries in the half-precision variant -- so each code of
+// a row is one LDS read for the whole group.  A thread scores kLutU rows per
+// round for all G queries, each sum in float32 over m = 0..M-1 from +0.0f
+// (the per-query scan's order, hence its bits).
+constexpr int kLutBlock = 1024;  // threads per block (one block per CU: tables take most of LDS)
+constexpr int kLutU = 2;         // rows per thread and round
+constexpr int kLutMaxW = 9;      // up to 36 subspaces (4 * 9 * 256 * 16 bytes of tables)
+
+template <int W, bool H>
+__global__ __launch_bounds__(kLutBlock) void k_lm_lut(DevIndex ix, const float* __restrict__ lut,
+                                                      LmArgs a) {
+  constexpr int G = H ? 8 : 4;
+  constexpr int MS = 4 * W;  // table subspaces (those past M unused)
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint4* s_t = reinterpret_cast<uint4*>(smem);  // [MS * 256]
+  unsigned long long* s_thr = reinterpret_cast<unsigned long long*>(smem + MS * kKsub * 16);
+  int* s_qid = reinterpret_cast<int*>(s_thr + G);  // [G]
+  int* s_it = s_qid + G;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int M = ix.M;
+  const uint64_t lanemask = (1ull << lane) - 1ull;
+  const int nitems = a.ctr[0];
+  for (;;) {
+    if (tid == 0) {
+      const int it = atomicAdd(&a.ctr[1], 1);
+      s_it[0] = it;
+      if (it < nitems) lm_item(ix, a, it, G, s_it);
+    }
+    __syncthreads();
+    if (s_it[0] >= nitems) break;  // block-uniform
+    const int gcnt = s_it[1], row0 = s_it[2], row1 = s_it[3], qbase = s_it[4];
+    if (tid < G) {
+      const int qid = tid < gcnt ? a.invq[qbase + tid] : -1;
+      s_qid[tid] = qid;
+      s_thr[tid] = qid >= 0 ? a.thr[qid] : 0ull;  // 0: an empty slot never passes
+    }
+    __syncthreads();
+    int qid[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) qid[g] = s_qid[g];
+    for (int i = tid; i < M * kKsub; i += kLutBlock) {  // the group's tables, interleaved
+      float v[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) v[g] = qid[g] >= 0 ? lut[(size_t)qid[g] * M * kKsub + i] : 0.f;
+      uint4 wv;
+      if constexpr (H) {  // nearest binary16, ties to even (as the per-query scan's variant)
+        uint32_t hw[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+          hw[d] = (uint32_t)__half_as_ushort(__float2half_rn(v[2 * d])) |
+                  ((uint32_t)__half_as_ushort(__float2half_rn(v[2 * d + 1])) << 16);
+        wv = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+      } else {
+        wv = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                        __float_as_uint(v[3]));
+      }
+      s_t[i] = wv;
+    }
+    unsigned long long th[G];
+    uint32_t th_hi[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      th[g] = s_thr[g];
+      th_hi[g] = (uint32_t)(th[g] >> 32);
+    }
+    __syncthreads();
+    for (int base = row0; base < row1; base += kLutBlock * kLutU) {  // uniform trip count
+      uint32_t cw[kLutU][W];
+      uint32_t ext[kLutU];
+      int rr[kLutU];
+#pragma unroll
+      for (int u = 0; u < kLutU; ++u) {
+        const int row = base + u * kLutBlock + tid;
+        rr[u] = row < row1 ? row : row0;
+        ext[u] = (uint32_t)ix.row2ext[rr[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kLutU; ++u) load_row<W>(ix.codes + (size_t)rr[u] * ix.row_bytes, cw[u]);
+#pragma unroll
+      for (int u = 0; u < kLutU; ++u) asm volatile("" ::"v"(ext[u]));
+#pragma unroll
+      for (int u = 0; u < kLutU; ++u) {
+        const bool rv = base + u * kLutBlock + tid < row1;
+        float acc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] = 0.f;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int m = 4 * i + b;
+            if (i < W - 1 || m < M) {
+              const uint4 e = s_t[m * kKsub + ((cw[u][i] >> (8 * b)) & 255u)];
+              const uint32_t ew[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+              for (int g = 0; g < G; ++g) {
+                float x;
+                if constexpr (H)
+                  x = __half2float(__ushort_as_half((unsigned short)(ew[g >> 1] >> (16 * (g & 1)))));
+                else
+                  x = __uint_as_float(ew[g]);
+                acc[g] = acc[g] + x;
+              }
+            }
+          }
+        }
+        uint32_t h[G];
+        bool c = false;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          h[g] = ord32(acc[g]);
+          c = c || h[g] <= th_hi[g];
+        }
+        if (__ballot(c) == 0) continue;  // wave-uniform: no key can pass
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const uint64_t key = ((uint64_t)h[g] << 32) | ext[u];
+          const bool pass = rv && key < th[g];
+          const uint64_t m = __ballot(pass);
+          if (m) {  // wave-uniform: one atomic per query and wave
+            int pos0 = 0;
+            if (lane == __ffsll((unsigned long long)m) - 1)
+              pos0 = atomicAdd(&a.cnt2[qid[g]], __popcll(m));
+            pos0 = __shfl(pos0, __ffsll((unsigned long long)m) - 1, 64);
+            if (pass) {
+              const int pos = pos0 + __popcll(m & lanemask);
+              if (pos < a.cap2) a.out2[(size_t)qid[g] * a.cap2 + pos] = key;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();  // the next item restages the tables
+  }
+}
+
 // Per query: the n smallest of the per-query scan's item keys and the
 // list-major keys, into item 0 (sq = 1), with the work counts; a query whose
 // list-major area overflowed is flagged for a full per-query scan instead.
 __global__ __launch_bounds__(kBlock) void k_lm_select(
     DevIndex ix, const int32_t* __restrict__ lists, const int32_t* __restrict__ np_eff,
-    int np_max, const int32_t* __restrict__ walkp, int smax, int n, uint64_t* __restrict__ pkeys,
+    int np_max, const int32_t* __restrict__ walkp, int min_rows, int smax, int n,
+    uint64_t* __restrict__ pkeys,
     int32_t* __restrict__ pcount, int32_t* __restrict__ pscan, int32_t* __restrict__ sq,
     const int32_t* __restrict__ cnt2, const uint64_t* __restrict__ out2, int cap2,
     uint8_t* __restrict__ flag) {
@@ -2762,12 +2925,14 @@ __global__ __launch_bounds__(kBlock) void k_lm_select(
     const int incl = (int)wave_incl_scan((uint32_t)c);
     if (tid < S) s_off[tid] = incl - c;
     if (tid == S - 1) s_off[S] = incl;
-    const int np = np_eff[q];
-    for (int p = min(np, walkp[q]) + tid; p < np; p += 64) {  // rows of the list-major part
+    const int np = np_eff[q], wp = walkp[q];
+    for (int p = min(np, wp) + tid; p < np; p += 64) {  // rows of the list-major part
       const int l = lists[(size_t)q * np_max + p];
       const int r = ix.pstart[l + 1] - ix.pstart[l];
-      sc += r;
-      sw += r;
+      if (lm_slot(p, wp, r, min_rows)) {
+        sc += r;
+        sw += r;
+      }
     }
 #pragma unroll
     for (int d = 32; d > 0; d >>= 1) {
@@ -2985,11 +3150,18 @@ namespace ann {
 // ---------------------------------------------------------------------------
 // Batched form: the list-major pass (see k_lm_mfma).
 
-bool lmajor_supported(const DevIndex& ix) {
+// Integer-grid indexes: decode + int8 MFMA (k_lm_mfma); float indexes:
+// interleaved tables (k_lm_lut).
+bool lmajor_mfma(const DevIndex& ix) {
   return ix.int_grid && ix.cb8 && ix.cent8 &&
-         (ix.dsub == 1 || ix.dsub == 2 || ix.dsub == 4 || ix.dsub == 8) && ix.dim_pad <= 256 &&
-         (size_t)ix.M * kKsub * ix.dsub <= 64 * 1024;
+         (ix.dsub == 1 || ix.dsub == 2 || ix.dsub == 4 || ix.dsub == 8) && ix.dim_pad <= 256;
 }
+
+bool lmajor_supported(const DevIndex& ix) {
+  return lmajor_mfma(ix) || (!ix.int_grid && (ix.M + 3) / 4 <= kLutMaxW);
+}
+
+int lmajor_group(const DevIndex& ix, bool lut16) { return lmajor_mfma(ix) ? kLmG : lut16 ? 8 : 4; }
 
 int lmajor_cap2(int n) { return std::min(32768, std::max(4096, 16 * n)); }
 
@@ -3005,6 +3177,19 @@ LmFn lm_kernel_ds(int ds) {
     case 4: return k_lm_mfma<KC, 4>;
     default: return k_lm_mfma<KC, 8>;
   }
+}
+
+using LutFn = void (*)(DevIndex, const float*, LmArgs);
+
+template <int... Ws>
+constexpr LutFn lut_kernel_entry(int w, bool h, std::integer_sequence<int, Ws...>) {
+  LutFn f = nullptr;
+  ((f = (w == Ws + 1) ? (h ? k_lm_lut<Ws + 1, true> : k_lm_lut<Ws + 1, false>) : f), ...);
+  return f;
+}
+
+LutFn lut_kernel(const DevIndex& ix, bool h) {
+  return lut_kernel_entry((ix.M + 3) / 4, h, std::make_integer_sequence<int, kLutMaxW>{});
 }
 
 LmFn lm_kernel(const DevIndex& ix) {
@@ -3034,29 +3219,48 @@ hipError_t launch_lmajor(const DevIndex& ix, const float* q, const LaunchCfg& c,
                          lw.cnt2, lw.flag, lw.lcnt, lw.lfill, lw.ctr);
       return hipGetLastError();
     }
-    case 1:  // per-query part: leading lists' first-list rows, every replica entry
+    case 1: {  // per-query part: leading lists, short lists, replica entries; the bound
+      ScanSplit sp;
+      sp.walkp = lw.walkp;
+      sp.thr_out = lw.thr;
+      sp.min_rows = lc.min_rows;
       return scan_fn(W)(ix, w.lists, w.np_eff, c.np_max, c.qc, q, nullptr, w.sq, c.smax, c.tile,
                         c.n, cap, w.pkeys, w.pcount, w.pscan, nullptr, false, c.lut16, 0, nullptr,
-                        nullptr, nullptr, ScanSplit{lw.walkp, nullptr, lw.thr}, st);
-    case 2:  // the work list
+                        nullptr, nullptr, sp, st);
+    }
+    case 2: {  // the work list
+      const int G = lmajor_group(ix, c.lut16);
       hipLaunchKernelGGL(k_lm_count, gp, dim3(256), 0, st, ix, w.lists, w.np_eff, lw.walkp,
-                         c.np_max, c.qc, lw.lcnt);
-      hipLaunchKernelGGL(k_lm_offsets, dim3(1), dim3(1024), 0, st, ix, lw.lcnt, lc.tile_rows,
+                         c.np_max, c.qc, lc.min_rows, lw.lcnt);
+      hipLaunchKernelGGL(k_lm_offsets, dim3(1), dim3(1024), 0, st, ix, lw.lcnt, lc.tile_rows, G,
                          lw.loff, lw.ioff, lw.ctr);
       hipLaunchKernelGGL(k_lm_fill, gp, dim3(256), 0, st, ix, w.lists, w.np_eff, lw.walkp,
-                         c.np_max, c.qc, lw.loff, lw.lfill, lw.invq);
+                         c.np_max, c.qc, lc.min_rows, lw.loff, lw.lfill, lw.invq);
       return hipGetLastError();
+    }
     case 3: {  // the persistent list-major launch
-      const size_t lds = (size_t)lm_cb_bytes(ix.dim_pad) + (size_t)kLmG * ix.dim_pad + kLmG * 8 +
-                         kLmG * 4 + 8 * 4;
-      const LmFn kern = lm_kernel(ix);
-      if (lds > 65536)
-        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-      const int blocks = lc.blocks > 0 ? lc.blocks : 4 * std::max(1, num_cu);
+      const int G = lmajor_group(ix, c.lut16);
       LmArgs a{lw.loff, lw.ioff, lw.lcnt, lw.invq, lw.thr, lw.cnt2, lw.out2, lw.cap2, lw.ctr,
-               lc.tile_rows};
-      hipLaunchKernelGGL(kern, dim3(blocks), dim3(kLmBlock), lds, st, ix, q, a);
+               lc.tile_rows, G};
+      if (lmajor_mfma(ix)) {
+        const size_t lds = (size_t)lm_cb_bytes(ix.dim_pad) + (size_t)kLmG * ix.dim_pad +
+                           kLmG * 8 + kLmG * 4 + 8 * 4;
+        const LmFn kern = lm_kernel(ix);
+        if (lds > 65536)
+          (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds);
+        const int blocks = lc.blocks > 0 ? lc.blocks : 4 * std::max(1, num_cu);
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(kLmBlock), lds, st, ix, q, a);
+        return hipGetLastError();
+      }
+      // float index: the chunk's tables, then the table-lookup kernel
+      hipLaunchKernelGGL(k_lut, dim3(c.qc), dim3(kBlock), 0, st, ix, q, c.qc, lw.lut);
+      const size_t lds = (size_t)4 * ((ix.M + 3) / 4) * kKsub * 16 + G * 8 + G * 4 + 8 * 4;
+      const LutFn kern = lut_kernel(ix, c.lut16);
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+      const int blocks = lc.blocks > 0 ? lc.blocks : std::max(1, num_cu);
+      hipLaunchKernelGGL(kern, dim3(blocks), dim3(kLutBlock), lds, st, ix, lw.lut, a);
       return hipGetLastError();
     }
     case 4: {  // both parts' n best per query
@@ -3065,14 +3269,17 @@ hipError_t launch_lmajor(const DevIndex& ix, const float* q, const LaunchCfg& c,
         (void)hipFuncSetAttribute((const void*)k_lm_select,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_sel);
       hipLaunchKernelGGL(k_lm_select, dim3(c.qc), dim3(kBlock), lds_sel, st, ix, w.lists,
-                         w.np_eff, c.np_max, lw.walkp, c.smax, c.n, w.pkeys, w.pcount, w.pscan,
-                         w.sq, lw.cnt2, lw.out2, lw.cap2, lw.flag);
+                         w.np_eff, c.np_max, lw.walkp, lc.min_rows, c.smax, c.n, w.pkeys,
+                         w.pcount, w.pscan, w.sq, lw.cnt2, lw.out2, lw.cap2, lw.flag);
       return hipGetLastError();
     }
-    default:  // queries whose list-major output overflowed: the whole query per query
+    default: {  // queries whose list-major output overflowed: the whole query per query
+      ScanSplit sp;
+      sp.active = lw.flag;
       return scan_fn(W)(ix, w.lists, w.np_eff, c.np_max, c.qc, q, nullptr, w.sq, c.smax, c.tile,
                         c.n, cap, w.pkeys, w.pcount, w.pscan, nullptr, false, c.lut16, 0, nullptr,
-                        nullptr, nullptr, ScanSplit{nullptr, lw.flag, nullptr}, st);
+                        nullptr, nullptr, sp, st);
+    }
   }
 }
 

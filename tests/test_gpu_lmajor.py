@@ -1,9 +1,10 @@
 """List-major batched search (ANN_OPT_LIST_MAJOR) through the C ABI.
 
-On integer-grid indexes the batched form inverts a chunk's (query, probed
-list) pairs into per-list query groups and scores each list's code rows once
-per group on the int8 matrix cores, leaving the replica entries and a few
-leading lists per query to the per-query scan.  Every result -- final IDs and
+The batched form inverts a chunk's (query, probed list) pairs into per-list
+query groups and scores each list's code rows once per group -- on the int8
+matrix cores for integer-grid indexes, by interleaved LDS tables (float32 or
+binary16) for float indexes -- leaving the replica entries, short lists and a
+few leading lists per query to the per-query scan.  Every result -- final IDs and
 distances, the top-n with its Eq. 1 values, the candidate counts, the
 heuristic re-ranking -- must equal the plain per-query form's and the CPU
 oracle's bit for bit, whatever the tuning (alpha, rows per work item, number
@@ -21,6 +22,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 OPT_LIST_MAJOR, OPT_LM_ALPHA, OPT_LM_TILE, OPT_LM_BLOCKS, OPT_LM_CAP = 5, 6, 7, 8, 9
+OPT_LUT_F16, OPT_LM_MIN_ROWS = 3, 10
 
 
 def _say(*a):
@@ -188,16 +190,100 @@ def test_list_major_graph_and_heuristic(ann, setup, orc, name):
     assert np.array_equal(h_rr.cpu().numpy().astype(np.int64), rh.reranked)
 
 
-def test_list_major_ignored_on_float_indexes(ann, tmp_path, orc):
-    X = fx.mixture(91, 5000, 32, "f32", n_centres=8)
-    p, _ = fx.built(tmp_path, "f32", X, "f32", nlist=32, M=8)
-    g = ann.Index(p, 0)
-    try:
-        Qh = fx.mixture(92, 40, 32, "f32", n_centres=8).astype(np.float32)
-        _set_lm(g, True)
-        ids, d = g.search(_cuda(Qh), 8, 10, 100)
-        torch.cuda.synchronize()
-        r = orc.search(orc.read_index(p), Qh, 8, 10, 100)
-        assert np.array_equal(ids.cpu().numpy(), r.ids) and np.array_equal(d.cpu().numpy(), r.dists)
-    finally:
+@pytest.fixture(scope="module")
+def fsetup(tmp_path_factory, orc, ann):
+    """Float indexes: R = 3 (64-d, M 16), 96-d M 24 with empty lists, 30-d M 10
+    (3-d subspaces), and a Zipf-skewed unit-norm index (one list holds a large
+    share of the vectors; per-query nprobe U{8..128})."""
+    from paper_2409_16576_amd import workloads
+    d = tmp_path_factory.mktemp("lmf")
+    out = {}
+
+    def add(name, path, Q, npq=None):
+        out[name] = (orc.read_index(path), ann.Index(path, 0), Q.astype(np.float32), npq)
+
+    X = fx.mixture(93, 15000, 64, "f32", n_centres=12)
+    add("f32r3", fx.built(d, "f32r3", X, "f32", nlist=48, M=16, R=3, eps=0.25)[0],
+        fx.mixture(94, 200, 64, "f32", n_centres=12))
+    X = fx.mixture(95, 6000, 96, "f32", n_centres=4)
+    add("f32m24", fx.built(d, "f32m24", X, "f32", nlist=96, M=24)[0],
+        fx.mixture(96, 160, 96, "f32", n_centres=4))
+    X = fx.mixture(97, 8000, 30, "f32", n_centres=8)
+    add("f32d30", fx.built(d, "f32d30", X, "f32", nlist=32, M=10)[0],
+        fx.mixture(98, 130, 30, "f32", n_centres=8))
+    w = workloads.scaled(workloads.ZIPF_F32_5M, n=40000, nlist=64, n_centres=16, nq=300)
+    add("zipf", workloads.ensure_index(w), workloads.queries(w), workloads.nprobe_per_query(w))
+    yield out
+    for _, g, _, _ in out.values():
         g.close()
+
+
+FNAMES = ["f32r3", "f32m24", "f32d30", "zipf"]
+FTUNINGS = [(2, 4096, 0, 0), (1, 1 << 24, 0, 0), (8, 256, 3, 500), (1, 64, 1, 3000)]
+
+
+@pytest.mark.parametrize("name", FNAMES)
+@pytest.mark.parametrize("tuning", FTUNINGS)
+@pytest.mark.parametrize("lut16", [0, 1])
+def test_list_major_float_tables_equal_plain_and_oracle(fsetup, orc, name, tuning, lut16):
+    """Float indexes: four float32 (or eight binary16) tables side by side;
+    lists shorter than the minimum stay per query; results bit-identical."""
+    ix, g, Qh, npq = fsetup[name]
+    if npq is None:
+        rng = np.random.default_rng(13)
+        npq = rng.integers(0, min(ix.nlist, 30) + 1, size=len(Qh)).astype(np.int32)
+        npq[:2] = (0, ix.nlist)
+    npq = np.minimum(npq, ix.nlist).astype(np.int32)
+    Q, NP = _cuda(Qh), _cuda(npq)
+    alpha, tile, blocks, min_rows = tuning
+    g.set_option(OPT_LUT_F16, lut16)
+    try:
+        for k, n in ((10, 100), (10, 700)):
+            _set_lm(g, False)
+            p_ids, p_d = g.search(Q, NP, k, n)
+            _set_lm(g, True, alpha, tile, blocks)
+            g.set_option(OPT_LM_MIN_ROWS, min_rows)
+            _say("float", name, tuning, lut16, k, n)
+            l_ids, l_d = g.search(Q, NP, k, n)
+            torch.cuda.synchronize()
+            g.set_option(OPT_LM_MIN_ROWS, 0)
+            _set_lm(g, False)
+            r = orc.search(ix, Qh, npq, k, n, lut_f16=bool(lut16))
+            assert np.array_equal(l_ids.cpu().numpy(), r.ids), (k, n)
+            assert np.array_equal(l_d.cpu().numpy(), r.dists), (k, n)
+            assert torch.equal(l_ids, p_ids)
+            assert torch.equal(l_d.view(torch.int32), p_d.view(torch.int32))
+    finally:
+        g.set_option(OPT_LUT_F16, 0)
+
+
+@pytest.mark.parametrize("lut16", [0, 1])
+def test_list_major_float_topn_graph(ann, fsetup, orc, lut16):
+    """Zipf index: top-n with its Eq. 1 values and candidate counts, and a
+    graph replaying the list-major search, equal the oracle's."""
+    ix, g, Qh, npq = fsetup["zipf"]
+    Q, NP = _cuda(Qh), _cuda(npq)
+    g.set_option(OPT_LUT_F16, lut16)
+    try:
+        _set_lm(g, True, 1, 2048, 0)
+        g.set_option(OPT_LM_MIN_ROWS, 200)
+        ids, adc, nc = g.search_topn(Q, NP, 300)
+        torch.cuda.synchronize()
+        r = orc.search(ix, Qh, npq, 1, 300, lut_f16=bool(lut16))
+        assert np.array_equal(ids.cpu().numpy(), r.topn_ids)
+        assert np.array_equal(adc.cpu().numpy(), r.topn_adc)
+        assert np.array_equal(nc.cpu().numpy(), r.ncand)
+        r = orc.search(ix, Qh, npq, 10, 400, lut_f16=bool(lut16))
+        gr = ann.Graph(g, Q, NP, 10, 400)
+        try:
+            for rep in range(3):
+                ids, d = gr.launch()
+                torch.cuda.synchronize()
+                assert np.array_equal(ids.cpu().numpy(), r.ids), rep
+                assert np.array_equal(d.cpu().numpy(), r.dists), rep
+        finally:
+            gr.close()
+    finally:
+        g.set_option(OPT_LUT_F16, 0)
+        g.set_option(OPT_LM_MIN_ROWS, 0)
+        _set_lm(g, False)

@@ -114,11 +114,13 @@ def parse():
     ap.add_argument("--lm", default="",
                     help="with --split: list-major alpha,rows,blocks[,min_rows] instead of "
                          "per-query only")
+    ap.add_argument("--page-bytes", type=int, default=4096,
+                    help="host_raw form: bytes per page of the host-memory raw tier")
     ap.add_argument("--build-only", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this size (counter calibration)")
     args = ap.parse_args()
-    known = {"plain", "batched", "served", "heuristic"}
+    known = {"plain", "batched", "served", "heuristic", "host_raw"}
     names = [f for f in args.forms.split(",") if f]
     if not set(names) <= known:
         ap.error(f"--forms: unknown form(s) {sorted(set(names) - known)}")
@@ -218,6 +220,56 @@ def run_served(ann, g, Qh, npq, w, k, n, args):
     return {"qps": best, "ms_per_step": nq / best * 1e3, "loads": loads, "saturation": sat,
             "max_slots": 4, "max_batch": 1024, "request_sizes": "U{1..256}",
             "arrivals": "Poisson"}
+
+
+def run_host_raw(ann, path, Q, nprobe_arg, k, n, opts, args, out, heur):
+    """The search with the raw vectors kept in pinned host memory on pages
+    (Sec. 4.3 layout; raw_tier 1): the same tuned batched search, with step 8
+    reading whole pages over PCIe -- each page once per query, shared by its
+    candidates on it.  Reports queries/s, pages read per query and the PCIe
+    bytes they move, for the fixed re-rank and the heuristic one (Alg. 1)."""
+    import numpy as np
+    import torch
+
+    t0 = time.time()
+    gh = ann.Index(path, 0, raw_tier=1, page_bytes=args.page_bytes)
+    log(f"host raw tier: {gh.desc['pages']} pages of {args.page_bytes} B "
+        f"({gh.desc['host_bytes'] / 2**30:.2f} GiB pinned) in {time.time() - t0:.1f}s")
+    for o, v in opts.items():
+        gh.set_option(o, v)
+    st = torch.cuda.current_stream(Q.device)
+    nq = Q.shape[0]
+    res = {"page_bytes": args.page_bytes, "pages": int(gh.desc["pages"])}
+    for label, (bs, eps, beta, nn) in (("fixed", (0, 0.0, 1, n)),
+                                       ("heuristic", (heur[1], heur[2], heur[3], heur[0]))):
+        for _ in range(max(1, args.warmup)):
+            r = gh.search_pages(Q, nprobe_arg, k, nn, bs, eps, beta)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(args.steps):
+            r = gh.search_pages(Q, nprobe_arg, k, nn, bs, eps, beta)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        ids, d, rr, pr = r
+        reads = float(pr.double().mean())
+        item = {"ms_per_step": round(ms, 4), "qps": round(nq / (ms / 1e3), 1),
+                "rerank_n": nn, "reranked_per_query": round(float(rr.double().mean()), 1),
+                "page_reads_per_query": round(reads, 1),
+                "pcie_gb_per_s": round(reads * nq * args.page_bytes / (ms / 1e3) / 1e9, 2)}
+        ref = out.get("graph_res") if label == "fixed" else out.get("heur_res")
+        if ref is not None:
+            item["results_equal_hbm_tier"] = bool(torch.equal(ids, ref[0]) and
+                                                  torch.equal(d.view(torch.int32),
+                                                              ref[1].view(torch.int32)))
+        res[label] = item
+        log(f"host raw tier, {label}: {ms:.3f} ms/step, {item['qps']:.0f} q/s, "
+            f"{reads:.1f} pages per query, {item['pcie_gb_per_s']} GB/s over PCIe")
+    gh.close()
+    res["qps"] = res["fixed"]["qps"]
+    res["ms_per_step"] = res["fixed"]["ms_per_step"]
+    return res
 
 
 def run_diff(args):
@@ -454,6 +506,10 @@ def main():
     batched_opts = get_opts()
     results = {}
     for name in names:
+        if name == "host_raw":
+            results[name] = run_host_raw(ann, path, Q, nprobe_arg, k, n, batched_opts, args, out,
+                                         (hn, hb, heps, hbeta))
+            continue
         if name == "served":  # the server launches with the tuned work split
             set_opts({**batched_opts, g.OPT_LIST_MAJOR: 0})
             results[name] = run_served(ann, g, Qh, npq, w, k, n, args)

@@ -456,8 +456,12 @@ typedef struct {
 } ann_server_stats;
 
 /* Start a server on a loaded index (cfg NULL: all defaults).  The index must
- * outlive the server.  Errors: ANN_EINVAL (limits, budget too small),
- * ANN_ENOMEM, ANN_EDEVICE. */
+ * outlive the server.  Errors: ANN_EINVAL (limits; a budget too small for one
+ * launch of max_batch queries; max_nprobe with max_rerank_n needing more
+ * scan LDS than a block has; max_rerank_n above 2048 on the host-memory raw
+ * tier), ANN_ENOMEM, ANN_EDEVICE.  A launch that fails with a device error
+ * stops the server (later submits fail); any other failure fails only the
+ * requests of that launch. */
 ann_status ann_server_start(ann_index* ix, const ann_server_cfg* cfg, ann_server** out);
 
 /* Queue a request of nq (1..max_batch) float32 queries in HOST memory
@@ -497,6 +501,17 @@ ann_status ann_server_stop(ann_server* s);
 ann_status ann_adc_forward(const float* d_queries, int64_t B, const float* d_codebooks, int32_t M,
                            int32_t dsub, const uint8_t* d_codes, int64_t C, float* d_out,
                            void* stream);
+
+/*
+ * Exact squared distances of a query batch to a vector batch, the reference
+ * term of the fine-tuning loss: d_out[b][c] = sum_t (q[b][t] - x[c][t])^2,
+ * summed in float64 over t in order and rounded once to float32 (direct
+ * form: no expansion into norms and a product).
+ *   d_queries float32 [B, D], d_vectors float32 [C, D], d_out float32 [B, C]
+ * B <= 1048560.  Index-free.
+ */
+ann_status ann_exact_sq(const float* d_queries, int64_t B, const float* d_vectors, int64_t C,
+                        int32_t D, float* d_out, void* stream);
 
 /* Bytes of device workspace ann_adc_backward needs for these sizes. */
 size_t ann_adc_backward_workspace(int64_t B, int64_t C, int32_t M, int32_t dsub);

@@ -109,6 +109,8 @@ def lib():
         L.ann_set_option.argtypes = [P, ctypes.c_int, i64]
         L.ann_get_option.argtypes = [P, ctypes.c_int, ctypes.POINTER(i64)]
         L.ann_adc_forward.argtypes = [P, i64, P, i32, i32, P, i64, P, P]
+        L.ann_exact_sq.argtypes = [P, i64, P, i64, i32, P, P]
+        L.ann_exact_sq.restype = ctypes.c_int
         L.ann_adc_forward.restype = ctypes.c_int
         L.ann_adc_backward_workspace.argtypes = [i64, i64, i32, i32]
         L.ann_adc_backward_workspace.restype = ctypes.c_size_t
@@ -510,6 +512,46 @@ class ADCDistance(torch.autograd.Function):
                                       _ptr(dQ), _ptr(dCB), _ptr(ws), nbytes,
                                       _stream(Q.device, None)))
         return dQ, dCB, None
+
+
+def _exact_sq_fwd(Q, X):
+    Q = Q.detach().contiguous()
+    X = X.detach().contiguous()
+    if not (Q.is_cuda and X.is_cuda and Q.dtype == torch.float32 and X.dtype == torch.float32
+            and Q.dim() == 2 and X.dim() == 2 and Q.shape[1] == X.shape[1]):
+        raise ValueError("exact_sq: float32 [B, D] and [C, D] tensors on the GPU")
+    out = torch.empty((Q.shape[0], X.shape[0]), dtype=torch.float32, device=Q.device)
+    _check(lib().ann_exact_sq(_ptr(Q), Q.shape[0], _ptr(X), X.shape[0], Q.shape[1], _ptr(out),
+                              _stream(Q.device, None)))
+    return out
+
+
+class ExactSq(torch.autograd.Function):
+    """E[b, c] = ||q_b - x_c||^2 by ann_exact_sq (direct form); its gradient
+    dE/dq_b = 2 sum_c G[b, c] (q_b - x_c) (and likewise for x_c) is a plain
+    product with the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, Q, X):
+        ctx.save_for_backward(Q, X)
+        return _exact_sq_fwd(Q, X)
+
+    @staticmethod
+    def backward(ctx, G):
+        Q, X = ctx.saved_tensors
+        G = G.contiguous()
+        dQ = dX = None
+        if ctx.needs_input_grad[0]:
+            dQ = 2.0 * (G.sum(1, keepdim=True) * Q - G @ X)
+        if ctx.needs_input_grad[1]:
+            dX = 2.0 * (G.sum(0)[:, None] * X - G.t().contiguous() @ Q)
+        return dQ, dX
+
+
+def exact_sq(Q, X):
+    """Exact squared distances [B, C] (ann_exact_sq: direct form, float64 sums
+    rounded once), differentiable in Q and X."""
+    return ExactSq.apply(Q, X)
 
 
 def adc_distance(Q, CB, codes):

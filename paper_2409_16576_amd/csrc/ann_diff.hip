@@ -11,6 +11,7 @@
 // scatter into the codebook is a deterministic segmented sum: one thread per
 // (subspace, codeword) adds its members in increasing candidate order.
 #include <algorithm>
+#include <cstdint>
 
 #include "ann.h"
 #include "ann_internal.h"
@@ -48,6 +49,36 @@ __global__ __launch_bounds__(kBlock) void k_adc_fwd(const float* __restrict__ Q,
   }
 }
 
+
+// Exact squared distances in direct form (no expansion into norms and a
+// product, so no cancellation): out[b][c] = sum_t (q_bt - x_ct)^2 summed in
+// float64 over t in order and rounded once to float32.  Block: 16 x 16 pairs,
+// Q and X staged 64 dimensions at a time.
+__global__ __launch_bounds__(kBlock) void k_exact_sq(const float* __restrict__ Q,
+                                                      const float* __restrict__ X, int B, int C,
+                                                      int D, float* __restrict__ out) {
+  __shared__ float s_q[16][65], s_x[16][65];
+  const int tb = threadIdx.x >> 4, tc = threadIdx.x & 15;
+  const int b = blockIdx.y * 16 + tb, c = blockIdx.x * 16 + tc;
+  double acc = 0.0;
+  for (int t0 = 0; t0 < D; t0 += 64) {
+    for (int i = threadIdx.x; i < 16 * 64; i += kBlock) {
+      const int r = i >> 6, t = t0 + (i & 63);
+      const int qb = blockIdx.y * 16 + r, xc = blockIdx.x * 16 + r;
+      s_q[r][i & 63] = qb < B && t < D ? Q[(size_t)qb * D + t] : 0.f;
+      s_x[r][i & 63] = xc < C && t < D ? X[(size_t)xc * D + t] : 0.f;
+    }
+    __syncthreads();
+    const int tn = min(64, D - t0);
+    for (int t = 0; t < tn; ++t) {
+      const double u = (double)s_q[tb][t] - (double)s_x[tc][t];
+      const double sq = u * u;
+      acc = acc + sq;
+    }
+    __syncthreads();
+  }
+  if (b < B && c < C) out[(size_t)b * C + c] = (float)acc;
+}
 
 // Out[i][j] = sum over k in [k0, k1) of A(i, k) * Bm(k, j), fp32 MFMA
 // 16x16x4.  A(i, k) = A[i * lda_i + k * lda_k] (a transposed operand is
@@ -327,6 +358,20 @@ extern "C" ann_status ann_adc_forward(const float* d_queries, int64_t B, const f
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(k_adc_fwd, dim3((unsigned)B), dim3(kBlock), (size_t)M * kKsub * 4, st,
                      d_queries, d_codebooks, d_codes, (int)B, (int)C, D, M, dsub, d_out);
+  return hipGetLastError() == hipSuccess ? ANN_OK : diff_fail(ANN_EDEVICE, "launch failed");
+}
+
+extern "C" ann_status ann_exact_sq(const float* d_queries, int64_t B, const float* d_vectors,
+                                    int64_t C, int32_t D, float* d_out, void* stream) {
+  if (B < 0 || C < 0 || D < 1 || B >= (1ll << 31) || C >= (1ll << 31))
+    return diff_fail(ANN_EINVAL, "bad shapes");
+  if (B == 0 || C == 0) return ANN_OK;
+  if (!d_queries || !d_vectors || !d_out) return diff_fail(ANN_EINVAL, "NULL pointer");
+  if ((C + 15) / 16 > INT32_MAX || (B + 15) / 16 > 65535)
+    return diff_fail(ANN_EINVAL, "too many queries for one call (at most 1048560)");
+  const dim3 grid((unsigned)((C + 15) / 16), (unsigned)((B + 15) / 16));
+  hipLaunchKernelGGL(k_exact_sq, grid, dim3(kBlock), 0, (hipStream_t)stream, d_queries,
+                     d_vectors, (int)B, (int)C, D, d_out);
   return hipGetLastError() == hipSuccess ? ANN_OK : diff_fail(ANN_EDEVICE, "launch failed");
 }
 

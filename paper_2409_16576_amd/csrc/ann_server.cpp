@@ -275,7 +275,9 @@ struct ann_server {
         q_done += r->nq;
       }
     }
-    if (st != ANN_OK) fatal = st;
+    // a device failure stops the server; any other failure (a request the
+    // kernels cannot take) fails only that launch's requests
+    if (st == ANN_EDEVICE) fatal = st;
     arena.release(s.off, s.bytes);
     --in_flight;
     s.reqs.clear();
@@ -341,6 +343,22 @@ extern "C" ann_status ann_server_start(ann_index* ix, const ann_server_cfg* cfg_
     return (ann_status)set_error(ANN_EINVAL, "max_rerank_n must be in [1, %d]", kMaxRerank);
   if (c.max_k < 1 || c.max_k > c.max_rerank_n)
     return (ann_status)set_error(ANN_EINVAL, "max_k must be in [1, max_rerank_n]");
+  // every admissible request must fit the scan's LDS (the largest request
+  // needs the most: LDS grows with nprobe and rerank_n) and the raw tier
+  int max_lds = 0;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                            index_device(ix)) != hipSuccess)
+    return (ann_status)set_error(ANN_EDEVICE, "hipDeviceGetAttribute failed");
+  const size_t lds = scan_lds_bytes(dv, c.max_nprobe, c.max_rerank_n, false);
+  if ((int64_t)lds > (int64_t)max_lds)
+    return (ann_status)set_error(ANN_EINVAL,
+                                 "max_nprobe %d with max_rerank_n %d needs %zu bytes of scan LDS "
+                                 "per block; the device allows %d",
+                                 c.max_nprobe, c.max_rerank_n, lds, max_lds);
+  if (dv.hpages && c.max_rerank_n > kHostMaxRerank)
+    return (ann_status)set_error(ANN_EINVAL,
+                                 "max_rerank_n must be <= %d with the host-memory raw tier",
+                                 kHostMaxRerank);
   // the budget must admit one launch of the largest kind
   size_t biggest = 0;
   for (int n = 1; n <= c.max_rerank_n; ++n)

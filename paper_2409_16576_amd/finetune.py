@@ -3,9 +3,10 @@
 The loss is the PQ distance's distortion against the exact squared distance,
 L = mean_{b,c} (Dhat[b, c] - ||q_b - x_c||^2)^2, over batches of queries and
 candidate vectors; Dhat and its gradients come from the library's kernels
-(ann.adc_distance), the exact distance and the optimizer step are ordinary
-torch float32 tensor code.  Used on float32 indexes (an integer-grid index
-would lose its exactness with non-integer codebooks).
+(ann.adc_distance), and so does the exact term (ann.exact_sq: direct form,
+float64 sums rounded once -- no cancellation); the optimizer step is ordinary
+torch code.  Used on float32 indexes (an integer-grid index would lose its
+exactness with non-integer codebooks).
 """
 from __future__ import annotations
 
@@ -15,10 +16,8 @@ from . import ann
 
 
 def exact_sq(Q: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
-    """||q_b - x_c||^2 [B, C] in float32 (2-D products only)."""
-    qn = (Q * Q).sum(1, keepdim=True)
-    xn = (X * X).sum(1)[None, :]
-    return qn + xn - 2.0 * (Q @ X.t().contiguous())
+    """||q_b - x_c||^2 [B, C] (library kernel; constant w.r.t. the codebooks)."""
+    return ann.exact_sq(Q, X)
 
 
 def distortion_loss(Q, CB, codes, X) -> torch.Tensor:

@@ -166,3 +166,25 @@ def test_server_errors(ann, setup):
         ann.Server(g, max_slots=17)
     with pytest.raises(ann.AnnError):
         ann.Server(g, max_batch=10 ** 7)
+
+
+def test_server_rejects_limits_beyond_the_scan_lds(ann, tmp_path):
+    """Limits whose largest request would need more scan LDS than a block has
+    are refused at start (an int8 index with 50 subspaces: its float32 table
+    alone is 52 KiB; nprobe 4096 with rerank_n 4096 does not fit), instead of
+    failing the server at the first such request; smaller limits start."""
+    X = fx.mixture(53, 6000, 100, "i8", n_centres=8, lo=-128, hi=127)
+    p, _ = fx.built(tmp_path, "i8s", X, "i8", nlist=40, M=50)
+    g = ann.Index(p, 0)
+    try:
+        with pytest.raises(ann.AnnError):
+            ann.Server(g, max_batch=16, max_nprobe=4096, max_k=10, max_rerank_n=4096)
+        srv = ann.Server(g, max_batch=16, max_nprobe=64, max_k=10, max_rerank_n=400)
+        try:
+            Q = fx.mixture(54, 8, 100, "i8", n_centres=8, lo=-128, hi=127).astype(np.float32)
+            t = srv.submit(Q, 16, 10, 400)
+            assert srv.poll(t, wait=True) is not None
+        finally:
+            srv.stop()
+    finally:
+        g.close()

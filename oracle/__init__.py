@@ -67,6 +67,11 @@ class _OrcIndex(ctypes.Structure):
     ]
 
 
+class _OrcGraph(ctypes.Structure):
+    _fields_ = [("adj", ctypes.c_void_p), ("deg", ctypes.c_int32), ("n_entry", ctypes.c_int32),
+                ("entry", ctypes.c_void_p), ("beam", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -87,7 +92,8 @@ def _load(path: str | None = None):
         lib.orc_adc.argtypes = [P, P, P, P, i64, P, P]
         lib.orc_exact.argtypes = [P, P, P, i64, P]
         lib.orc_search.argtypes = [P, P, i64, P, i32, i32, P, P, P, P, P, P, ctypes.c_int,
-                                   ctypes.c_int, i32, ctypes.c_double, i32, P, P, P]
+                                   ctypes.c_int, i32, ctypes.c_double, i32, P, P, P, P]
+        lib.orc_graph_probe.argtypes = [P, P, P, i64, P, i32, P, P, P, ctypes.c_int]
         lib.orc_page_layout.argtypes = [P, i64, i32, i32, i32, P, P]
         lib.orc_page_layout.restype = i64
         lib.orc_bruteforce.argtypes = [P, P, i64, i32, P, P, ctypes.c_int]
@@ -269,6 +275,38 @@ def index_page_layout(ix: "Index", page_bytes: int = 4096) -> PageLayout:
 
 
 @dataclass
+class NavGraph:
+    """A navigation graph over the list centroids (Sec. 4.1): adj [nlist, deg]
+    neighbour lists (-1 padded), the entry vertices, and the walk's beam width."""
+    adj: np.ndarray
+    entry: np.ndarray
+    beam: int
+
+    def cstruct(self) -> _OrcGraph:
+        self.adj = np.ascontiguousarray(self.adj, dtype=np.int32)
+        self.entry = np.ascontiguousarray(self.entry, dtype=np.int32)
+        return _OrcGraph(self.adj.ctypes.data, self.adj.shape[1], len(self.entry),
+                         self.entry.ctypes.data, int(self.beam), 0)
+
+
+def graph_probe(ix: Index, g: NavGraph, Q, nprobe, threads: int = 0):
+    """Step 2 by a best-first beam search of the navigation graph: (lists [nq,
+    max nprobe] -1 padded, float32 distances +inf padded, distances computed
+    per query)."""
+    Q = _q(Q)
+    nq = Q.shape[0]
+    npr = _np(nprobe, nq)
+    w = int(npr.max()) if nq else 0
+    lists = np.empty((nq, w), dtype=np.int32)
+    d = np.empty((nq, w), dtype=np.float32)
+    nd = np.empty(nq, dtype=np.int64)
+    gs = g.cstruct()
+    _load().orc_graph_probe(ctypes.byref(ix.cstruct()), ctypes.byref(gs), _p(Q), nq, _p(npr), w,
+                            _p(lists), _p(d), _p(nd), threads)
+    return lists, d, nd
+
+
+@dataclass
 class SearchResult:
     ids: np.ndarray
     dists: np.ndarray
@@ -281,11 +319,12 @@ class SearchResult:
 
 
 def search(ix: Index, Q, nprobe, k: int, rerank_n: int, threads: int = 0,
-           lut_f16: bool = False, heuristic=None, pages: PageLayout = None) -> SearchResult:
+           lut_f16: bool = False, heuristic=None, pages: PageLayout = None,
+           graph: NavGraph = None) -> SearchResult:
     """Steps 1-8 for a batch of queries (lut_f16: half-precision table variant;
     heuristic = (batch_size, eps, beta): step 8 by the heuristic re-ranking;
     pages: a page layout of the raw vectors, whose page reads per query are
-    then counted)."""
+    then counted; graph: step 2 by the navigation-graph walk)."""
     Q = _q(Q)
     nq = Q.shape[0]
     npr = _np(nprobe, nq)
@@ -301,7 +340,8 @@ def search(ix: Index, Q, nprobe, k: int, rerank_n: int, threads: int = 0,
     _load().orc_search(ctypes.byref(ix.cstruct()), _p(Q), nq, _p(npr), k, rerank_n, _p(ids),
                        _p(dists), _p(tids), _p(tadc), _p(nc), _p(ne), threads,
                        1 if lut_f16 else 0, int(hb), float(he), int(hbeta), _p(rr),
-                       _p(pages.page) if pages is not None else None, _p(pr))
+                       _p(pages.page) if pages is not None else None, _p(pr),
+                       ctypes.byref(graph.cstruct()) if graph is not None else None)
     return SearchResult(ids, dists, tids, tadc, nc, ne, rr, pr)
 
 

@@ -20,7 +20,8 @@
  *  - dist() of Eq. 1 is the squared Euclidean distance of the subvectors, so
  *    the table sum equals the squared distance to the decoded vector.
  *  - Non-residual PQ: one table per query, built before the lists are known.
- *  - The probe is exact over all centroids (no navigation graph).
+ *  - The probe is exact over all centroids, or a best-first beam search over
+ *    a navigation graph of the centroids when one is given.
  *  - Every distance that decides a selection is a float32 value: exact
  *    squared distances are evaluated in float64 (sequential over dimensions)
  *    or in integers, then rounded to nearest-even float32.  The table sum of
@@ -161,6 +162,100 @@ static int probe_one(const orc_index* ix, const double* q, int np, int32_t* out_
   }
   return np;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Step 2 through a navigation graph over the list centroids (Sec. 4.1: the  */
+/* host traverses an in-memory graph whose vertices are the posting-list    */
+/* centroids, each joined to its nearest neighbours, to find the top-m      */
+/* lists).  The traversal read here is a best-first beam search:            */
+/*   - the candidate set C holds at most `beam` (distance, list) pairs,      */
+/*     ascending, each marked expanded or not; every centroid whose          */
+/*     distance has been computed is "visited" and never computed again;     */
+/*   - C starts with the entry vertices (their `beam` smallest);             */
+/*   - repeatedly the smallest member of C not yet expanded is expanded:     */
+/*     each unvisited neighbour is visited and offered to C, which keeps its */
+/*     `beam` smallest pairs; the search ends when every member of C has     */
+/*     been expanded;                                                        */
+/*   - the result is C's first m pairs.                                      */
+/* beam is raised to m when smaller.  Distances are those of the exact      */
+/* probe (float64 sums rounded once), ties to the lower list.  Pairs are     */
+/* never re-admitted once dropped (C's largest member only decreases once C  */
+/* is full), so each list is expanded at most once and the search ends.      */
+
+typedef struct {
+  pair_t p;
+  int expanded;
+} beam_t;
+
+/* Offer pair x to the ascending candidate set c[0..*cnt) of capacity cap. */
+static void beam_offer(beam_t* c, int* cnt, int cap, pair_t x) {
+  if (*cnt == cap && pair_cmp(&x, &c[cap - 1].p) >= 0) return;
+  int pos = *cnt < cap ? *cnt : cap - 1;
+  while (pos > 0 && pair_cmp(&x, &c[pos - 1].p) < 0) {
+    c[pos] = c[pos - 1];
+    --pos;
+  }
+  c[pos].p = x;
+  c[pos].expanded = 0;
+  if (*cnt < cap) ++*cnt;
+}
+
+/* One query's graph walk; returns the lists found (<= np) and adds the
+ * distances it computed to *ndist. */
+static int graph_probe_one(const orc_index* ix, const double* q, const int32_t* adj, int deg,
+                           const int32_t* entry, int n_entry, int beam, int np, int32_t* out_l,
+                           float* out_d, beam_t* c, uint8_t* visited, int64_t* ndist) {
+  if (np > ix->nlist) np = ix->nlist;
+  if (np < 0) np = 0;
+  if (beam < np) beam = np;
+  if (beam < 1) beam = 1;
+  memset(visited, 0, (size_t)ix->nlist);
+  int cnt = 0;
+  for (int i = 0; i < n_entry; ++i) {
+    const int32_t e = entry[i];
+    if (e < 0 || e >= ix->nlist || visited[e]) continue;
+    visited[e] = 1;
+    ++*ndist;
+    pair_t x;
+    x.d = sqdist_f64(q, ix->centroids + (int64_t)e * ix->dim, ix->dim);
+    x.id = e;
+    beam_offer(c, &cnt, beam, x);
+  }
+  for (;;) {
+    int i = 0;
+    while (i < cnt && c[i].expanded) ++i;
+    if (i == cnt) break;
+    c[i].expanded = 1;
+    const int32_t v = c[i].p.id;
+    for (int j = 0; j < deg; ++j) {
+      const int32_t u = adj[(int64_t)v * deg + j];
+      if (u < 0 || u >= ix->nlist || visited[u]) continue;
+      visited[u] = 1;
+      ++*ndist;
+      pair_t x;
+      x.d = sqdist_f64(q, ix->centroids + (int64_t)u * ix->dim, ix->dim);
+      x.id = u;
+      beam_offer(c, &cnt, beam, x);
+    }
+  }
+  const int got = cnt < np ? cnt : np;
+  for (int p = 0; p < got; ++p) {
+    out_l[p] = c[p].p.id;
+    if (out_d) out_d[p] = c[p].p.d;
+  }
+  return got;
+}
+
+/* A navigation graph: adj[nlist][deg] neighbour lists (-1 padded), the entry
+ * vertices, and the beam width of the walk. */
+typedef struct {
+  const int32_t* adj;
+  int32_t deg;
+  int32_t n_entry;
+  const int32_t* entry;
+  int32_t beam;
+  int32_t pad_;
+} orc_graph;
 
 /* The binary16 value nearest to x, ties to the even significand, as a float
  * (exact: every binary16 value is a float).  binary16 has 10 fraction bits,
@@ -415,6 +510,45 @@ void orc_probe(const orc_index* ix, const float* Q, int64_t nq, const int32_t* n
   }
 }
 
+/* Step 2 for a batch through a navigation graph.  probe/pdist: nq x
+ * nprobe_max, padded with -1/+inf; ndist (optional, nq): centroid distances
+ * computed by each query's walk. */
+void orc_graph_probe(const orc_index* ix, const orc_graph* g, const float* Q, int64_t nq,
+                     const int32_t* nprobe, int32_t nprobe_max, int32_t* probe, float* pdist,
+                     int64_t* ndist, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+  {
+    double* q = (double*)malloc(sizeof(double) * ix->dim);
+    int cap = g->beam > nprobe_max ? g->beam : nprobe_max;
+    if (cap < 1) cap = 1;
+    beam_t* c = (beam_t*)malloc(sizeof(beam_t) * cap);
+    uint8_t* visited = (uint8_t*)malloc((size_t)ix->nlist);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 4)
+#endif
+    for (int64_t i = 0; i < nq; ++i) {
+      convert_query(ix, Q + i * ix->dim, q);
+      int32_t* pl = probe + i * nprobe_max;
+      float* pd = pdist ? pdist + i * nprobe_max : NULL;
+      int64_t nd = 0;
+      int np = nprobe[i] < nprobe_max ? nprobe[i] : nprobe_max;
+      int got = graph_probe_one(ix, q, g->adj, g->deg, g->entry, g->n_entry, g->beam, np, pl, pd,
+                                c, visited, &nd);
+      for (int p = got; p < nprobe_max; ++p) {
+        pl[p] = -1;
+        if (pd) pd[p] = INFINITY;
+      }
+      if (ndist) ndist[i] = nd;
+    }
+    free(q);
+    free(c);
+    free(visited);
+  }
+}
+
 /* Step 1 for a batch.  lut32: nq x M x ksub; lut64 optional (same shape);
  * f16: round the float32 entries to binary16. */
 void orc_lut(const orc_index* ix, const float* Q, int64_t nq, float* lut32, double* lut64,
@@ -486,7 +620,7 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
                 int32_t k, int32_t rerank_n, int64_t* ids, float* dists, int32_t* topn_ids,
                 float* topn_adc, int64_t* ncand, int64_t* nentries, int nthreads, int lut_f16,
                 int32_t h_batch, double h_eps, int32_t h_beta, int64_t* reranked,
-                const int32_t* page, int64_t* page_reads) {
+                const int32_t* page, int64_t* page_reads, const orc_graph* graph) {
   int64_t maxg = ix->offsets[ix->nlist];
   if (maxg < 1) maxg = 1;
 #ifdef _OPENMP
@@ -503,6 +637,13 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
     pair_t* rr = (pair_t*)malloc(sizeof(pair_t) * (rerank_n > 0 ? rerank_n : 1));
     member_t* best = (member_t*)malloc(sizeof(member_t) * (k > 0 ? k : 1));
     int32_t* seen = (int32_t*)malloc(sizeof(int32_t) * (rerank_n > 0 ? rerank_n : 1));
+    beam_t* gc = NULL;
+    uint8_t* visited = NULL;
+    if (graph) {
+      int cap = graph->beam > ix->nlist ? graph->beam : ix->nlist;
+      gc = (beam_t*)malloc(sizeof(beam_t) * (cap > 0 ? cap : 1));
+      visited = (uint8_t*)malloc((size_t)ix->nlist);
+    }
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 1)
 #endif
@@ -510,7 +651,14 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
       convert_query(ix, Q + i * ix->dim, q);
       int_query(ix, q, qi);
       lut_one(ix, q, lut, NULL, lut_f16);                          /* step 1 */
-      int np = probe_one(ix, q, nprobe[i], probe, NULL, scratch);  /* step 2 */
+      int np;                                                      /* step 2 */
+      if (graph) {
+        int64_t nd = 0;
+        np = graph_probe_one(ix, q, graph->adj, graph->deg, graph->entry, graph->n_entry,
+                             graph->beam, nprobe[i], probe, NULL, gc, visited, &nd);
+      } else {
+        np = probe_one(ix, q, nprobe[i], probe, NULL, scratch);
+      }
       int64_t nu = 0;
       int64_t g = gather_dedup(ix, probe, np, buf, &nu);           /* steps 3, 5 */
       for (int64_t c = 0; c < nu; ++c) {                           /* step 6 */
@@ -558,6 +706,8 @@ void orc_search(const orc_index* ix, const float* Q, int64_t nq, const int32_t* 
     free(rr);
     free(best);
     free(seen);
+    free(gc);
+    free(visited);
   }
 }
 

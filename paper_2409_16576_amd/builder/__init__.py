@@ -4,8 +4,9 @@ The index follows the paper's offline processing (Sec. 3, Sec. 4.1): the
 dataset is clustered into posting lists, boundary vectors are replicated into
 neighbouring lists by the rule of Eq. 2 (at most R lists per vector), the
 posting lists are reduced to vector IDs, and every vector gets one M-byte PQ
-code (Sec. 2.2).  The navigation graph over centroids is not built: the search
-probes centroids exactly.
+code (Sec. 2.2).  ``build_nav_graph`` builds the navigation graph over the
+list centroids (Sec. 4.1) for the graph probe; without it the search probes
+the centroids exactly.
 
 Clustering is flat k-means for up to ``FLAT_MAX_LISTS`` lists and two-level
 (hierarchical) k-means above that, following the paper's hierarchical
@@ -93,6 +94,7 @@ def _load():
         lib.bld_assign_flat.argtypes = [P, i64, i32, P, i32, i32, f32, P]
         lib.bld_assign_hier.argtypes = [P, i64, i32, P, i32, P, P, i32, i32, f32, P]
         lib.bld_pq_encode.argtypes = [P, i64, i32, P, i32, i32, i32, P]
+        lib.bld_nav_graph.argtypes = [P, i32, i32, i32, P, i32, P, P, i32, P]
         _lib = lib
     return _lib
 
@@ -346,3 +348,59 @@ def read_list_meta(path: str):
     sizes = np.diff(offsets)
     primary = np.bincount(first, minlength=nlist).astype(np.int64)
     return sizes, primary
+
+
+def build_nav_graph(C: np.ndarray, deg: int = 32, seed: int = 0, gprobe: int = 8):
+    """Navigation graph over list centroids C [nlist, D] (Sec. 4.1).
+
+    Each centroid is joined to its ``deg`` nearest other centroids among the
+    members of its ``gprobe`` nearest centroid groups (a k-means of the
+    centroids into about sqrt(nlist) groups), and a centroid that another one
+    chose also takes that one when it is among its own ``deg`` nearest
+    candidates (reverse edges).  Entry vertices: the member nearest to each
+    group's centre, plus one vertex of every part of the graph those do not
+    reach, so every centroid is reachable from the entries.
+
+    Returns (adj [nlist, deg] int32, ascending distance, -1 padded; entry int32).
+    """
+    lib = _load()
+    C = np.ascontiguousarray(C, dtype=np.float32)
+    k, d = C.shape
+    deg = max(1, min(int(deg), max(k - 1, 1)))
+    ng = max(1, min(k, int(round(np.sqrt(k)))))
+    G = kmeans(C, ng, 5, seed + 31)
+    gof = np.empty(k, dtype=np.int32)
+    gd = np.empty(k, dtype=np.float32)
+    lib.bld_nearest(_ptr(C), k, d, _ptr(G), ng, _ptr(gof), _ptr(gd))
+    order = np.lexsort((np.arange(k), gof))
+    gmem = np.ascontiguousarray(order.astype(np.int32))
+    goff = np.zeros(ng + 1, dtype=np.int32)
+    goff[1:] = np.cumsum(np.bincount(gof, minlength=ng))
+    adj = np.empty((k, deg), dtype=np.int32)
+    lib.bld_nav_graph(_ptr(C), k, d, deg, _ptr(G), ng, _ptr(goff), _ptr(gmem), int(gprobe),
+                      _ptr(adj))
+    entry = []
+    for g in range(ng):
+        mem = gmem[goff[g]:goff[g + 1]]
+        if len(mem):
+            dd = ((C[mem] - G[g]) ** 2).sum(1)
+            entry.append(int(mem[np.lexsort((mem, dd))[0]]))
+    # reachability from the entries (breadth first); unreached parts get an entry
+    seen = np.zeros(k, dtype=bool)
+
+    def reach(starts):
+        front = np.array(starts, dtype=np.int64)
+        seen[front] = True
+        while len(front):
+            nb = adj[front].reshape(-1)
+            nb = np.unique(nb[nb >= 0])
+            nb = nb[~seen[nb]]
+            seen[nb] = True
+            front = nb
+
+    reach(entry)
+    while not seen.all():
+        v = int(np.argmin(seen))
+        entry.append(v)
+        reach([v])
+    return adj, np.asarray(entry, dtype=np.int32)

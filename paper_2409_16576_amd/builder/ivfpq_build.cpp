@@ -232,4 +232,65 @@ void bld_pq_encode(const float* X, int64_t n, int d, const float* CB, int M, int
   }
 }
 
+// Navigation graph over the list centroids (Sec. 4.1): every centroid is
+// joined to its `deg` nearest other centroids, and a centroid chosen by a
+// later one also takes it among its own nearest when it is nearer than its
+// current farthest edge (keeping at most `deg`), as when vertices are added
+// one at a time and their neighbours update their edge lists.  Candidates of
+// vertex v are the centroids of the `gprobe` groups nearest to v (groups: a
+// k-means of the centroids, `gof[v]` = v's group, members listed in
+// gmem[goff[g] .. goff[g+1])).  adj: k x deg, ascending (distance, id), -1
+// padded.
+void bld_nav_graph(const float* C, int k, int d, int deg, const float* G, int ng,
+                   const int32_t* goff, const int32_t* gmem, int gprobe, int32_t* adj) {
+  gprobe = std::min(gprobe, ng);
+  std::vector<float> gt = transpose(G, ng, d);
+  // 1. each vertex's nearest among its candidate groups
+  std::vector<std::vector<std::pair<float, int32_t>>> knn(k);
+#pragma omp parallel
+  {
+    std::vector<float> gd(ng);
+    std::vector<int32_t> gi(ng);
+    std::vector<std::pair<float, int32_t>> cand;
+#pragma omp for schedule(dynamic, 64)
+    for (int v = 0; v < k; ++v) {
+      const float* cv = C + (size_t)v * d;
+      sqdist_block(cv, gt.data(), ng, ng, d, gd.data());
+      for (int g = 0; g < ng; ++g) gi[g] = g;
+      std::partial_sort(gi.begin(), gi.begin() + gprobe, gi.end(), [&](int a, int b) {
+        return gd[a] < gd[b] || (gd[a] == gd[b] && a < b);
+      });
+      cand.clear();
+      for (int s = 0; s < gprobe; ++s) {
+        const int g = gi[s];
+        for (int32_t j = goff[g]; j < goff[g + 1]; ++j) {
+          const int32_t u = gmem[j];
+          if (u != v) cand.emplace_back(sqdist(cv, C + (size_t)u * d, d), u);
+        }
+      }
+      const size_t r = std::min<size_t>(deg, cand.size());
+      std::partial_sort(cand.begin(), cand.begin() + r, cand.end());
+      knn[v].assign(cand.begin(), cand.begin() + r);
+    }
+  }
+  // 2. reverse edges: u chosen by v is offered v as well
+  std::vector<std::vector<std::pair<float, int32_t>>> rev(k);
+  for (int v = 0; v < k; ++v)
+    for (const auto& e : knn[v]) rev[e.second].emplace_back(e.first, v);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int v = 0; v < k; ++v) {
+    std::vector<std::pair<float, int32_t>> all = knn[v];
+    all.insert(all.end(), rev[v].begin(), rev[v].end());
+    std::sort(all.begin(), all.end());
+    all.erase(std::unique(all.begin(), all.end(),
+                          [](const std::pair<float, int32_t>& a,
+                             const std::pair<float, int32_t>& b) { return a.second == b.second; }),
+              all.end());
+    int32_t* row = adj + (size_t)v * deg;
+    int w = 0;
+    for (size_t i = 0; i < all.size() && w < deg; ++i) row[w++] = all[i].second;
+    for (; w < deg; ++w) row[w] = -1;
+  }
+}
+
 }  // extern "C"

@@ -367,6 +367,109 @@ def run_diff(args):
     print(json.dumps(line), flush=True)
 
 
+def run_nav(args):
+    """Navigation-graph probe (Sec. 4.1) at the paper's list count, where the
+    exact probe stops being cheap: 2M x 100-d int8 vectors (8192-centre
+    mixture), 200,000 lists (0.1 N), PQ 50 x 256; 10,000 queries, nprobe 256,
+    rerank_n 200, k 10.  Builds the centroid graph (32 edges per vertex), then
+    times step 2 alone and the whole search (one ann_search over the batch)
+    with the exact probe and with graph walks of several beam widths, each
+    bracketed by HIP events on the launch stream; reports the share of the
+    exact top-nprobe lists each walk finds.  The CPU leg adds recall@10
+    against exact kNN and the bit-exact parity of the GPU graph search with
+    the oracle's on a query sample."""
+    import numpy as np
+    import torch
+
+    from paper_2409_16576_amd import ann, builder, workloads
+
+    w = workloads.ALL["nav_i8_2m"]
+    t0 = time.time()
+    path = workloads.ensure_index(w, verbose=True)
+    log(f"index ready in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    C = builder.read_centroids(path)
+    deg = 32
+    adj, entry = builder.build_nav_graph(C, deg=deg, seed=1)
+    log(f"navigation graph: {C.shape[0]} vertices, {deg} edges each, {len(entry)} entries, "
+        f"{time.time() - t0:.1f}s")
+    if args.build_only:
+        return
+    dev = torch.device("cuda", 0)
+    g = ann.Index(path, 0)
+    g.set_nav_graph(adj, entry)
+    Qh = workloads.queries(w)
+    Q = torch.from_numpy(Qh).to(dev)
+    nq, npr, k, n = len(Qh), int(w.nprobe), w.k, w.rerank_n
+    st = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            out = fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+
+    reps = max(1, args.steps)
+    g.set_option(g.OPT_PROBE_BEAM, 0)
+    p_ms, (ex_lists, _) = timed(lambda: g.probe(Q, npr, with_dists=False), reps)
+    s_ms, (ex_ids, _) = timed(lambda: g.search(Q, npr, k, n), reps)
+    exact = {"probe_ms": round(p_ms, 4), "search_ms": round(s_ms, 4),
+             "qps": round(nq / (s_ms / 1e3), 1)}
+    log(f"exact probe: probe {p_ms:.3f} ms, search {s_ms:.3f} ms per {nq} queries")
+    exs = ex_lists.cpu().numpy()
+    walks = []
+    for beam in (256, 384, 512, 768):
+        g.set_option(g.OPT_PROBE_BEAM, beam)
+        p_ms, (gl, _) = timed(lambda: g.probe(Q, npr, with_dists=False), reps)
+        s_ms, (gi, _) = timed(lambda: g.search(Q, npr, k, n), reps)
+        gls = gl.cpu().numpy()
+        found = np.mean([len(np.intersect1d(a, b)) / npr for a, b in zip(gls, exs)])
+        same10 = float((gi.cpu().numpy() == ex_ids.cpu().numpy()).mean())
+        walks.append({"beam": beam, "probe_ms": round(p_ms, 4), "search_ms": round(s_ms, 4),
+                      "qps": round(nq / (s_ms / 1e3), 1), "exact_lists_found": round(found, 4),
+                      "top10_equal_exact_probe": round(same10, 4)})
+        log(f"graph probe beam {beam}: probe {p_ms:.3f} ms, search {s_ms:.3f} ms, "
+            f"{found:.4f} of the exact lists")
+    line = {"metric": "navigation-graph probe vs exact probe at nlist = 0.1 N, queries/s",
+            "value": walks[0]["qps"], "unit": "queries/s", "n_gpus": 1, "steps": reps,
+            "warmup": 1, "ms_per_step": walks[0]["search_ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+            "config": {**w.describe(), "graph_degree": deg, "entries": int(len(entry))},
+            "exact_probe": exact, "graph_probe": walks}
+    if not args.no_cpu:
+        import oracle
+        oracle.build(force=False)
+        ix = oracle.read_index(path)
+        m = 200
+        t0 = time.time()
+        truth, _ = oracle.bruteforce(ix, Qh[:m], k)
+        beam = walks[0]["beam"]
+        g.set_option(g.OPT_PROBE_BEAM, beam)
+        gi, gd = g.search(Q[:m], npr, k, n)
+        r = oracle.search(ix, Qh[:m], npr, k, n, graph=oracle.NavGraph(adj, entry, beam))
+        parity = {"queries": m, "beam": beam,
+                  "ids_equal": bool(np.array_equal(gi.cpu().numpy(), r.ids)),
+                  "dists_equal": bool(np.array_equal(gd.cpu().numpy().view(np.int32),
+                                                     r.dists.view(np.int32)))}
+        g.set_option(g.OPT_PROBE_BEAM, 0)
+        ei, _ = g.search(Q[:m], npr, k, n)
+        rec = {"exact_probe": round(oracle.recall_at_k(ei.cpu().numpy(), truth, k), 4)}
+        for wk in walks:
+            g.set_option(g.OPT_PROBE_BEAM, wk["beam"])
+            gi, _ = g.search(Q[:m], npr, k, n)
+            rec[f"beam_{wk['beam']}"] = round(oracle.recall_at_k(gi.cpu().numpy(), truth, k), 4)
+        line["recall_at_10"] = rec
+        line["parity_sample"] = parity
+        log(f"recall@10 {rec}, parity {parity} ({time.time() - t0:.1f}s)")
+    g.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -380,6 +483,8 @@ def main():
 
     if args.workload == "diff_f32_1m":
         return run_diff(args)
+    if args.workload == "nav_i8_2m":
+        return run_nav(args)
     w = workloads.ALL[args.workload]
     t0 = time.time()
     path = workloads.ensure_index(w, verbose=True)
@@ -694,6 +799,29 @@ def main():
         log(f"brute force of {nr} queries in {time.perf_counter() - t0:.1f}s")
         line["recall_at_10"] = round(oracle.recall_at_k(ids_gpu[:nr], gt, k), 4)
         line["recall_queries"] = nr
+        # Per-query minimum re-ranking number (the paper's Sec. 2.3 study): a
+        # query's exact top-k comes out of re-ranking its top-n ADC candidates
+        # once all k true neighbours are among them, i.e. from n = 1 + the
+        # largest ADC rank of a true neighbour (never, when one lies outside
+        # the probed lists).  Ranks from the GPU's top-4096 ADC candidates.
+        nmax = min(4096, g.desc["max_rerank_n"])
+        tids, _, _ = g.search_topn(Q[:nr], nprobe_arg if fixed_np else nprobe_arg[:nr], nmax)
+        tids = tids.cpu().numpy()
+        need = np.full(nr, np.inf)
+        for i in range(nr):
+            pos = {int(v): r_ for r_, v in enumerate(tids[i]) if v >= 0}
+            rk = [pos.get(int(v), None) for v in gt[i][:k]]
+            if all(x is not None for x in rk):
+                need[i] = 1 + max(rk)
+        grid = [10, 20, 40, 100, 200, 400, 1000, 2000, 4096]
+        line["min_rerank_n"] = {
+            "queries": nr, "n_max": nmax,
+            "share_exact_at_n": {str(x): round(float((need <= x).mean()), 4) for x in grid},
+            "never": round(float(np.isinf(need).mean()), 4),
+            "median": (float(np.median(need)) if np.isfinite(np.median(need)) else None),
+            "p90": (float(np.percentile(need, 90)) if np.isfinite(np.percentile(need, 90))
+                    else None)}
+        log(f"minimum re-ranking number: {line['min_rerank_n']}")
         if "heur_res" in out:
             hid = out["heur_res"][0][:nr].cpu().numpy()
             line["forms"]["heuristic"]["recall_at_10"] = round(oracle.recall_at_k(hid, gt, k), 4)

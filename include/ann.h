@@ -348,6 +348,14 @@ ann_status ann_get_profile(ann_index* ix, ann_profile* out, int reset);
  *                       entries become +inf).  ann_search / ann_search_topn
  *                       and the forms built on them; ann_lut and
  *                       ann_scan_trace stay float32.
+ * Probe variant (changes which lists are probed):
+ *   ANN_OPT_PROBE_BEAM  > 0: step 2 walks the navigation graph given by
+ *                       ann_set_nav_graph with this beam width, in [1, 1024]
+ *                       (raised to a query's nprobe when smaller); nprobe_max
+ *                       is then at most 1024.  0 (default): exact probe over
+ *                       all centroids.  Applies to every search entry point,
+ *                       ann_probe, the server, and graphs created while it is
+ *                       set.
  * Errors: ANN_EINVAL for an unknown option or an out-of-range value.
  */
 enum {
@@ -360,10 +368,36 @@ enum {
   ANN_OPT_LM_TILE = 7,
   ANN_OPT_LM_BLOCKS = 8,
   ANN_OPT_LM_CAP = 9,
-  ANN_OPT_LM_MIN_ROWS = 10
+  ANN_OPT_LM_MIN_ROWS = 10,
+  ANN_OPT_PROBE_BEAM = 11
 };
 ann_status ann_set_option(ann_index* ix, int option, int64_t value);
 ann_status ann_get_option(ann_index* ix, int option, int64_t* value);
+
+/*
+ * Navigation graph over the list centroids (Sec. 4.1: the top-m lists are
+ * found by walking an in-memory graph whose vertices are the posting lists'
+ * centroids, each joined to its nearest neighbours).  With
+ * ANN_OPT_PROBE_BEAM = B > 0 step 2 becomes a best-first beam walk of it, per
+ * query (B raised to the query's nprobe when smaller):
+ *   - the candidate set holds the B nearest (centroid distance, list) pairs
+ *     found so far, each expanded or not; it starts with the entry vertices;
+ *   - the nearest candidate not yet expanded is expanded: each neighbour whose
+ *     distance was not computed before is computed and offered to the set,
+ *     which keeps its B nearest;
+ *   - the walk ends when every candidate has been expanded; the first nprobe
+ *     candidates are the probed lists, ascending.
+ * Distances are those of the exact probe, ties to the lower list id.
+ *   adj      host int32 [nlist, deg]: neighbours of each list (-1 pads a row;
+ *            no list twice in a row), deg in [1, 1024]
+ *   entry    host int32 [n_entry]: distinct entry lists, 1 <= n_entry <= nlist
+ * The arrays are copied to the device (the caller keeps ownership).  A NULL
+ * adj removes the graph and sets the beam to 0.  The call waits for the
+ * device, and must not run concurrently with searches on this index.
+ * Errors: ANN_EINVAL (ranges, duplicates), ANN_ENOMEM, ANN_EDEVICE.
+ */
+ann_status ann_set_nav_graph(ann_index* ix, const int32_t* adj, int32_t deg, const int32_t* entry,
+                             int32_t n_entry);
 
 /*
  * Batched form: the search of one query batch captured into a HIP graph.

@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -107,6 +108,7 @@ def lib():
         L.ann_set_profiling.argtypes = [P, ctypes.c_int]
         L.ann_get_profile.argtypes = [P, ctypes.POINTER(Profile), ctypes.c_int]
         L.ann_set_option.argtypes = [P, ctypes.c_int, i64]
+        L.ann_set_nav_graph.argtypes = [P, P, i32, P, i32]
         L.ann_get_option.argtypes = [P, ctypes.c_int, ctypes.POINTER(i64)]
         L.ann_adc_forward.argtypes = [P, i64, P, i32, i32, P, i64, P, P]
         L.ann_exact_sq.argtypes = [P, i64, P, i64, i32, P, P]
@@ -135,7 +137,7 @@ def lib():
                   "ann_server_submit", "ann_server_poll", "ann_server_get_stats",
                   "ann_server_stop", "ann_graph_create", "ann_graph_launch", "ann_autotune",
                   "ann_search_heuristic", "ann_search_noalloc", "ann_load_index_ex",
-                  "ann_search_pages"):
+                  "ann_search_pages", "ann_set_nav_graph"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -329,6 +331,18 @@ class Index:
     OPT_LM_BLOCKS = 8
     OPT_LM_CAP = 9
     OPT_LM_MIN_ROWS = 10
+    OPT_PROBE_BEAM = 11
+
+    def set_nav_graph(self, adj, entry):
+        """Navigation graph over the list centroids (host arrays: adj [nlist,
+        deg] int32 -1 padded, entry int32); None removes it.  The probe walks
+        it once OPT_PROBE_BEAM is set."""
+        if adj is None:
+            _check(lib().ann_set_nav_graph(self._h, None, 0, None, 0))
+            return
+        a = np.ascontiguousarray(adj, dtype=np.int32)
+        e = np.ascontiguousarray(entry, dtype=np.int32)
+        _check(lib().ann_set_nav_graph(self._h, a.ctypes.data, a.shape[1], e.ctypes.data, len(e)))
 
     def set_option(self, option: int, value: int):
         _check(lib().ann_set_option(self._h, int(option), int(value)))

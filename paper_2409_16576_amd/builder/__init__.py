@@ -331,6 +331,20 @@ def build_index(path: str, X: np.ndarray, kind: str, p: BuildParams, progress=No
     return ix
 
 
+def read_centroids(path: str) -> np.ndarray:
+    """The list centroids [nlist, D] float32 of an index file."""
+    with open(path, "rb") as f:
+        hdr = f.read(HEADER_BYTES)
+        if hdr[:8] != MAGIC:
+            raise ValueError("not an index file")
+        dim, nlist = struct.unpack_from("<I", hdr, 20)[0], struct.unpack_from("<I", hdr, 32)[0]
+        off, nbytes = struct.unpack_from("<QQ", hdr, 128)
+        if nbytes != nlist * dim * 4:
+            raise ValueError("centroid section size")
+        f.seek(off)
+        return np.frombuffer(f.read(nbytes), dtype=np.float32).reshape(nlist, dim).copy()
+
+
 def read_list_meta(path: str):
     """(list sizes, first-list member counts) of an index file, without the big sections."""
     with open(path, "rb") as f:

@@ -303,6 +303,8 @@ ann_status validate_args(ann_index* ix, const void* q, int64_t nq, int32_t np_ma
   if (nq < 0) return fail(ANN_EINVAL, "nq < 0");
   if (nq > 0 && !q) return fail(ANN_EINVAL, "queries pointer is NULL");
   if (np_max < 1 || np_max > 4096) return fail(ANN_EINVAL, "nprobe_max must be in [1, 4096]");
+  if (ix->d.nav_beam > 0 && np_max > kNavMaxBeam)
+    return fail(ANN_EINVAL, "nprobe_max above %d with the graph probe", kNavMaxBeam);
   return ANN_OK;
 }
 
@@ -646,12 +648,19 @@ extern "C" ann_status ann_load_index_ex(const char* path, int device, const ann_
 
   const int row_bytes = (M + 3) / 4 * 4;
   const int es = elem_size(dtype);
-  std::vector<uint8_t> codes_rows((size_t)n * row_bytes, 0);
+  std::vector<uint8_t> codes_rows((n + rep.size()) * row_bytes, 0);
   std::vector<int32_t> asg_rows((size_t)n * R);
   for (uint64_t row = 0; row < n; ++row) {
     const uint64_t v = (uint64_t)row2ext[row];
     std::memcpy(&codes_rows[row * row_bytes], codes + v * M, M);
     std::memcpy(&asg_rows[row * R], asg + v * R, (size_t)R * 4);
+  }
+  // rows n + e: replica entry e's code row and ID, in entry order
+  row2ext.resize(n + rep.size());
+  for (size_t e = 0; e < rep.size(); ++e) {
+    const uint32_t row = (uint32_t)rep[e].x & kRowMask;
+    std::memcpy(&codes_rows[(n + e) * row_bytes], &codes_rows[(size_t)row * row_bytes], row_bytes);
+    row2ext[n + e] = row2ext[row];
   }
   std::vector<float> cent_t((size_t)dim * nlist);
   for (int l = 0; l < nlist; ++l)
@@ -927,6 +936,7 @@ int ann::get_opt(const ann_index* ix, int option, int64_t* v) {
     case ANN_OPT_LM_BLOCKS: *v = ix->opt_lm_blocks; return ANN_OK;
     case ANN_OPT_LM_CAP: *v = ix->opt_lm_cap; return ANN_OK;
     case ANN_OPT_LM_MIN_ROWS: *v = ix->opt_lm_min_rows; return ANN_OK;
+    case ANN_OPT_PROBE_BEAM: *v = ix->d.nav_beam; return ANN_OK;
     default: return ANN_EINVAL;
   }
 }
@@ -1175,9 +1185,80 @@ extern "C" ann_status ann_set_option(ann_index* ix, int option, int64_t value) {
         return fail(ANN_EINVAL, "list-major minimum rows must be in [0, 2^30]");
       ix->opt_lm_min_rows = value;
       return ANN_OK;
+    case ANN_OPT_PROBE_BEAM:
+      if (value < 0 || value > kNavMaxBeam)
+        return fail(ANN_EINVAL, "probe beam must be in [0, %d]", kNavMaxBeam);
+      if (value > 0 && !ix->d.nav_adj) return fail(ANN_EINVAL, "no navigation graph (ann_set_nav_graph)");
+      ix->d.nav_beam = (int)value;
+      return ANN_OK;
     default:
       return fail(ANN_EINVAL, "unknown option %d", option);
   }
+}
+
+namespace {
+void free_dev(ann_index* ix, const void* p) {
+  if (!p) return;
+  auto it = std::find(ix->allocs.begin(), ix->allocs.end(), const_cast<void*>(p));
+  if (it != ix->allocs.end()) {
+    ix->allocs.erase(it);
+    (void)hipFree(const_cast<void*>(p));
+  }
+}
+}  // namespace
+
+extern "C" ann_status ann_set_nav_graph(ann_index* ix, const int32_t* adj, int32_t deg,
+                                        const int32_t* entry, int32_t n_entry) {
+  if (!ix) return fail(ANN_EINVAL, "index is NULL");
+  DevIndex& d = ix->d;
+  if (!adj) {  // remove the graph: the probe is exact again
+    HIP_TRY(hipSetDevice(ix->device));
+    HIP_TRY(hipDeviceSynchronize());
+    free_dev(ix, d.nav_adj);
+    free_dev(ix, d.nav_entry);
+    d.nav_adj = d.nav_entry = nullptr;
+    d.nav_deg = d.nav_nentry = d.nav_beam = 0;
+    return ANN_OK;
+  }
+  if (deg < 1 || deg > 1024) return fail(ANN_EINVAL, "degree must be in [1, 1024]");
+  if (!entry || n_entry < 1 || n_entry > d.nlist)
+    return fail(ANN_EINVAL, "need 1 to nlist entry vertices");
+  std::vector<int32_t> row(deg);
+  for (int v = 0; v < d.nlist; ++v) {
+    int c = 0;
+    for (int j = 0; j < deg; ++j) {
+      const int32_t u = adj[(size_t)v * deg + j];
+      if (u < -1 || u >= d.nlist) return fail(ANN_EINVAL, "vertex %d: neighbour %d out of range", v, u);
+      if (u >= 0) row[c++] = u;
+    }
+    std::sort(row.begin(), row.begin() + c);
+    if (std::adjacent_find(row.begin(), row.begin() + c) != row.begin() + c)
+      return fail(ANN_EINVAL, "vertex %d lists a neighbour twice", v);
+  }
+  std::vector<int32_t> es(entry, entry + n_entry);
+  std::sort(es.begin(), es.end());
+  if (es.front() < 0 || es.back() >= d.nlist) return fail(ANN_EINVAL, "entry vertex out of range");
+  if (std::adjacent_find(es.begin(), es.end()) != es.end())
+    return fail(ANN_EINVAL, "an entry vertex is listed twice");
+  HIP_TRY(hipSetDevice(ix->device));
+  HIP_TRY(hipDeviceSynchronize());  // no search may still read the old graph
+  free_dev(ix, d.nav_adj);
+  free_dev(ix, d.nav_entry);
+  d.nav_adj = d.nav_entry = nullptr;
+  d.nav_deg = d.nav_nentry = d.nav_beam = 0;
+  ann_status s;
+  const int32_t* pa = nullptr;
+  const int32_t* pe = nullptr;
+  if ((s = dev_upload(ix, adj, (size_t)d.nlist * deg, &pa)) != ANN_OK) return s;
+  if ((s = dev_upload(ix, entry, (size_t)n_entry, &pe)) != ANN_OK) {
+    free_dev(ix, pa);
+    return s;
+  }
+  d.nav_adj = pa;
+  d.nav_entry = pe;
+  d.nav_deg = deg;
+  d.nav_nentry = n_entry;
+  return ANN_OK;
 }
 
 extern "C" ann_status ann_get_option(ann_index* ix, int option, int64_t* value) {

@@ -30,9 +30,12 @@ constexpr uint32_t kRowMask = (1u << kRankShift) - 1;
 struct DevIndex {
   int dtype, dim, nlist, M, row_bytes, dsub, R, int_grid;
   int64_t n;
-  const uint8_t* codes;       // [n, row_bytes] PQ codes by row (M used bytes)
+  // Codes and IDs by row.  Rows n + e (e < replica entries) repeat the row
+  // of replica entry e, so a run of replica entries reads its code rows and
+  // IDs contiguously instead of gathering them from the vectors' first lists.
+  const uint8_t* codes;       // [n + replica entries, row_bytes] PQ codes (M used bytes)
   const void* vecs;           // [n, dim] raw vectors by external ID
-  const int32_t* row2ext;     // [n]
+  const int32_t* row2ext;     // [n + replica entries]
   const float* centroids;     // [nlist, dim]
   const float* centroids_t;   // [dim, nlist]
   const float* codebooks;     // [M, 256, dsub]
@@ -57,6 +60,11 @@ struct DevIndex {
   const int32_t* vpage;       // [n] page of each vector (by external ID)
   const int32_t* vslot;       // [n] its position on the page
   int page_bytes;
+  // navigation graph over the list centroids (null: none); nav_beam > 0 makes
+  // step 2 a beam walk of it instead of the exact probe
+  const int32_t* nav_adj;     // [nlist, nav_deg] neighbour lists, -1 padded
+  const int32_t* nav_entry;   // [nav_nentry] entry vertices
+  int nav_deg, nav_nentry, nav_beam;
 };
 
 // Working buffers of the list-major pass of the batched form (integer-grid
@@ -132,6 +140,7 @@ hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, 
                         int64_t* out_ids, float* out_dists, int32_t* reranked,
                         int32_t* page_reads, hipStream_t st);
 constexpr int kHostMaxRerank = 2048;  // largest rerank_n with the host-memory raw tier
+constexpr int kNavMaxBeam = 1024;     // largest beam (and nprobe) of the graph walk
 // Batched form on integer-grid indexes: after launch_probe, in place of
 // launch_scan (same outputs for launch_merge, one item per query).
 bool lmajor_supported(const DevIndex& ix);

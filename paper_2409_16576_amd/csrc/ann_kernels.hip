@@ -646,6 +646,7 @@ struct ScanMisc {
   int ncount;
   int scanned;
   int done;  // waves that have walked all their entries
+  int seg;   // the query's replica entries are laid out as surviving groups
 };
 
 // Exclusive prefix sum of v over the block (in thread order); s_wsum holds
@@ -825,10 +826,12 @@ __host__ __device__ inline bool lm_slot(int p, int walkp, int rows, int min_rows
 
 // Runs of up to 64 probed lists laid out by one wave (lane p: list p): run
 // starts in s_rstart, exclusive entry offsets in s_pre[0..nruns], and
-// s_pre[nruns] = the query's entries; *s_nruns = nruns.
+// s_pre[nruns] = the query's entries; *s_nruns = nruns, *s_seg = whether the
+// replica runs are surviving groups.
 __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_list, int np,
                           int walk_np, int min_rows, const uint32_t* s_bits, int segmented,
-                          int max_runs, uint32_t* s_rstart, int32_t* s_pre, int* s_nruns) {
+                          int max_runs, uint32_t* s_rstart, int32_t* s_pre, int* s_nruns,
+                          int* s_seg) {
   const int lane = threadIdx.x & 63;
   int cnt = 0, l = 0, s0 = 0, s1 = 0;
   if (lane < np) {
@@ -884,6 +887,7 @@ __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_l
   if (lane == 0) {
     s_pre[nruns] = total;
     *s_nruns = nruns;
+    *s_seg = seg ? 1 : 0;
   }
 }
 
@@ -1018,7 +1022,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   if (wave_setup) {
     if (tid < 64) {
       runs_wave(ix, s_list, np, walk_np, sp.min_rows, s_bits, segmented, max_runs, s_rstart,
-                s_pre, &s_wsum[kScanBlock / 64]);
+                s_pre, &s_wsum[kScanBlock / 64], &mc->seg);
     } else {
       build_table(tid - 64, kScanBlock - 64);
     }
@@ -1026,6 +1030,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     nruns = s_wsum[kScanBlock / 64];
   }
   bool seg = segmented != 0;  // as in runs_wave: surviving groups as runs while they fit
+  bool seg_all;
   if (!wave_setup && seg) {
     int tot = 0;
     for (int p0 = 0; p0 < np; p0 += kScanBlock) {  // uniform trip count
@@ -1044,6 +1049,12 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     }
     seg = tot <= max_runs;
   }
+  if (!wave_setup) seg_all = seg;
+  else seg_all = mc->seg != 0;  // runs_wave's decision (read after its barrier)
+  // With at most two lists per vector, every entry of a surviving group is
+  // kept (its vector's only earlier list is the group's, not probed), so
+  // the entries themselves need not be read.
+  const bool grp = seg_all && ix.R == 2;
   for (int p0 = 0; !wave_setup && p0 < np; p0 += kScanBlock) {  // uniform trip count
     const int p = p0 + tid;
     int cnt = 0, l = 0;
@@ -1154,13 +1165,18 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
             rows[u] = (int)rs + o;
             keep[u] = true;
           } else {
-            const int2 r = ix.rep[(int)(rs & ~kRunReplica) + o];
-            const int row = (int)((uint32_t)r.x & kRowMask);
-            const int rank = (int)((uint32_t)r.x >> kRankShift);
-            bool k = !testbit(s_bits, r.y);
-            for (int i = 1; i < rank && k; ++i)
-              k = !testbit(s_bits, ix.assign_rows[(size_t)row * ix.R + i]);
-            rows[u] = row;
+            // replica entry ei: its code row and ID are row n + ei
+            const int ei = (int)(rs & ~kRunReplica) + o;
+            bool k = true;
+            if (!grp) {
+              const int2 r = ix.rep[ei];
+              const int row = (int)((uint32_t)r.x & kRowMask);
+              const int rank = (int)((uint32_t)r.x >> kRankShift);
+              k = !testbit(s_bits, r.y);
+              for (int i = 1; i < rank && k; ++i)
+                k = !testbit(s_bits, ix.assign_rows[(size_t)row * ix.R + i]);
+            }
+            rows[u] = (int)ix.n + ei;
             keep[u] = k;
           }
         }
@@ -2275,6 +2291,205 @@ size_t fused_lds(const DevIndex& ix) {
          kFQ * 8 + (size_t)16 * ix.dim_pad;
 }
 
+// ---------------------------------------------------------------------------
+// Step 2 through the navigation graph over the list centroids (Sec. 4.1).
+//
+// One wave per query walks the graph best first: the candidate set C holds
+// the query's `beam` nearest (distance, list) keys found so far, ascending,
+// each marked expanded or not; the nearest not-yet-expanded one is expanded
+// by scoring its neighbours (one lane each) and merging those that are new
+// and below C's last key into C; the walk ends when all of C is expanded and
+// the first np keys are the probe.  Offering a list twice changes nothing (a
+// key already in C is dropped as a duplicate, and a key once dropped from a
+// full C can never re-enter, because C's last key only decreases), so a
+// lossy visited cache (a list whose slot holds it was scored before) only
+// saves distances.  Distances are the exact probe's.
+constexpr int kNavVis = 1024;  // visited-cache slots per query
+
+__host__ __device__ inline size_t nav_wave_bytes(int dim, int dim_pad, int cap) {
+  size_t o = (size_t)cap * 16;                 // two key buffers
+  o += (size_t)cap * 2;                        // two flag buffers
+  o = (o + 15) / 16 * 16;
+  o += 64 * 8 + 64 * 4;                        // new keys and their ranks in C
+  o += (size_t)kNavVis * 4;                    // visited cache
+  const size_t qb = (size_t)dim * 8 > (size_t)dim_pad ? (size_t)dim * 8 : (size_t)dim_pad;
+  o += (qb + 15) / 16 * 16;                    // the query (float64 or shifted int8)
+  return o;
+}
+
+__device__ __forceinline__ uint32_t nav_slot(int u) {
+  return ((uint32_t)u * 2654435761u) >> (32 - 10);  // kNavVis = 2^10
+}
+
+template <bool INT>
+__global__ __launch_bounds__(kBlock) void k_probe_graph(DevIndex ix, const float* __restrict__ Q,
+                                                      int qc, const int32_t* __restrict__ nprobe,
+                                                      int np_max, int cap,
+                                                      int32_t* __restrict__ lists,
+                                                      float* __restrict__ out_d,
+                                                      int32_t* __restrict__ np_eff) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = blockIdx.x * (blockDim.x >> 6) + w;
+  if (q >= qc) return;  // wave-uniform; the waves of a block never synchronise
+  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned char* base = smem + (size_t)w * nav_wave_bytes(ix.dim, ix.dim_pad, cap);
+  uint64_t* keys[2] = {reinterpret_cast<uint64_t*>(base), reinterpret_cast<uint64_t*>(base) + cap};
+  uint8_t* flg[2] = {reinterpret_cast<uint8_t*>(keys[1] + cap),
+                     reinterpret_cast<uint8_t*>(keys[1] + cap) + cap};
+  size_t off = ((size_t)cap * 18 + 15) / 16 * 16;
+  uint64_t* nk = reinterpret_cast<uint64_t*>(base + off);
+  int32_t* nr = reinterpret_cast<int32_t*>(nk + 64);
+  int32_t* vis = nr + 64;
+  unsigned char* qv = reinterpret_cast<unsigned char*>(vis + kNavVis);
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+
+  int np = nprobe ? nprobe[q] : np_max;
+  np = max(0, min(np, min(np_max, ix.nlist)));
+  const int B = max(max(ix.nav_beam, np), 1);  // <= cap
+
+  // the query: shifted int8 (integer grid) or float64 values
+  int qn = 0;
+  if constexpr (INT) {
+    int8_t* q8 = reinterpret_cast<int8_t*>(qv);
+    for (int t = lane; t < ix.dim_pad; t += 64) {
+      const int v = t < ix.dim ? (int)conv_query(Q[(size_t)q * ix.dim + t], ix.dtype) - ix.shift8 : 0;
+      q8[t] = (int8_t)v;
+      qn += v * v;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) qn += __shfl_xor(qn, d, 64);
+  } else {
+    double* qd = reinterpret_cast<double*>(qv);
+    for (int t = lane; t < ix.dim; t += 64) qd[t] = (double)conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
+  }
+  for (int i = lane; i < kNavVis; i += 64) vis[i] = -1;
+  __threadfence_block();
+
+  // key of list u: (ordered distance bits << 32) | u, the exact probe's distance
+  auto key_of = [&](int u) -> uint64_t {
+    float dist;
+    if constexpr (INT) {
+      const int4* cr = reinterpret_cast<const int4*>(ix.cent8 + (size_t)u * ix.dim_pad);
+      const int4* qr = reinterpret_cast<const int4*>(qv);
+      int dot = 0;
+      for (int c = 0; c < ix.dim_pad / 16; ++c) {
+        const int4 a = cr[c], b = qr[c];
+        dot = __builtin_amdgcn_sdot4(a.x, b.x, dot, false);
+        dot = __builtin_amdgcn_sdot4(a.y, b.y, dot, false);
+        dot = __builtin_amdgcn_sdot4(a.z, b.z, dot, false);
+        dot = __builtin_amdgcn_sdot4(a.w, b.w, dot, false);
+      }
+      dist = (float)(qn + ix.cnorm8[u] - 2 * dot);
+    } else {
+      const double* qd = reinterpret_cast<const double*>(qv);
+      const float* c = ix.centroids + (size_t)u * ix.dim;
+      double acc = 0.0;
+      for (int t = 0; t < ix.dim; ++t) {
+        const double x = qd[t] - (double)c[t];
+        const double sq = x * x;
+        acc = acc + sq;
+      }
+      dist = (float)acc;
+    }
+    return ((uint64_t)ord32(dist) << 32) | (uint32_t)u;
+  };
+
+  int cur = 0, cnt = 0;
+  // Merge each lane's key (if `valid`) into C: drop duplicates and keys that
+  // would land at or past B; every key's new position is its old position
+  // plus the number of keys of the other side below it.
+  auto merge = [&](uint64_t kk, bool valid) {
+    int r = 0;
+    if (valid) {
+      int lo = 0, hi = cnt;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (keys[cur][mid] < kk) lo = mid + 1;
+        else hi = mid;
+      }
+      r = lo;
+      if ((r < cnt && keys[cur][r] == kk) || r >= B) valid = false;
+    }
+    const uint64_t m = __ballot(valid);
+    if (m == 0) return;
+    const int nv = __popcll(m);
+    if (valid) {
+      const int slot = __popcll(m & below);
+      nk[slot] = kk;
+      nr[slot] = r;
+    }
+    __threadfence_block();
+    const int dst = cur ^ 1;
+    for (int i = lane; i < cnt; i += 64) {
+      const uint64_t ki = keys[cur][i];
+      int sb = 0;
+      for (int t = 0; t < nv; ++t) sb += nk[t] < ki ? 1 : 0;
+      const int pos = i + sb;
+      if (pos < B) {
+        keys[dst][pos] = ki;
+        flg[dst][pos] = flg[cur][i];
+      }
+    }
+    if (lane < nv) {
+      const uint64_t kj = nk[lane];
+      int sb = 0;
+      for (int t = 0; t < nv; ++t) sb += nk[t] < kj ? 1 : 0;
+      const int pos = nr[lane] + sb;
+      if (pos < B) {
+        keys[dst][pos] = kj;
+        flg[dst][pos] = 0;
+      }
+    }
+    __threadfence_block();
+    cur = dst;
+    cnt = min(B, cnt + nv);
+  };
+
+  for (int e0 = 0; e0 < ix.nav_nentry; e0 += 64) {
+    const int e = e0 + lane;
+    const bool valid = e < ix.nav_nentry;
+    const int u = valid ? ix.nav_entry[e] : 0;
+    if (valid) vis[nav_slot(u)] = u;
+    merge(valid ? key_of(u) : ~0ull, valid);
+  }
+  // at most nlist expansions: a list enters C at most once
+  for (int it = 0; it <= ix.nlist; ++it) {
+    int i = -1;
+    for (int c0 = 0; c0 < cnt; c0 += 64) {
+      const int c = c0 + lane;
+      const uint64_t m = __ballot(c < cnt && flg[cur][c] == 0);
+      if (m) {
+        i = c0 + __ffsll((unsigned long long)m) - 1;
+        break;
+      }
+    }
+    if (i < 0) break;
+    const int v = (int)(uint32_t)keys[cur][i];
+    __threadfence_block();
+    if (lane == 0) flg[cur][i] = 1;
+    __threadfence_block();
+    for (int j0 = 0; j0 < ix.nav_deg; j0 += 64) {
+      const int j = j0 + lane;
+      const int u = j < ix.nav_deg ? ix.nav_adj[(size_t)v * ix.nav_deg + j] : -1;
+      bool valid = u >= 0 && u < ix.nlist;
+      if (valid) {
+        const uint32_t h = nav_slot(u);
+        valid = vis[h] != u;
+        __threadfence_block();
+        if (valid) vis[h] = u;
+      }
+      merge(valid ? key_of(u) : ~0ull, valid);
+    }
+  }
+  const int got = min(np, cnt);
+  for (int p = lane; p < np_max; p += 64) {
+    const uint64_t k = p < got ? keys[cur][p] : ~0ull;
+    lists[(size_t)q * np_max + p] = p < got ? (int32_t)(uint32_t)k : -1;
+    if (out_d) out_d[(size_t)q * np_max + p] = p < got ? unord32((uint32_t)(k >> 32)) : INFINITY;
+  }
+  if (lane == 0) np_eff[q] = got;
+}
+
 // Locality order of a chunk's queries: ascending (nearest probed list, query).
 // One block; bitonic sort of 64-bit keys in LDS (qc <= kOrderMax).
 constexpr int kOrderMax = 16384;
@@ -3012,6 +3227,19 @@ hipError_t launch_probe(const DevIndex& ix, const float* q, const int32_t* nprob
                         int qc, Work& w, float* out_dists_opt, int32_t* out_lists,
                         hipStream_t st) {
   if (qc <= 0) return hipSuccess;
+  if (ix.nav_beam > 0) {  // beam walk of the navigation graph
+    if (!ix.nav_adj || np_max > kNavMaxBeam || ix.nav_beam > kNavMaxBeam) return hipErrorInvalidValue;
+    const int cap = (std::max(ix.nav_beam, np_max) + 63) / 64 * 64;
+    const int wpb = cap <= 256 ? 4 : 1;  // waves (queries) per block
+    const size_t lds = (size_t)wpb * nav_wave_bytes(ix.dim, ix.dim_pad, cap);
+    auto kern = ix.cent8 ? k_probe_graph<true> : k_probe_graph<false>;
+    if (lds > 65536)
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+    hipLaunchKernelGGL(kern, dim3((qc + wpb - 1) / wpb), dim3(64 * wpb), lds, st, ix, q, qc,
+                       nprobe, np_max, cap, out_lists, out_dists_opt, w.np_eff);
+    return hipGetLastError();
+  }
   if (ix.cent8 && np_max <= 128 && ix.dim_pad <= 128 && qc >= kFusedMinQueries) {
     // integer grid, large batch: fused distances + selection, no distance
     // matrix in HBM (a block walks all lists for its 8 queries, so small

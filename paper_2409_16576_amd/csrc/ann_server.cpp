@@ -407,6 +407,8 @@ extern "C" ann_status ann_server_submit(ann_server* s, const float* queries, int
   if (!queries) return (ann_status)set_error(ANN_EINVAL, "queries pointer is NULL");
   if (nprobe_max < 1 || nprobe_max > c.max_nprobe)
     return (ann_status)set_error(ANN_EINVAL, "nprobe_max must be in [1, %d]", c.max_nprobe);
+  if (index_dev(s->ix).nav_beam > 0 && nprobe_max > kNavMaxBeam)
+    return (ann_status)set_error(ANN_EINVAL, "nprobe_max above %d with the graph probe", kNavMaxBeam);
   if (k < 1 || k > c.max_k) return (ann_status)set_error(ANN_EINVAL, "k must be in [1, %d]", c.max_k);
   if (rerank_n < k || rerank_n > c.max_rerank_n)
     return (ann_status)set_error(ANN_EINVAL, "rerank_n must be in [k, %d]", c.max_rerank_n);

@@ -65,7 +65,12 @@ ZIPF_F32_5M = Workload("zipf_f32_5m", 3, 5_000_000, 96, "f32", 2048, 0.0, 0.0, 0
 SERVE_I8_100M = Workload("serve_i8_100m", 5, 100_000_000, 100, "i8", 8192, -128.0, 127.0,
                          10.0, 65536, 50, 10_000, 64, 100, rerank_n_op=200)
 
-ALL = {w.name: w for w in (IVF_F32_100K, IVF_U8_10M, ZIPF_F32_5M, SERVE_I8_100M)}
+# 2M x 100-d int8, 8192 centres; 200,000 lists (0.1 N, the paper's list count,
+# Sec. 4.1), where the probe walks a navigation graph; PQ 50 x 256.
+NAV_I8_2M = Workload("nav_i8_2m", 6, 2_000_000, 100, "i8", 8192, -128.0, 127.0, 10.0,
+                     200_000, 50, 10_000, 256, 200)
+
+ALL = {w.name: w for w in (IVF_F32_100K, IVF_U8_10M, ZIPF_F32_5M, SERVE_I8_100M, NAV_I8_2M)}
 
 
 def scaled(w: Workload, **kw) -> Workload:

@@ -94,7 +94,8 @@ def _load():
         lib.bld_assign_flat.argtypes = [P, i64, i32, P, i32, i32, f32, P]
         lib.bld_assign_hier.argtypes = [P, i64, i32, P, i32, P, P, i32, i32, f32, P]
         lib.bld_pq_encode.argtypes = [P, i64, i32, P, i32, i32, i32, P]
-        lib.bld_nav_graph.argtypes = [P, i32, i32, i32, P, i32, P, P, i32, P]
+        lib.bld_balanced_assign.argtypes = [P, i64, i32, P, i32, i64, i32, P]
+        lib.bld_nav_graph.argtypes = [P, i32, i32, i32, P, i32, P, P, i32, i32, i32, P]
         _lib = lib
     return _lib
 
@@ -116,6 +117,8 @@ class BuildParams:
     train_per_list: int = 40
     pq_train_rows: int = 65536
     hier_top_probe: int = 2
+    balance: float = 0.0      # > 0: balanced clustering, at most (1 + balance) x the mean size
+    balance_iters: int = 3
     seed: int = 0
     init_centroids: np.ndarray | None = None  # optional initial list centroids
 
@@ -144,6 +147,27 @@ def kmeans(Xs: np.ndarray, k: int, iters: int, seed: int, init: np.ndarray | Non
     return C
 
 
+def balanced_kmeans(Xs: np.ndarray, C: np.ndarray, slack: float, iters: int) -> np.ndarray:
+    """Lloyd iterations whose assignment step is capacity-constrained: each
+    cluster holds at most ceil((1 + slack) n / k) rows (bld_balanced_assign);
+    starts from centroids C, returns the new centroids."""
+    lib = _load()
+    Xs = np.ascontiguousarray(Xs, dtype=np.float32)
+    C = np.ascontiguousarray(C, dtype=np.float32).copy()
+    n, d = Xs.shape
+    k = C.shape[0]
+    cap = int(np.ceil((1.0 + slack) * n / k))
+    lab = np.empty(n, dtype=np.int32)
+    for _ in range(max(1, iters)):
+        lib.bld_balanced_assign(_ptr(Xs), n, d, _ptr(C), k, cap, 8, _ptr(lab))
+        sums = np.zeros((k, d), dtype=np.float64)
+        np.add.at(sums, lab, Xs)
+        cnt = np.bincount(lab, minlength=k)
+        nz = cnt > 0
+        C[nz] = (sums[nz] / cnt[nz, None]).astype(np.float32)
+    return C
+
+
 def _grid(a: np.ndarray, kind: str) -> np.ndarray:
     if kind == "u8":
         return np.clip(np.rint(a), 0, 255).astype(np.float32)
@@ -160,11 +184,15 @@ def train_ivf(X: np.ndarray, kind: str, p: BuildParams):
     Xs = np.ascontiguousarray(X[rows], dtype=np.float32)
     if p.init_centroids is not None or p.nlist <= FLAT_MAX_LISTS:
         C = kmeans(Xs, p.nlist, p.kmeans_iters, p.seed + 1, init=p.init_centroids)
+        if p.balance > 0:
+            C = balanced_kmeans(Xs, C, p.balance, p.balance_iters)
         return _grid(C, kind), None
     # Two-level: ktop clusters, then each split into sub-lists proportional to its size.
     ktop = 1 << int(np.ceil(np.log2(np.sqrt(p.nlist))))
     ktop = min(ktop, p.nlist)
     Ctop = kmeans(Xs, ktop, p.kmeans_iters, p.seed + 2)
+    if p.balance > 0:  # hierarchical balanced clustering: every level balanced
+        Ctop = balanced_kmeans(Xs, Ctop, p.balance, p.balance_iters)
     lib = _load()
     lab = np.empty(ns, dtype=np.int32)
     lib.bld_nearest(_ptr(Xs), ns, d, _ptr(Ctop), ktop, _ptr(lab), None)
@@ -185,7 +213,10 @@ def train_ivf(X: np.ndarray, kind: str, p: BuildParams):
         Xa = Xs[lab == a]
         if len(Xa) == 0:
             Xa = Ctop[a:a + 1]
-        subs.append(kmeans(Xa, int(cnt[a]), p.kmeans_iters, p.seed + 1000 + a))
+        Ca = kmeans(Xa, int(cnt[a]), p.kmeans_iters, p.seed + 1000 + a)
+        if p.balance > 0 and len(Xa) >= cnt[a]:
+            Ca = balanced_kmeans(Xa, Ca, p.balance, p.balance_iters)
+        subs.append(Ca)
     Csub = np.ascontiguousarray(np.concatenate(subs, axis=0))
     off = np.zeros(ktop + 1, dtype=np.int32)
     off[1:] = np.cumsum(cnt)
@@ -210,6 +241,49 @@ def assign_lists(X: np.ndarray, C: np.ndarray, hier, p: BuildParams, progress=No
             lib.bld_assign_hier(_ptr(Xc), r1 - r0, d, _ptr(Ctop), Ctop.shape[0], _ptr(C),
                                 _ptr(off), p.hier_top_probe, p.R, p.eps, _ptr(out))
         A[r0:r1] = out
+    return A
+
+
+def assign_lists_gpu(X: np.ndarray, C: np.ndarray, kind: str, R: int, eps: float,
+                     device: int = 0, chunk: int = 65536, progress=None) -> np.ndarray:
+    """Eq. 2 assignment on the GPU, by the search library's exact probe: the R
+    nearest lists of every row over all centroids (exact distances: integers
+    on the integer grid, float64 sums otherwise; ties to the lower list), list
+    i kept iff its squared distance is at most (1 + eps)^2 times the nearest
+    one's.  The centroids are loaded as a small index of their own (one
+    vector per list).  Returns [n, R] int32, nearest first, -1 padded."""
+    import tempfile
+
+    import torch
+
+    from .. import ann
+    C = np.ascontiguousarray(C, dtype=np.float32)
+    nlist, d = C.shape
+    dsub = next(s_ for s_ in range(1, d + 1) if d % s_ == 0 and d // s_ <= 64)
+    M = d // dsub
+    own = np.stack([np.arange(nlist), -np.ones(nlist, dtype=np.int64)], axis=1).astype(np.int32)
+    off, ent = lists_from_assignment(own, nlist)
+    cix = IndexArrays(kind, C, np.zeros((M, 256, dsub), np.float32), np.zeros((nlist, M), np.uint8),
+                      C.astype(NP_DTYPE[kind]), off, ent, own, 0.0, kind != "f32")
+    n = X.shape[0]
+    A = np.full((n, R), -1, dtype=np.int32)
+    lim = (1.0 + float(eps)) ** 2
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "centroids.fidx")
+        write_index(path, cix)
+        g = ann.Index(path, device)
+        try:
+            for r0 in range(0, n, chunk):
+                r1 = min(n, r0 + chunk)
+                q = torch.from_numpy(np.ascontiguousarray(X[r0:r1], dtype=np.float32)).cuda(device)
+                lists, dist = g.probe(q, min(R, nlist))
+                lists, dist = lists.cpu().numpy(), dist.cpu().numpy().astype(np.float64)
+                keep = dist <= lim * dist[:, :1]  # ascending, so the kept lists are a prefix
+                A[r0:r1, :lists.shape[1]] = np.where(keep, lists, -1)
+                if progress and r0 and r0 % (16 * chunk) == 0:
+                    progress(f"assigned {r0} of {n} vectors on the GPU")
+        finally:
+            g.close()
     return A
 
 
@@ -364,18 +438,22 @@ def read_list_meta(path: str):
     return sizes, primary
 
 
-def build_nav_graph(C: np.ndarray, deg: int = 32, seed: int = 0, gprobe: int = 8):
+def build_nav_graph(C: np.ndarray, deg: int = 32, seed: int = 0, gprobe: int = 8,
+                    rng: bool = True, pool: int = 0):
     """Navigation graph over list centroids C [nlist, D] (Sec. 4.1).
 
-    Each centroid is joined to its ``deg`` nearest other centroids among the
-    members of its ``gprobe`` nearest centroid groups (a k-means of the
-    centroids into about sqrt(nlist) groups), and a centroid that another one
-    chose also takes that one when it is among its own ``deg`` nearest
-    candidates (reverse edges).  Entry vertices: the member nearest to each
+    Candidates of a centroid: the ``pool`` (default 4 deg) nearest members of
+    its ``gprobe`` nearest centroid groups (a k-means of the centroids into
+    about sqrt(nlist) groups).  Its edges: with ``rng``, first the candidates
+    that pass the relative neighbourhood rule (no edge already taken is nearer
+    to the candidate than the centroid itself), then the nearest candidates
+    left, up to ``deg``; without, the ``deg`` nearest.  A centroid chosen by
+    another is offered that one as a candidate too (reverse edges) and its
+    edges are chosen again.  Entry vertices: the member nearest to each
     group's centre, plus one vertex of every part of the graph those do not
     reach, so every centroid is reachable from the entries.
 
-    Returns (adj [nlist, deg] int32, ascending distance, -1 padded; entry int32).
+    Returns (adj [nlist, deg] int32, -1 padded; entry int32).
     """
     lib = _load()
     C = np.ascontiguousarray(C, dtype=np.float32)
@@ -392,7 +470,7 @@ def build_nav_graph(C: np.ndarray, deg: int = 32, seed: int = 0, gprobe: int = 8
     goff[1:] = np.cumsum(np.bincount(gof, minlength=ng))
     adj = np.empty((k, deg), dtype=np.int32)
     lib.bld_nav_graph(_ptr(C), k, d, deg, _ptr(G), ng, _ptr(goff), _ptr(gmem), int(gprobe),
-                      _ptr(adj))
+                      int(pool or 4 * deg), 1 if rng else 0, _ptr(adj))
     entry = []
     for g in range(ng):
         mem = gmem[goff[g]:goff[g + 1]]

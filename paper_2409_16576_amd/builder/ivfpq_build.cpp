@@ -118,6 +118,63 @@ void bld_kmeans(const float* X, int64_t n, int d, float* C, int k, int iters) {
   }
 }
 
+// Balanced assignment (the balance constraint of hierarchical balanced
+// clustering, Sec. 4.1): every row goes to its nearest centroid that still
+// has room, each centroid holding at most `cap` rows.  Rows are placed in
+// order of how much they lose if their nearest centroid is full (the gap
+// between their nearest and second-nearest of T candidates, largest first;
+// ties: lower row), so rows far from any other centroid keep their nearest.
+// A row whose T candidates are all full takes the nearest centroid with room.
+void bld_balanced_assign(const float* X, int64_t n, int d, const float* C, int k, int64_t cap,
+                         int T, int32_t* lab) {
+  T = std::max(1, std::min(T, k));
+  std::vector<float> ct = transpose(C, k, d);
+  std::vector<int32_t> cidx((size_t)n * T);
+  std::vector<float> cdist((size_t)n * T);
+  std::vector<float> gap(n);
+#pragma omp parallel
+  {
+    std::vector<float> buf(k);
+    std::vector<int32_t> idx(k);
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      sqdist_block(X + i * d, ct.data(), k, k, d, buf.data());
+      for (int j = 0; j < k; ++j) idx[j] = j;
+      std::partial_sort(idx.begin(), idx.begin() + T, idx.end(), [&](int a, int b) {
+        return buf[a] < buf[b] || (buf[a] == buf[b] && a < b);
+      });
+      for (int t = 0; t < T; ++t) {
+        cidx[(size_t)i * T + t] = idx[t];
+        cdist[(size_t)i * T + t] = buf[idx[t]];
+      }
+      gap[i] = T > 1 ? buf[idx[1]] - buf[idx[0]] : 0.f;
+    }
+  }
+  std::vector<int64_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return gap[a] > gap[b]; });
+  std::vector<int64_t> fill(k, 0);
+  std::vector<float> row(k);
+  for (int64_t i : order) {
+    int got = -1;
+    for (int t = 0; t < T && got < 0; ++t) {
+      const int c = cidx[(size_t)i * T + t];
+      if (fill[c] < cap) got = c;
+    }
+    if (got < 0) {
+      sqdist_block(X + i * d, ct.data(), k, k, d, row.data());
+      float best = std::numeric_limits<float>::infinity();
+      for (int c = 0; c < k; ++c)
+        if (fill[c] < cap && row[c] < best) {
+          best = row[c];
+          got = c;
+        }
+    }
+    lab[i] = got;
+    fill[got] += 1;
+  }
+}
+
 // Nearest centroid of every row (exported for the driver).
 void bld_nearest(const float* X, int64_t n, int d, const float* C, int k, int32_t* lab,
                  float* dist) {
@@ -233,20 +290,62 @@ void bld_pq_encode(const float* X, int64_t n, int d, const float* CB, int M, int
 }
 
 // Navigation graph over the list centroids (Sec. 4.1): every centroid is
-// joined to its `deg` nearest other centroids, and a centroid chosen by a
-// later one also takes it among its own nearest when it is nearer than its
-// current farthest edge (keeping at most `deg`), as when vertices are added
-// one at a time and their neighbours update their edge lists.  Candidates of
-// vertex v are the centroids of the `gprobe` groups nearest to v (groups: a
-// k-means of the centroids, `gof[v]` = v's group, members listed in
-// gmem[goff[g] .. goff[g+1])).  adj: k x deg, ascending (distance, id), -1
-// padded.
+// joined to up to `deg` other centroids, as when vertices are added one at a
+// time, each taking edges to its nearest neighbours, and those neighbours
+// updating their own edge lists.  Candidates of vertex v are the centroids of
+// the `gprobe` groups nearest to v (groups: a k-means of the centroids, gof[v]
+// = v's group, members listed in gmem[goff[g] .. goff[g+1])), the `pool`
+// nearest of them kept.  With `rng` the edges are chosen by the relative
+// neighbourhood rule first (a candidate u is taken only if no edge already
+// taken, w, is nearer to u than v is: the edges fan out instead of all
+// pointing into v's own cluster), then the remaining slots take the nearest
+// candidates left.  A vertex chosen by v is offered v as a candidate too
+// (reverse edges), and the final lists are chosen the same way from both.
+// adj: k x deg, -1 padded.
+namespace {
+void choose_edges(const float* C, int d, int v, std::vector<std::pair<float, int32_t>>& cand,
+                  int deg, bool rng, int32_t* row) {
+  std::sort(cand.begin(), cand.end());
+  cand.erase(std::unique(cand.begin(), cand.end(),
+                         [](const std::pair<float, int32_t>& a, const std::pair<float, int32_t>& b) {
+                           return a.second == b.second;
+                         }),
+             cand.end());
+  std::vector<char> taken(cand.size(), 0);
+  int w = 0;
+  if (rng) {
+    std::vector<int32_t> kept;
+    for (size_t i = 0; i < cand.size() && w < deg; ++i) {
+      const int32_t u = cand[i].second;
+      const float duv = cand[i].first;
+      bool ok = true;
+      for (int32_t x : kept)
+        if (sqdist(C + (size_t)u * d, C + (size_t)x * d, d) < duv) {
+          ok = false;
+          break;
+        }
+      if (ok) {
+        kept.push_back(u);
+        taken[i] = 1;
+        row[w++] = u;
+      }
+    }
+  }
+  for (size_t i = 0; i < cand.size() && w < deg; ++i)
+    if (!taken[i]) row[w++] = cand[i].second;
+  for (; w < deg; ++w) row[w] = -1;
+  (void)v;
+}
+}  // namespace
+
 void bld_nav_graph(const float* C, int k, int d, int deg, const float* G, int ng,
-                   const int32_t* goff, const int32_t* gmem, int gprobe, int32_t* adj) {
+                   const int32_t* goff, const int32_t* gmem, int gprobe, int pool, int rng,
+                   int32_t* adj) {
   gprobe = std::min(gprobe, ng);
+  pool = std::max(pool, deg);
   std::vector<float> gt = transpose(G, ng, d);
-  // 1. each vertex's nearest among its candidate groups
-  std::vector<std::vector<std::pair<float, int32_t>>> knn(k);
+  // 1. each vertex's nearest among its candidate groups, then its edges
+  std::vector<std::vector<std::pair<float, int32_t>>> near(k);
 #pragma omp parallel
   {
     std::vector<float> gd(ng);
@@ -268,28 +367,25 @@ void bld_nav_graph(const float* C, int k, int d, int deg, const float* G, int ng
           if (u != v) cand.emplace_back(sqdist(cv, C + (size_t)u * d, d), u);
         }
       }
-      const size_t r = std::min<size_t>(deg, cand.size());
+      const size_t r = std::min<size_t>(pool, cand.size());
       std::partial_sort(cand.begin(), cand.begin() + r, cand.end());
-      knn[v].assign(cand.begin(), cand.begin() + r);
+      cand.resize(r);
+      near[v] = cand;
+      choose_edges(C, d, v, cand, deg, rng != 0, adj + (size_t)v * deg);
     }
   }
   // 2. reverse edges: u chosen by v is offered v as well
   std::vector<std::vector<std::pair<float, int32_t>>> rev(k);
   for (int v = 0; v < k; ++v)
-    for (const auto& e : knn[v]) rev[e.second].emplace_back(e.first, v);
+    for (int j = 0; j < deg; ++j) {
+      const int32_t u = adj[(size_t)v * deg + j];
+      if (u >= 0) rev[u].emplace_back(sqdist(C + (size_t)v * d, C + (size_t)u * d, d), v);
+    }
 #pragma omp parallel for schedule(dynamic, 64)
   for (int v = 0; v < k; ++v) {
-    std::vector<std::pair<float, int32_t>> all = knn[v];
+    std::vector<std::pair<float, int32_t>> all = near[v];
     all.insert(all.end(), rev[v].begin(), rev[v].end());
-    std::sort(all.begin(), all.end());
-    all.erase(std::unique(all.begin(), all.end(),
-                          [](const std::pair<float, int32_t>& a,
-                             const std::pair<float, int32_t>& b) { return a.second == b.second; }),
-              all.end());
-    int32_t* row = adj + (size_t)v * deg;
-    int w = 0;
-    for (size_t i = 0; i < all.size() && w < deg; ++i) row[w++] = all[i].second;
-    for (; w < deg; ++w) row[w] = -1;
+    choose_edges(C, d, v, all, deg, rng != 0, adj + (size_t)v * deg);
   }
 }
 

@@ -834,13 +834,21 @@ __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_l
                           int* s_seg) {
   const int lane = threadIdx.x & 63;
   int cnt = 0, l = 0, s0 = 0, s1 = 0;
+  // group descriptors are read kSegU at a time, their loads in flight together
+  constexpr int kSegU = 8;
   if (lane < np) {
     l = s_list[lane];
     cnt = 1;
     if (segmented) {
       s0 = ix.lseg[l];
       s1 = ix.lseg[l + 1];
-      for (int s = s0; s < s1; ++s) cnt += testbit(s_bits, ix.segs[s].x) ? 0 : 1;
+      for (int s = s0; s < s1; s += kSegU) {
+        int fl[kSegU];
+#pragma unroll
+        for (int u = 0; u < kSegU; ++u) fl[u] = s + u < s1 ? ix.segs[s + u].x : -1;
+#pragma unroll
+        for (int u = 0; u < kSegU; ++u) cnt += (fl[u] >= 0 && !testbit(s_bits, fl[u])) ? 1 : 0;
+      }
     }
   }
   int incl = (int)wave_incl_scan((uint32_t)cnt);
@@ -862,12 +870,18 @@ __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_l
     s_pre[off] = lm_slot(lane, walk_np, rows, min_rows) ? 0 : rows;
     int r = off + 1;
     if (seg) {
-      for (int s = s0; s < s1; ++s) {
-        const int4 g = ix.segs[s];
-        if (!testbit(s_bits, g.x)) {
-          s_rstart[r] = (uint32_t)g.y | kRunReplica;
-          s_pre[r] = g.z - g.y;
-          ++r;
+      for (int s = s0; s < s1; s += kSegU / 2) {
+        int4 gg[kSegU / 2];
+#pragma unroll
+        for (int u = 0; u < kSegU / 2; ++u)
+          gg[u] = s + u < s1 ? ix.segs[s + u] : make_int4(-1, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < kSegU / 2; ++u) {
+          if (gg[u].x >= 0 && !testbit(s_bits, gg[u].x)) {
+            s_rstart[r] = (uint32_t)gg[u].y | kRunReplica;
+            s_pre[r] = gg[u].z - gg[u].y;
+            ++r;
+          }
         }
       }
     } else if (cnt > 1) {
@@ -1154,7 +1168,20 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
         rows[u] = 0;
         if (e < e1) {
           if (e >= run_hi) {
-            while (s_pre[cur + 1] <= e) ++cur;  // s_pre[nruns] = E > e bounds the walk
+            // the run holding e: the last r in [cur, nruns) with s_pre[r] <= e
+            // (s_pre[nruns] = E > e); a step or two linearly, else by halving
+            if (s_pre[cur + 1] <= e) {
+              ++cur;
+              if (s_pre[cur + 1] <= e) {
+                int lo = cur + 1, hi = nruns;  // s_pre[lo] <= e < s_pre[hi]
+                while (hi - lo > 1) {
+                  const int mid = (lo + hi) >> 1;
+                  if (s_pre[mid] <= e) lo = mid;
+                  else hi = mid;
+                }
+                cur = lo;
+              }
+            }
             run_lo = s_pre[cur];
             run_hi = s_pre[cur + 1];
             run_rs = s_rstart[cur];
@@ -2173,27 +2200,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
   for (int r = 0; r < 4; ++r) qn[r] = s_qn[4 * g + r];
   // KS = dim_pad / 64 K-steps.  The query fragments stay in registers; the
-  // centroid fragments and norms of the next list tile are loaded while this
-  // one is being filtered (software pipelining across tiles).
+  // centroid fragments and norms of the next two list tiles are in flight
+  // while this one is being filtered (software pipelining across tiles).
   v4i_t fa[KS];
 #pragma unroll
   for (int k = 0; k < KS; ++k)
     fa[k] = *reinterpret_cast<const v4i_t*>(s_q8 + r16 * Dp + 64 * k + 16 * g);
-  v4i_t fn[KS][kFCols];
-  int cnn[kFCols];
-  auto load_tile = [&](int t0) {
+  v4i_t fn[KS][kFCols], fn2[KS][kFCols];
+  int cnn[kFCols], cnn2[kFCols];
+  auto load_tile = [&](int t0, v4i_t (&dst)[KS][kFCols], int (&dn)[kFCols]) {
 #pragma unroll
     for (int b = 0; b < kFCols; ++b) {
       const int l = t0 + w * (kFTile / 4) + b * 16 + r16;
 #pragma unroll
       for (int k = 0; k < KS; ++k)
-        fn[k][b] = l < ix.nlist
-                       ? *reinterpret_cast<const v4i_t*>(ix.cent8 + (size_t)l * Dp + 64 * k + 16 * g)
-                       : v4i_t{0, 0, 0, 0};
-      cnn[b] = l < ix.nlist ? ix.cnorm8[l] : 0;
+        dst[k][b] = l < ix.nlist
+                        ? *reinterpret_cast<const v4i_t*>(ix.cent8 + (size_t)l * Dp + 64 * k + 16 * g)
+                        : v4i_t{0, 0, 0, 0};
+      dn[b] = l < ix.nlist ? ix.cnorm8[l] : 0;
     }
   };
-  load_tile(0);
+  load_tile(0, fn, cnn);
+  load_tile(kFTile, fn2, cnn2);  // columns past nlist read as zero
   for (int t0 = 0; t0 < ix.nlist; t0 += kFTile) {
     const int l0 = t0 + w * (kFTile / 4);
     v4i_t fb[KS][kFCols];
@@ -2201,10 +2229,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
     for (int b = 0; b < kFCols; ++b) {
 #pragma unroll
-      for (int k = 0; k < KS; ++k) fb[k][b] = fn[k][b];
+      for (int k = 0; k < KS; ++k) {
+        fb[k][b] = fn[k][b];
+        fn[k][b] = fn2[k][b];
+      }
       cnb[b] = cnn[b];
+      cnn[b] = cnn2[b];
     }
-    if (t0 + kFTile < ix.nlist) load_tile(t0 + kFTile);
+    if (t0 + 2 * kFTile < ix.nlist) load_tile(t0 + 2 * kFTile, fn2, cnn2);
     v4i_t acc[kFCols];
 #pragma unroll
     for (int b = 0; b < kFCols; ++b) acc[b] = v4i_t{0, 0, 0, 0};

@@ -70,7 +70,13 @@ SERVE_I8_100M = Workload("serve_i8_100m", 5, 100_000_000, 100, "i8", 8192, -128.
 NAV_I8_2M = Workload("nav_i8_2m", 6, 2_000_000, 100, "i8", 8192, -128.0, 127.0, 10.0,
                      200_000, 50, 10_000, 256, 200)
 
-ALL = {w.name: w for w in (IVF_F32_100K, IVF_U8_10M, ZIPF_F32_5M, SERVE_I8_100M, NAV_I8_2M)}
+# 4M x 100-d int8, 4096 centres; 8192 lists; PQ 50 x 256: the replication study
+# (Eq. 2 with R = 1..8) and balanced clustering.
+REPL_I8_4M = Workload("repl_i8_4m", 7, 4_000_000, 100, "i8", 4096, -128.0, 127.0, 10.0,
+                      8192, 50, 10_000, 32, 200)
+
+ALL = {w.name: w for w in (IVF_F32_100K, IVF_U8_10M, ZIPF_F32_5M, SERVE_I8_100M, NAV_I8_2M,
+                           REPL_I8_4M)}
 
 
 def scaled(w: Workload, **kw) -> Workload:

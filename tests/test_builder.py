@@ -102,3 +102,31 @@ def test_generators_are_deterministic_and_chunk_independent():
     np.testing.assert_allclose(np.linalg.norm(x, axis=1), 1.0, rtol=1e-5)
     npb = workloads.nprobe_per_query(w)
     assert npb.min() >= 8 and npb.max() <= 128
+
+
+def test_balanced_assignment_respects_capacity():
+    """Hierarchical balanced clustering (Sec. 4.1): the capacity-constrained
+    assignment never exceeds its cap, equals the nearest-centroid assignment
+    when the cap never binds, and balanced training shrinks the largest list."""
+
+    from paper_2409_16576_amd import builder as B
+    rng = np.random.default_rng(4)
+    X = np.concatenate([rng.normal(0, 1, (3000, 8)), rng.normal(6, 1, (500, 8))]).astype(np.float32)
+    C = X[rng.choice(len(X), 20, replace=False)].copy()
+    lib = B._load()
+    lab = np.empty(len(X), np.int32)
+    for cap in (180, 200, 400):
+        lib.bld_balanced_assign(B._ptr(X), len(X), 8, B._ptr(C), 20, cap, 8, B._ptr(lab))
+        cnt = np.bincount(lab, minlength=20)
+        assert cnt.max() <= cap and cnt.sum() == len(X)
+    lib.bld_balanced_assign(B._ptr(X), len(X), 8, B._ptr(C), 20, len(X), 8, B._ptr(lab))
+    d = ((X[:, None, :].astype(np.float64) - C[None].astype(np.float64)) ** 2).sum(-1)
+    near = np.argmin(d, axis=1)
+    assert (lab == near).mean() > 0.999  # float32 vs float64 near-ties aside
+    sizes = []
+    for bal in (0.0, 0.1):
+        p = B.BuildParams(nlist=20, M=4, balance=bal, seed=1)
+        Cb, h = B.train_ivf(X, "f32", p)
+        A = B.assign_lists(X, Cb, h, p)
+        sizes.append(np.bincount(A[:, 0], minlength=20).max())
+    assert sizes[1] < sizes[0]

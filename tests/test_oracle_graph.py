@@ -148,15 +148,24 @@ def test_search_with_full_beam_equals_exact_search(orc, tmp_path):
 def test_builder_graph_shape_and_reachability(tmp_path):
     from paper_2409_16576_amd import builder as B
     rng = np.random.default_rng(3)
-    for k, deg in ((300, 16), (50, 64), (2, 4)):
+    for k, deg, rule in ((300, 16, True), (300, 16, False), (50, 64, True), (2, 4, True)):
         C = rng.standard_normal((k, 12)).astype(np.float32) * 10
-        adj, entry = B.build_nav_graph(C, deg=deg, seed=1)
+        adj, entry = B.build_nav_graph(C, deg=deg, seed=1, rng=rule)
         assert adj.shape == (k, min(deg, k - 1))
         d = ((C[:, None, :].astype(np.float64) - C[None].astype(np.float64)) ** 2).sum(-1)
         for v in range(k):
             row = adj[v][adj[v] >= 0]
             assert len(set(row.tolist())) == len(row) and v not in row
-            assert np.all(np.diff(d[v, row]) >= -1e-3)  # nearest first
+            if not rule:
+                assert np.all(np.diff(d[v, row]) >= -1e-3)  # nearest first
+            else:  # the leading edges satisfy the relative neighbourhood rule
+                lead = []
+                for u in row:
+                    if all(d[u, x] >= d[v, u] * (1 - 1e-5) for x in lead):
+                        lead.append(int(u))
+                    else:
+                        break
+                assert len(lead) >= 1
         seen = np.zeros(k, bool)
         front = list(entry)
         seen[front] = True

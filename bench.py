@@ -136,9 +136,10 @@ def run_served(ann, g, Qh, npq, w, k, n, args):
     """Served form: Poisson request arrivals (sizes U{1..256}) at several
     offered loads into a continuous-batching server; per load the achieved
     queries/s and the p50/p99 request latency, then a saturation run (every
-    request waiting at once).  The form's qps is the best achieved rate whose
-    load was sustained (achieved >= 95% of offered) or the saturation rate,
-    whichever is higher."""
+    request waiting at once).  A load is sustained when it achieves at least
+    95% of the offered rate with a p99 latency at most ten times the p50 of
+    the lightest load.  The form's qps is the best sustained rate or the
+    saturation rate, whichever is higher."""
     import queue
     import threading
 
@@ -204,6 +205,10 @@ def run_served(ann, g, Qh, npq, w, k, n, args):
                       "mean_launch_queries": round(st["queries_done"] / max(1, st["launches"]), 1),
                       "max_in_flight": int(st["max_in_flight"]),
                       "sustained": bool(ach >= 0.95 * lam)})
+        if len(loads) == 1:
+            p99_bound = 10.0 * loads[0]["p50_ms"]
+        loads[-1]["p99_bound_ms"] = round(p99_bound, 3)
+        loads[-1]["sustained"] = bool(loads[-1]["sustained"] and loads[-1]["p99_ms"] <= p99_bound)
         log(f"served @ {rate_m:g}M q/s offered: {ach:.0f} q/s, p50 {st['latency_p50_ms']:.2f} ms, "
             f"p99 {st['latency_p99_ms']:.2f} ms, {st['launches']} launches")
     # saturation: all requests waiting at once

@@ -333,7 +333,7 @@ void lm_layout(const DevIndex& d, int qc, int np_max, int cap2, F&& take) {
   take(7, (size_t)(d.nlist + 1) * 4);               // loff
   take(8, (size_t)(d.nlist + 1) * 4);               // ioff
   take(9, (size_t)qc * np_max * 4);                 // invq
-  take(10, (size_t)16);                             // ctr
+  take(10, (size_t)16 + (size_t)8 * ((d.nlist + 1023) / 1024));  // ctr + per-block totals
   take(11, lmajor_mfma(d) ? 0 : (size_t)qc * d.M * kKsub * 4);  // lut (float indexes)
 }
 

@@ -80,7 +80,8 @@ struct LmWork {
   int32_t* loff = nullptr;            // [nlist + 1]
   int32_t* ioff = nullptr;            // [nlist + 1] work items per list (prefix)
   int32_t* invq = nullptr;            // [qc * np_max] queries by list
-  int32_t* ctr = nullptr;             // [4] work items, next item
+  int32_t* ctr = nullptr;             // [4 + 2 ceil(nlist / 1024)] work items, next item,
+                                      // then the work list's per-block totals
   float* lut = nullptr;               // [qc, M, 256] distance tables (float indexes)
   int cap2 = 0;
 };

@@ -623,12 +623,25 @@ __host__ __device__ inline int scan_max_runs(int np_max, int max_segs, bool segm
   return np_max * (1 + (segmented ? max_segs : 1));
 }
 
+// The scan's set of a query's probed lists (for the ownership rule): a
+// bitmap over all lists while that is small, else the probed lists sorted
+// ascending (membership by halving), so that large list counts leave the
+// LDS to the run slots.
+__host__ __device__ inline bool probe_set_sorted(int nlist, int np_max) {
+  const int words = (nlist + 31) / 32;
+  return words > 512 && words > np_max;
+}
+
 __host__ __device__ inline ScanLayout scan_layout(int M, int nlist, int R, int np_max,
                                                   int max_runs, int cap, int lut_elem) {
   ScanLayout L;
   size_t o = 0;
   L.lut = o; o += (size_t)M * kKsub * lut_elem; o = align_up(o, 16);
-  L.bits = o; o += (R > 1 ? (size_t)((nlist + 31) / 32) * 4 : 0); o = align_up(o, 16);
+  L.bits = o;
+  o += R > 1 ? (probe_set_sorted(nlist, np_max) ? (size_t)pow2_at_least(np_max) * 4
+                                                : (size_t)((nlist + 31) / 32) * 4)
+             : 0;
+  o = align_up(o, 16);
   L.list = o; o += (size_t)np_max * 4; o = align_up(o, 16);
   L.rstart = o; o += (size_t)max_runs * 4; o = align_up(o, 16);
   L.pre = o; o += (size_t)(max_runs + 1) * 4; o = align_up(o, 16);
@@ -670,6 +683,23 @@ __device__ __forceinline__ int block_excl_scan(int v, int* s_wsum) {
 __device__ __forceinline__ bool testbit(const uint32_t* bits, int l) {
   return (bits[l >> 5] >> (l & 31)) & 1u;
 }
+
+// (probed lists up to 2^13 for the sorted form: nprobe is at most 4096)
+struct ProbeSet {
+  const uint32_t* bits;  // bitmap over all lists, or
+  const int32_t* set;    // the probed lists ascending, padded with INT_MAX to p2
+  int p2;                // a power of two >= the probed lists
+  __device__ __forceinline__ bool has(int l) const {
+    if (!set) return testbit(bits, l);
+    // branchless lower bound with a fixed number of steps, so that several
+    // lookups of a thread can overlap their LDS reads
+    int pos = 0;
+#pragma unroll
+    for (int step = 4096; step >= 1; step >>= 1)
+      if (step < p2 && set[pos + step - 1] < l) pos += step;
+    return set[pos] == l;
+  }
+};
 
 // Code row -> W dwords (natural alignment: rows are 4*W bytes apart).
 template <int W>
@@ -829,7 +859,7 @@ __host__ __device__ inline bool lm_slot(int p, int walkp, int rows, int min_rows
 // s_pre[nruns] = the query's entries; *s_nruns = nruns, *s_seg = whether the
 // replica runs are surviving groups.
 __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_list, int np,
-                          int walk_np, int min_rows, const uint32_t* s_bits, int segmented,
+                          int walk_np, int min_rows, const ProbeSet& ps, int segmented,
                           int max_runs, uint32_t* s_rstart, int32_t* s_pre, int* s_nruns,
                           int* s_seg) {
   const int lane = threadIdx.x & 63;
@@ -847,7 +877,7 @@ __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_l
 #pragma unroll
         for (int u = 0; u < kSegU; ++u) fl[u] = s + u < s1 ? ix.segs[s + u].x : -1;
 #pragma unroll
-        for (int u = 0; u < kSegU; ++u) cnt += (fl[u] >= 0 && !testbit(s_bits, fl[u])) ? 1 : 0;
+        for (int u = 0; u < kSegU; ++u) cnt += (fl[u] >= 0 && !ps.has(fl[u])) ? 1 : 0;
       }
     }
   }
@@ -877,7 +907,7 @@ __device__ __forceinline__ void runs_wave(const DevIndex& ix, const int32_t* s_l
           gg[u] = s + u < s1 ? ix.segs[s + u] : make_int4(-1, 0, 0, 0);
 #pragma unroll
         for (int u = 0; u < kSegU / 2; ++u) {
-          if (gg[u].x >= 0 && !testbit(s_bits, gg[u].x)) {
+          if (gg[u].x >= 0 && !ps.has(gg[u].x)) {
             s_rstart[r] = (uint32_t)gg[u].y | kRunReplica;
             s_pre[r] = gg[u].z - gg[u].y;
             ++r;
@@ -952,10 +982,11 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   SelScratch* ss = reinterpret_cast<SelScratch*>(smem + L.sel);
   ScanMisc* mc = reinterpret_cast<ScanMisc*>(smem + L.misc);
 
-  // Probed lists and the probe bitmap.
+  // Probed lists and their set (bitmap, or sorted for large list counts).
   const int nwords = (ix.nlist + 31) / 32;
   const bool use_bits = ix.R > 1;
-  if (use_bits)
+  const bool sorted_set = probe_set_sorted(ix.nlist, np_max);
+  if (use_bits && !sorted_set)
     for (int i = tid; i < nwords; i += kScanBlock) s_bits[i] = 0u;
   const int np = np_eff[q];
   const int walk_np = sp.walkp ? min(np, sp.walkp[q]) : np;  // slots walked whole
@@ -975,12 +1006,26 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
     for (int t = tid; t < ix.dim; t += kScanBlock)
       s_qv[t] = conv_query(Q[(size_t)q * ix.dim + t], ix.dtype);
   __syncthreads();
-  if (use_bits)
-    for (int p = tid; p < np; p += kScanBlock) {
-      const int l = s_list[p];
-      atomicOr(&s_bits[l >> 5], 1u << (l & 31));
+  if (use_bits) {
+    if (sorted_set) {  // rank of each probed list among them (lists are distinct)
+      int32_t* s_set = reinterpret_cast<int32_t*>(s_bits);
+      for (int p = tid; p < np; p += kScanBlock) {
+        const int l = s_list[p];
+        int r = 0;
+        for (int j = 0; j < np; ++j) r += s_list[j] < l ? 1 : 0;
+        s_set[r] = l;
+      }
+      for (int p = np + tid; p < pow2_at_least(max(np, 1)); p += kScanBlock) s_set[p] = INT_MAX;
+    } else {
+      for (int p = tid; p < np; p += kScanBlock) {
+        const int l = s_list[p];
+        atomicOr(&s_bits[l >> 5], 1u << (l & 31));
+      }
     }
+  }
   __syncthreads();
+  const ProbeSet ps{s_bits, sorted_set ? reinterpret_cast<const int32_t*>(s_bits) : nullptr,
+                    pow2_at_least(max(np, 1))};
 
   // Table entry i of the query (or its copy from the caller's table).
   auto table_entry = [&](int i) {
@@ -1035,7 +1080,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
   const bool wave_setup = np <= 64;
   if (wave_setup) {
     if (tid < 64) {
-      runs_wave(ix, s_list, np, walk_np, sp.min_rows, s_bits, segmented, max_runs, s_rstart,
+      runs_wave(ix, s_list, np, walk_np, sp.min_rows, ps, segmented, max_runs, s_rstart,
                 s_pre, &s_wsum[kScanBlock / 64], &mc->seg);
     } else {
       build_table(tid - 64, kScanBlock - 64);
@@ -1053,7 +1098,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
       if (p < np) {
         const int l = s_list[p];
         cnt = 1;
-        for (int s = ix.lseg[l]; s < ix.lseg[l + 1]; ++s) cnt += testbit(s_bits, ix.segs[s].x) ? 0 : 1;
+        for (int s = ix.lseg[l]; s < ix.lseg[l + 1]; ++s) cnt += ps.has(ix.segs[s].x) ? 0 : 1;
       }
       const int off = block_excl_scan(cnt, s_wsum);
       if (tid == kScanBlock - 1) s_wsum[kScanBlock / 64] = off + cnt;
@@ -1076,7 +1121,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
       l = s_list[p];
       cnt = 1;
       if (seg) {
-        for (int s = ix.lseg[l]; s < ix.lseg[l + 1]; ++s) cnt += testbit(s_bits, ix.segs[s].x) ? 0 : 1;
+        for (int s = ix.lseg[l]; s < ix.lseg[l + 1]; ++s) cnt += ps.has(ix.segs[s].x) ? 0 : 1;
       } else {
         cnt += ix.rstart[l + 1] > ix.rstart[l] ? 1 : 0;
       }
@@ -1092,7 +1137,7 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
       if (seg) {
         for (int s = ix.lseg[l]; s < ix.lseg[l + 1]; ++s) {
           const int4 g = ix.segs[s];
-          if (!testbit(s_bits, g.x)) {
+          if (!ps.has(g.x)) {
             s_rstart[r] = (uint32_t)g.y | kRunReplica;
             s_pre[r] = g.z - g.y;
             ++r;
@@ -1199,9 +1244,9 @@ __global__ __launch_bounds__(kScanBlock) __attribute__((amdgpu_waves_per_eu(8, 8
               const int2 r = ix.rep[ei];
               const int row = (int)((uint32_t)r.x & kRowMask);
               const int rank = (int)((uint32_t)r.x >> kRankShift);
-              k = !testbit(s_bits, r.y);
+              k = !ps.has(r.y);
               for (int i = 1; i < rank && k; ++i)
-                k = !testbit(s_bits, ix.assign_rows[(size_t)row * ix.R + i]);
+                k = !ps.has(ix.assign_rows[(size_t)row * ix.R + i]);
             }
             rows[u] = (int)ix.n + ei;
             keep[u] = k;
@@ -2200,43 +2245,58 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
   for (int r = 0; r < 4; ++r) qn[r] = s_qn[4 * g + r];
   // KS = dim_pad / 64 K-steps.  The query fragments stay in registers; the
-  // centroid fragments and norms of the next two list tiles are in flight
-  // while this one is being filtered (software pipelining across tiles).
+  // centroid fragments and norms of the next list tile are in flight while
+  // this one is being filtered (software pipelining across tiles).
   v4i_t fa[KS];
 #pragma unroll
   for (int k = 0; k < KS; ++k)
     fa[k] = *reinterpret_cast<const v4i_t*>(s_q8 + r16 * Dp + 64 * k + 16 * g);
   v4i_t fn[KS][kFCols], fn2[KS][kFCols];
   int cnn[kFCols], cnn2[kFCols];
+  // this lane's centroid fragment and norm addresses for list column 0 of a
+  // tile (column b adds 16 lists); tiles wholly inside nlist load unguarded
+  const int8_t* cbase = ix.cent8 + (size_t)(w * (kFTile / 4) + r16) * Dp + 16 * g;
+  const int32_t* nbase = ix.cnorm8 + w * (kFTile / 4) + r16;
   auto load_tile = [&](int t0, v4i_t (&dst)[KS][kFCols], int (&dn)[kFCols]) {
+    const int8_t* cp = cbase + (size_t)t0 * Dp;
+    if (t0 + kFTile <= ix.nlist) {  // tile-uniform
 #pragma unroll
-    for (int b = 0; b < kFCols; ++b) {
-      const int l = t0 + w * (kFTile / 4) + b * 16 + r16;
+      for (int b = 0; b < kFCols; ++b) {
 #pragma unroll
-      for (int k = 0; k < KS; ++k)
-        dst[k][b] = l < ix.nlist
-                        ? *reinterpret_cast<const v4i_t*>(ix.cent8 + (size_t)l * Dp + 64 * k + 16 * g)
-                        : v4i_t{0, 0, 0, 0};
-      dn[b] = l < ix.nlist ? ix.cnorm8[l] : 0;
+        for (int k = 0; k < KS; ++k)
+          dst[k][b] = *reinterpret_cast<const v4i_t*>(cp + (size_t)b * 16 * Dp + 64 * k);
+        dn[b] = nbase[t0 + b * 16];
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < kFCols; ++b) {
+        const bool in = t0 + w * (kFTile / 4) + b * 16 + r16 < ix.nlist;
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+          dst[k][b] = in ? *reinterpret_cast<const v4i_t*>(cp + (size_t)b * 16 * Dp + 64 * k)
+                         : v4i_t{0, 0, 0, 0};
+        dn[b] = in ? nbase[t0 + b * 16] : 0;
+      }
     }
   };
-  load_tile(0, fn, cnn);
-  load_tile(kFTile, fn2, cnn2);  // columns past nlist read as zero
-  for (int t0 = 0; t0 < ix.nlist; t0 += kFTile) {
-    const int l0 = t0 + w * (kFTile / 4);
-    v4i_t fb[KS][kFCols];
-    int cnb[kFCols];
+  // A list l passes row r's filter when cn(l) - 2 q.c(l) <= lim[r] =
+  // (distance of the row's threshold key) - |q|^2, i.e. when its distance is
+  // at most the threshold's: a tie with the threshold distance is admitted
+  // (the key may be larger than the threshold key; cut-backs and the final
+  // selection keep exactly the smallest keys).  lim changes only at cut-backs.
+  int lim[4];
+  auto load_lim = [&]() {
 #pragma unroll
-    for (int b = 0; b < kFCols; ++b) {
-#pragma unroll
-      for (int k = 0; k < KS; ++k) {
-        fb[k][b] = fn[k][b];
-        fn[k][b] = fn2[k][b];
-      }
-      cnb[b] = cnn[b];
-      cnn[b] = cnn2[b];
+    for (int r = 0; r < 4; ++r) {
+      const uint64_t t = s_thr[4 * g + r];
+      lim[r] = t == ~0ull ? INT_MAX : (int)unord32((uint32_t)(t >> 32)) - qn[r];
     }
-    if (t0 + 2 * kFTile < ix.nlist) load_tile(t0 + 2 * kFTile, fn2, cnn2);
+  };
+  load_lim();
+  // one tile: its MFMAs (fragments fb, norms cnb), the filter into the
+  // buffers, and the cut-backs of buffers that might not take another tile
+  auto process = [&](int t0, const v4i_t (&fb)[KS][kFCols], const int (&cnb)[kFCols]) {
+    const int l0 = t0 + w * (kFTile / 4);
     v4i_t acc[kFCols];
 #pragma unroll
     for (int b = 0; b < kFCols; ++b) acc[b] = v4i_t{0, 0, 0, 0};
@@ -2245,25 +2305,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
       for (int b = 0; b < kFCols; ++b)
         acc[b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[k], fb[k][b], acc[b], 0, 0, 0);
-    // thresholds as (distance, list) integer pairs: the distances are exact
-    // non-negative integers, so comparing them as ints orders like the keys
-    int dT[4], lT[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint64_t t = s_thr[4 * g + r];
-      dT[r] = t == ~0ull ? INT_MAX : (int)unord32((uint32_t)(t >> 32));
-      lT[r] = t == ~0ull ? INT_MAX : (int)(uint32_t)t;
-    }
+    const bool whole = t0 + kFTile <= ix.nlist;  // tile-uniform
 #pragma unroll
     for (int b = 0; b < kFCols; ++b) {
       const int l = l0 + b * 16 + r16;  // output column = lane % 16
-      if (l >= ix.nlist) continue;
+      const bool in = whole || l < ix.nlist;
       const int cn = cnb[b];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {  // output row = 4 * (lane / 16) + r
-        const int d = qn[r] + cn - 2 * acc[b][r];
-        if (d < dT[r] || (d == dT[r] && l < lT[r])) {
+        const int v = cn - 2 * acc[b][r];
+        if (in && v <= lim[r]) {
           const int m = 4 * g + r;
+          const int d = v + qn[r];
           s_buf[m * CAP + atomicAdd(&s_cnt[m], 1)] =
               ((uint64_t)ord32((float)d) << 32) | (uint32_t)l;
         }
@@ -2289,6 +2342,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
       }
     }
     __syncthreads();
+    if (full) load_lim();  // block-uniform: the thresholds changed
+  };
+  // two register sets, alternating: the next tile loads while this one runs
+  load_tile(0, fn, cnn);
+  for (int t0 = 0; t0 < ix.nlist; t0 += 2 * kFTile) {
+    if (t0 + kFTile < ix.nlist) load_tile(t0 + kFTile, fn2, cnn2);
+    process(t0, fn, cnn);
+    if (t0 + kFTile >= ix.nlist) break;
+    if (t0 + 2 * kFTile < ix.nlist) load_tile(t0 + 2 * kFTile, fn, cnn);
+    process(t0 + kFTile, fn2, cnn2);
   }
   // the np smallest of each query, ascending
   for (int m = w; m < kFQ; m += 4) {
@@ -2553,9 +2616,23 @@ constexpr int kMaxSegRuns = 1024;
 // a query's groups become runs only when they fit (the block checks).
 inline bool scan_segmented(const DevIndex& ix, int) { return ix.segs != nullptr; }
 
-inline int scan_runs(const DevIndex& ix, int np_max) {
+// The scan kernel's static table: 4 * ceil(M / 4) subspaces of 256 entries.
+inline size_t scan_table_bytes(const DevIndex& ix, bool lut16) {
+  return (size_t)((ix.M + 3) / 4) * 4 * kKsub * (lut16 ? 2 : 4);
+}
+constexpr size_t kScanTwoPerCU = 80 * 1024;  // LDS of a scan block that still fits twice in a CU
+
+// Past the worst-case bound, as many run slots as keep two blocks per CU next
+// to the smallest top-n buffer (n + one round): at least two per probed list.
+inline int scan_runs(const DevIndex& ix, int np_max, int n, bool lut16) {
+  const int floor_runs = scan_max_runs(np_max, 0, false);
+  if (ix.segs == nullptr) return floor_runs;
   const int worst = scan_max_runs(np_max, ix.max_segs, true);
-  return ix.segs != nullptr && worst <= kMaxSegRuns ? worst : scan_max_runs(np_max, 0, false);
+  if (worst <= kMaxSegRuns) return worst;
+  const size_t fixed = scan_table_bytes(ix, lut16) +
+                       scan_layout(ix.M, ix.nlist, ix.R, np_max, 0, n + kScanBlock * kScanRT, 0).total;
+  const int fit = fixed + 64 < kScanTwoPerCU ? (int)((kScanTwoPerCU - 64 - fixed) / 8) - 8 : 0;
+  return std::max(floor_runs, std::min(worst, fit / 64 * 64));
 }
 
 template <int W>
@@ -2566,7 +2643,7 @@ hipError_t launch_scan_w(const DevIndex& ix, const int32_t* lists, const int32_t
                          int64_t t_capacity, int32_t* t_ids, float* t_adc, int64_t* t_count,
                          ScanSplit sp, hipStream_t st) {
   const int seg = scan_segmented(ix, np_max) ? 1 : 0;
-  const int max_runs = scan_runs(ix, np_max);
+  const int max_runs = scan_runs(ix, np_max, n, lut16);
   const ScanLayout L = scan_layout(ix.M, ix.nlist, ix.R, np_max, max_runs, cap, 0);
   const int qpad = (qc + 7) / 8 * 8;
   const dim3 grid((unsigned)((size_t)qpad * smax));
@@ -2716,41 +2793,84 @@ __global__ void k_lm_fill(DevIndex ix, const int32_t* __restrict__ lists,
   if (l >= 0) invq[loff[l] + atomicAdd(&lfill[l], 1)] = q;
 }
 
-// One block: per-list query offsets and work-item offsets (exclusive prefix
-// sums; each thread sums a contiguous run of lists), and the item count.
+// Per-list query offsets and work-item offsets (exclusive prefix sums) and
+// the item count, in two launches over blocks of 1024 lists: k_lm_offsets
+// scans each block's lists and records the block's totals after ctr[4];
+// k_lm_offsets_add adds the totals of the blocks before it.
+__device__ __forceinline__ int lm_items(const DevIndex& ix, int l, int c, int group, int tile_rows) {
+  if (c == 0) return 0;
+  const int len = ix.pstart[l + 1] - ix.pstart[l];
+  return ((c + group - 1) / group) * ((len + tile_rows - 1) / tile_rows);
+}
+
 __global__ __launch_bounds__(1024) void k_lm_offsets(DevIndex ix, const int32_t* __restrict__ lcnt,
                                                      int tile_rows, int group,
                                                      int32_t* __restrict__ loff,
                                                      int32_t* __restrict__ ioff,
                                                      int32_t* __restrict__ ctr) {
   __shared__ int s_a[17], s_b[17];
-  const int tid = threadIdx.x;
-  const int ch = (ix.nlist + 1023) / 1024;
-  const int l0 = min(ix.nlist, tid * ch), l1 = min(ix.nlist, l0 + ch);
-  auto items = [&](int l, int c) {
-    if (c == 0) return 0;
-    const int len = ix.pstart[l + 1] - ix.pstart[l];
-    return ((c + group - 1) / group) * ((len + tile_rows - 1) / tile_rows);
-  };
-  int sa = 0, sb = 0;
-  for (int l = l0; l < l1; ++l) {
-    const int c = lcnt[l];
-    sa += c;
-    sb += items(l, c);
-  }
-  int a = block_excl_scan(sa, s_a);
-  int b = block_excl_scan(sb, s_b);
-  for (int l = l0; l < l1; ++l) {
-    const int c = lcnt[l];
+  const int nblk = (ix.nlist + 1023) / 1024;
+  const int l = blockIdx.x * 1024 + threadIdx.x;
+  const int c = l < ix.nlist ? lcnt[l] : 0;
+  const int it = l < ix.nlist ? lm_items(ix, l, c, group, tile_rows) : 0;
+  const int a = block_excl_scan(c, s_a);
+  const int b = block_excl_scan(it, s_b);
+  if (l < ix.nlist) {
     loff[l] = a;
     ioff[l] = b;
-    a += c;
-    b += items(l, c);
   }
-  if (tid == 1023) {
-    loff[ix.nlist] = a;
-    ioff[ix.nlist] = b;
-    ctr[0] = b;
+  if (threadIdx.x == 1023) {
+    ctr[4 + blockIdx.x] = a + c;
+    ctr[4 + nblk + blockIdx.x] = b + it;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_lm_offsets_add(DevIndex ix, int32_t* __restrict__ loff,
+                                                         int32_t* __restrict__ ioff,
+                                                         int32_t* __restrict__ ctr) {
+  const int nblk = (ix.nlist + 1023) / 1024;  // <= 1024 (lmajor_supported)
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // totals of the blocks before this one (ta) and of all blocks (tot)
+  int ta = 0, tb = 0, aa = 0, ab = 0;
+  if (t < nblk) {
+    aa = ctr[4 + t];
+    ab = ctr[4 + nblk + t];
+    if (t < (int)blockIdx.x) {
+      ta = aa;
+      tb = ab;
+    }
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    ta += __shfl_xor(ta, d, 64);
+    tb += __shfl_xor(tb, d, 64);
+    aa += __shfl_xor(aa, d, 64);
+    ab += __shfl_xor(ab, d, 64);
+  }
+  __shared__ int s_t[4][16];
+  if (lane == 0) {
+    s_t[0][w] = ta;
+    s_t[1][w] = tb;
+    s_t[2][w] = aa;
+    s_t[3][w] = ab;
+  }
+  __syncthreads();
+  ta = tb = aa = ab = 0;
+  for (int i = 0; i < 16; ++i) {
+    ta += s_t[0][i];
+    tb += s_t[1][i];
+    aa += s_t[2][i];
+    ab += s_t[3][i];
+  }
+  const int l = blockIdx.x * 1024 + t;
+  if (l < ix.nlist) {
+    loff[l] += ta;
+    ioff[l] += tb;
+  }
+  if (blockIdx.x == 0 && t == 0) {
+    loff[ix.nlist] = aa;
+    ioff[ix.nlist] = ab;
+    ctr[0] = ab;
   }
 }
 
@@ -3228,19 +3348,15 @@ __global__ __launch_bounds__(kBlock) void k_lm_select(
 
 int scan_smax(int n) { return std::max(1, std::min(16, 4096 / std::max(n, 1))); }
 
-// The scan kernel's static table: 4 * ceil(M / 4) subspaces of 256 entries.
-inline size_t scan_table_bytes(const DevIndex& ix, bool lut16) {
-  return (size_t)((ix.M + 3) / 4) * 4 * kKsub * (lut16 ? 2 : 4);
-}
-
 // Top-n buffer slots of a scan block: n + one round of entries at least;
 // more slack (fewer cut-backs) while the block still fits twice in a CU's LDS.
 int scan_cap(const DevIndex& ix, int np_max, int n, bool lut16) {
-  constexpr size_t kTwoPerCU = 80 * 1024;
+  constexpr size_t kTwoPerCU = kScanTwoPerCU;
   constexpr int kRound = kScanBlock * kScanRT;
   const int base = n + kRound;
   const size_t fixed = scan_table_bytes(ix, lut16) +
-                       scan_layout(ix.M, ix.nlist, ix.R, np_max, scan_runs(ix, np_max), 0, 0).total;
+                       scan_layout(ix.M, ix.nlist, ix.R, np_max, scan_runs(ix, np_max, n, lut16), 0,
+                                   0).total;
   int extra = 0;
   if (fixed + (size_t)base * 8 + 64 < kTwoPerCU)
     extra = (int)((kTwoPerCU - 64 - fixed - (size_t)base * 8) / 8) / 64 * 64;
@@ -3249,7 +3365,7 @@ int scan_cap(const DevIndex& ix, int np_max, int n, bool lut16) {
 
 size_t scan_lds_bytes(const DevIndex& ix, int np_max, int n, bool lut16) {
   return scan_table_bytes(ix, lut16) + scan_layout(ix.M, ix.nlist, ix.R, np_max,
-                                                   scan_runs(ix, np_max),
+                                                   scan_runs(ix, np_max, n, lut16),
                                                    scan_cap(ix, np_max, n, lut16), 0).total;
 }
 
@@ -3418,6 +3534,7 @@ bool lmajor_mfma(const DevIndex& ix) {
 }
 
 bool lmajor_supported(const DevIndex& ix) {
+  if (ix.nlist > (1 << 20)) return false;  // the work list's offsets take 1024 blocks of lists
   return lmajor_mfma(ix) || (!ix.int_grid && (ix.M + 3) / 4 <= kLutMaxW);
 }
 
@@ -3492,8 +3609,11 @@ hipError_t launch_lmajor(const DevIndex& ix, const float* q, const LaunchCfg& c,
       const int G = lmajor_group(ix, c.lut16);
       hipLaunchKernelGGL(k_lm_count, gp, dim3(256), 0, st, ix, w.lists, w.np_eff, lw.walkp,
                          c.np_max, c.qc, lc.min_rows, lw.lcnt);
-      hipLaunchKernelGGL(k_lm_offsets, dim3(1), dim3(1024), 0, st, ix, lw.lcnt, lc.tile_rows, G,
-                         lw.loff, lw.ioff, lw.ctr);
+      const int nblk = (ix.nlist + 1023) / 1024;
+      hipLaunchKernelGGL(k_lm_offsets, dim3(nblk), dim3(1024), 0, st, ix, lw.lcnt, lc.tile_rows,
+                         G, lw.loff, lw.ioff, lw.ctr);
+      hipLaunchKernelGGL(k_lm_offsets_add, dim3(nblk), dim3(1024), 0, st, ix, lw.loff, lw.ioff,
+                         lw.ctr);
       hipLaunchKernelGGL(k_lm_fill, gp, dim3(256), 0, st, ix, w.lists, w.np_eff, lw.walkp,
                          c.np_max, c.qc, lc.min_rows, lw.loff, lw.lfill, lw.invq);
       return hipGetLastError();

@@ -299,7 +299,10 @@ ann_status ann_get_profile(ann_index* ix, ann_profile* out, int reset);
  * Options of an index.
  * Tuning knobs of the scan work split (no effect on any result: the top-n of
  * a query is the same however its gathered entries are split into items):
- *   ANN_OPT_SCAN_TILE   target entries per work item, in [64, 2^30] (default 65536)
+ *   ANN_OPT_SCAN_TILE   target entries per work item, in [64, 2^30]; 0 (default):
+ *                       65536 for launches of 1024 queries or more, and
+ *                       65536 * queries / 1024 but at least 4096 below, so a
+ *                       small launch still has work items enough to fill the GPU
  *   ANN_OPT_SCAN_SPLIT  most work items per query, in [1, 16] (default 16;
  *                       the kernel also caps it at max(1, 4096 / rerank_n))
  *   ANN_OPT_SCAN_ORDER  1: queries are scanned in order of their

@@ -100,7 +100,7 @@ struct ann_index {
   std::vector<std::unique_ptr<Workspace>> pool;
   std::vector<Workspace*> free_ws;
   // tuning (ann_set_option); never changes results
-  int64_t opt_tile = 65536;
+  int64_t opt_tile = 0;  // 0: the tile follows the launch size (default_tile)
   int64_t opt_split = 16;
   int64_t opt_lut16 = 0;
   int64_t opt_order = 0;
@@ -378,6 +378,13 @@ Need need_for(const DevIndex& d, int qc, int np_max, int n, int smax) {
   r.lut = 0;  // the scan builds each query's table in LDS
   r.cand = 0;
   return r;
+}
+
+// Unless set: 65536 entries per work item from 1024 queries a launch on,
+// proportionally fewer below (at least 4096), so that a small launch still
+// has enough work items to fill the GPU.
+int64_t default_tile(int qc) {
+  return qc >= 1024 ? 65536 : std::max<int64_t>(4096, (int64_t)65536 * qc / 1024 / 64 * 64);
 }
 
 // Items of up to `tile` entries (default 64k: one per query at typical probe
@@ -792,7 +799,8 @@ ann_status run_chunk(ann_index* ix, Work& w, const float* q, int qc, const int32
                      int32_t* topn_ids, float* topn_adc, int64_t* ncand, hipStream_t st,
                      const Heur& h = Heur(), int64_t* nwalk = nullptr) {
   const DevIndex& d = ix->d;
-  LaunchCfg c = cfg_for(qc, np_max, n, k, ix->opt_tile, ix->opt_split);
+  LaunchCfg c = cfg_for(qc, np_max, n, k, ix->opt_tile ? ix->opt_tile : default_tile(qc),
+                        ix->opt_split);
   c.lut16 = ix->opt_lut16 != 0;
   c.order = ix->opt_order != 0;
   c.hb = h.batch;
@@ -1143,7 +1151,8 @@ extern "C" ann_status ann_set_option(ann_index* ix, int option, int64_t value) {
   if (!ix) return fail(ANN_EINVAL, "index is NULL");
   switch (option) {
     case ANN_OPT_SCAN_TILE:
-      if (value < 64 || value > (int64_t)1 << 30) return fail(ANN_EINVAL, "tile must be in [64, 2^30]");
+      if (value != 0 && (value < 64 || value > (int64_t)1 << 30))
+        return fail(ANN_EINVAL, "tile must be 0 or in [64, 2^30]");
       ix->opt_tile = value;
       return ANN_OK;
     case ANN_OPT_SCAN_SPLIT:

@@ -4,7 +4,10 @@ The scan's 16 waves walk their share of each round (at most 128 inserted
 keys per wave and round) at their own pace; a wave checks the buffer count
 after each of its rounds and waits at a meeting when the count is above
 T = cap - 2048 or when it has finished.  At a meeting every wave reads the
-same decision (cut back, or all done); a cut-back leaves at most n <= T keys.
+same decision (cut back, or all done).  A cut-back first keeps the keys whose
+distance is at most the n-th smallest distance (ties may keep more than n),
+and cuts exactly to n only when that would still leave more than T: so it
+leaves between n and T keys, which the model draws at random.
 The model interleaves the waves' steps at random and checks what the kernel
 relies on: the count never exceeds cap, every meeting gathers all waves,
 every round of every wave is walked once, and the loop ends.
@@ -34,7 +37,7 @@ def _run(seed, rounds, cap, n):
             if done_waves == WAVES:
                 return peak, meetings, walked
             if count > T:
-                count = min(count, n)
+                count = rng.randint(min(count, n), min(count, T))  # loose or exact cut
                 p_pass = max(0.01, p_pass * 0.5)
             waiting.clear()
             state = ["next"] * WAVES

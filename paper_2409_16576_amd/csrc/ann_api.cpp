@@ -655,7 +655,7 @@ extern "C" ann_status ann_load_index_ex(const char* path, int device, const ann_
 
   const int row_bytes = (M + 3) / 4 * 4;
   const int es = elem_size(dtype);
-  std::vector<uint8_t> codes_rows((n + rep.size()) * row_bytes, 0);
+  std::vector<uint8_t> codes_rows((n + rep.size()) * row_bytes + kCodeSlack, 0);
   std::vector<int32_t> asg_rows((size_t)n * R);
   for (uint64_t row = 0; row < n; ++row) {
     const uint64_t v = (uint64_t)row2ext[row];

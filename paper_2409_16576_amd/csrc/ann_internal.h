@@ -33,7 +33,8 @@ struct DevIndex {
   // Codes and IDs by row.  Rows n + e (e < replica entries) repeat the row
   // of replica entry e, so a run of replica entries reads its code rows and
   // IDs contiguously instead of gathering them from the vectors' first lists.
-  const uint8_t* codes;       // [n + replica entries, row_bytes] PQ codes (M used bytes)
+  const uint8_t* codes;       // [n + replica entries, row_bytes] PQ codes (M used bytes),
+                              // then kCodeSlack zero bytes
   const void* vecs;           // [n, dim] raw vectors by external ID
   const int32_t* row2ext;     // [n + replica entries]
   const float* centroids;     // [nlist, dim]
@@ -141,6 +142,9 @@ hipError_t launch_merge(const DevIndex& ix, const float* q, const LaunchCfg& c, 
                         int64_t* out_ids, float* out_dists, int32_t* reranked,
                         int32_t* page_reads, hipStream_t st);
 constexpr int kHostMaxRerank = 2048;  // largest rerank_n with the host-memory raw tier
+// Bytes after the last code row: a kernel may read whole dwords up to
+// dim_pad / dsub (<= 256) bytes from a row's start.
+constexpr int kCodeSlack = 256;
 constexpr int kNavMaxBeam = 1024;     // largest beam (and nprobe) of the graph walk
 // Batched form on integer-grid indexes: after launch_probe, in place of
 // launch_scan (same outputs for launch_merge, one item per query).

@@ -2958,6 +2958,26 @@ __device__ __forceinline__ int sq_bytes(v4i_t v, int acc) {
   return __builtin_amdgcn_sdot4(v[3], v[3], acc, false);
 }
 
+// Sum of x over the four 16-lane groups (lanes l, l ^ 16, l ^ 32, l ^ 48),
+// in every lane: each swap exchanges a half (a pair of rows) of two copies
+// of x, so the two copies' sum holds both halves.
+__device__ __forceinline__ int sum_lane_groups(int x) {
+  const auto h = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)x, false, false);
+  const int y = (int)h[0] + (int)h[1];
+  const auto r = __builtin_amdgcn_permlane16_swap((unsigned)y, (unsigned)y, false, false);
+  return (int)r[0] + (int)r[1];
+}
+
+// Largest integer distance d >= 0 whose key's high word (the bits of
+// (float)d with the sign bit set) is <= hi, capped at 2^26 (the distances
+// of an integer-grid index stay below 2^24); -1 if there is none.
+__device__ __forceinline__ int lm_dist_limit(uint32_t hi) {
+  if (hi < 0x80000000u) return -1;
+  const uint32_t b = hi & 0x7fffffffu;
+  if (b >= 0x4c800000u) return 1 << 26;  // (float)2^26 and above, inf, NaN patterns
+  return (int)floorf(__uint_as_float(b));
+}
+
 // LDS codebook bytes of the list-major kernel: dim_pad / dsub subspaces (the
 // ones past M all zero), 256 codewords of dsub bytes each.
 __host__ __device__ inline int lm_cb_bytes(int dim_pad) { return dim_pad * kKsub; }
@@ -2990,19 +3010,19 @@ __global__ __launch_bounds__(kLmBlock) void k_lm_mfma(DevIndex ix, const float* 
       reinterpret_cast<int4*>(s_cb)[i] =
           i < real16 ? reinterpret_cast<const int4*>(ix.cb8)[i] : int4{0, 0, 0, 0};
   }
-  // per lane and chunk: code dword offsets in a row, LDS codebook base
-  int coff[KC][ND];
+  // Per lane: the code dwords of chunk kc sit at lane_off + 64 kc / DS + 4 i
+  // in a row (the lane's first code at byte b0[kc] of the first dword);
+  // cbk[kc]: the LDS codebook of that first code's subspace.  Dwords past
+  // the row's M codes read the next row's bytes (the buffer keeps slack
+  // after its last row): those codes index padded subspaces, whose LDS
+  // codewords are all zero.
+  const uint32_t lane_off = (uint32_t)((16 * g / DS) & ~3);
   int b0[KC];
   const unsigned char* cbk[KC];
 #pragma unroll
   for (int kc = 0; kc < KC; ++kc) {
     const int m0 = (kc * 64 + 16 * g) / DS;
     b0[kc] = m0 & 3;
-#pragma unroll
-    for (int i = 0; i < ND; ++i) {
-      const int off = (m0 & ~3) + 4 * i;
-      coff[kc][i] = off < ix.row_bytes ? off : 0;
-    }
     cbk[kc] = s_cb + m0 * kKsub * DS;
   }
   const int nitems = a.ctr[0];
@@ -3042,41 +3062,51 @@ __global__ __launch_bounds__(kLmBlock) void k_lm_mfma(DevIndex ix, const float* 
     qn_r += __shfl_xor(qn_r, 32, 64);  // ||q'||^2 of query row r16
     int qn[4], qid[4];
     unsigned long long th[4];
-    uint32_t th_hi[4];
+    int lim[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       qn[r] = __shfl(qn_r, 4 * g + r, 64);
       qid[r] = s_qid[4 * g + r];
       th[r] = s_thr[4 * g + r];
-      th_hi[r] = (uint32_t)(th[r] >> 32);
+      // rn - 2 acc <= lim[r] exactly when the key's high word is within the
+      // bound's (lm_dist_limit); qn <= 2^23 and 2 |acc| <= 2^23 keep the
+      // per-row test free of overflow
+      lim[r] = lm_dist_limit((uint32_t)(th[r] >> 32)) - qn[r];
     }
     constexpr int kStep = 16 * (kLmBlock / 64);
-    for (int base = row0 + 16 * wv; base < row1; base += kStep * kLmU) {
+    // the item's rows from block-uniform bases, so that every load takes a
+    // 32-bit lane offset (rows per item <= 2^24, row_bytes <= 256)
+    const int nrows = __builtin_amdgcn_readfirstlane(row1 - row0);
+    const int r0u = __builtin_amdgcn_readfirstlane(row0);
+    const unsigned char* icodes = ix.codes + (size_t)r0u * ix.row_bytes;
+    const unsigned char* iext = reinterpret_cast<const unsigned char*>(ix.row2ext + r0u);
+    for (int rel0 = 16 * wv; rel0 < nrows; rel0 += kStep * kLmU) {
       uint32_t cw[kLmU][KC][ND];
       uint32_t ext[kLmU];
-      int rr[kLmU];
+      uint32_t voff[kLmU];
 #pragma unroll
       for (int u = 0; u < kLmU; ++u) {  // every load of the round first, external IDs leading
-        const int row = base + u * kStep + r16;
-        rr[u] = row < row1 ? row : row0;
-        ext[u] = (uint32_t)ix.row2ext[rr[u]];
+        const int rel = rel0 + u * kStep + r16;
+        const uint32_t rc = rel < nrows ? (uint32_t)rel : 0u;  // past the item: its first row
+        ext[u] = *reinterpret_cast<const uint32_t*>(iext + 4u * rc);
+        voff[u] = __umul24(rc, (uint32_t)ix.row_bytes) + lane_off;
       }
 #pragma unroll
-      for (int u = 0; u < kLmU; ++u) {
-        const unsigned char* crow = ix.codes + (size_t)rr[u] * ix.row_bytes;
+      for (int u = 0; u < kLmU; ++u)
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
           for (int i = 0; i < ND; ++i)
-            cw[u][kc][i] = *reinterpret_cast<const uint32_t*>(crow + coff[kc][i]);
-      }
+            cw[u][kc][i] =
+                *reinterpret_cast<const uint32_t*>(icodes + voff[u] + (kc * 64 / DS + 4 * i));
+      __builtin_amdgcn_sched_barrier(0);  // every load issued before the first decode
       // the IDs are used only when a key may pass; keep their loads here (in
       // flight with the codes) rather than issued late on that rare path
 #pragma unroll
       for (int u = 0; u < kLmU; ++u) asm volatile("" ::"v"(ext[u]));
 #pragma unroll
       for (int u = 0; u < kLmU; ++u) {
-        const int row = base + u * kStep + r16;
+        const int rel = rel0 + u * kStep + r16;
         int rn = 0;
         v4i_t acc = v4i_t{0, 0, 0, 0};
 #pragma unroll
@@ -3085,21 +3115,17 @@ __global__ __launch_bounds__(kLmBlock) void k_lm_mfma(DevIndex ix, const float* 
           rn = sq_bytes(fb, rn);
           acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[kc], fb, acc, 0, 0, 0);
         }
-        rn += __shfl_xor(rn, 16, 64);
-        rn += __shfl_xor(rn, 32, 64);  // ||dec'||^2 of candidate r16
-        // d >= 0 is an exact integer: its order-preserving bits are bits | 2^31
-        uint32_t h[4];
-        bool c = false;
+        rn = sum_lane_groups(rn);  // ||dec'||^2 of candidate r16
+        uint64_t may = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) may |= __ballot(rn <= lim[r] + 2 * acc[r]);
+        if (may == 0) continue;  // wave-uniform: no key can pass
+        const bool rv = rel < nrows;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          h[r] = __float_as_uint((float)(qn[r] + rn - 2 * acc[r])) | 0x80000000u;
-          c = c || h[r] <= th_hi[r];
-        }
-        if (__ballot(c) == 0) continue;  // wave-uniform: no key can pass
-        const bool rv = row < row1;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const uint64_t key = ((uint64_t)h[r] << 32) | ext[u];
+          // d >= 0 is an exact integer: its order-preserving bits are bits | 2^31
+          const uint32_t h = __float_as_uint((float)(qn[r] + rn - 2 * acc[r])) | 0x80000000u;
+          const uint64_t key = ((uint64_t)h << 32) | ext[u];
           const bool pass = rv && key < th[r];
           const uint64_t m = __ballot(pass);
           if (m) {  // wave-uniform; append: one atomic per (query, 16-lane group)

@@ -336,7 +336,7 @@ ann_status ann_get_profile(ann_index* ix, ann_profile* out, int reset);
  *                       [1, 64] (default 2)
  *   ANN_OPT_LM_TILE     rows of a list per work item, in [64, 2^24] (default 4096)
  *   ANN_OPT_LM_BLOCKS   blocks of the persistent launch, in [0, 65536]
- *                       (default 0: four per compute unit)
+ *                       (default 0: as many as the device holds at once)
  *   ANN_OPT_LM_CAP      list-major keys kept per query before it falls back
  *                       to the per-query scan, in [0, 2^20] (default 0:
  *                       min(32768, max(4096, 16 * rerank_n)))

@@ -222,7 +222,8 @@ extern "C" ann_status ann_autotune(ann_index* ix, const float* d_queries, int64_
     if (lmajor_mfma(index_dev(ix))) {  // int8 MFMA groups of 16 (several blocks per CU fit)
       for (int alpha : {1, 2, 4, 8})
         for (int rows : {1024, 4096, 16384})
-          for (int64_t blocks : {2 * ncu, 4 * ncu, 8 * ncu}) lm.push_back({alpha, rows, 0, blocks});
+          for (int64_t blocks : {(int64_t)0, 2 * ncu, 8 * ncu})  // 0: all resident at once
+            lm.push_back({alpha, rows, 0, blocks});
     } else {  // tables in LDS: one block per CU; short lists stay per query
       for (int alpha : {1, 2, 8})
         for (int min_rows : {0, 2048, 16384})

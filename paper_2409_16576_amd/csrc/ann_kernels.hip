@@ -2978,9 +2978,14 @@ __device__ __forceinline__ int lm_dist_limit(uint32_t hi) {
   return (int)floorf(__uint_as_float(b));
 }
 
-// LDS codebook bytes of the list-major kernel: dim_pad / dsub subspaces (the
-// ones past M all zero), 256 codewords of dsub bytes each.
-__host__ __device__ inline int lm_cb_bytes(int dim_pad) { return dim_pad * kKsub; }
+// LDS codebook bytes of the list-major kernel: the lane groups (16 bytes of
+// a K chunk: 16 / dsub subspaces of 256 codewords of dsub bytes, 4096 bytes)
+// that hold at least one of the M subspaces; the subspaces past M inside
+// them are all zero.
+__host__ __device__ inline int lm_cb_bytes(int M, int dsub) {
+  const int per = 16 / dsub;
+  return (M + per - 1) / per * 16 * kKsub;
+}
 
 // The persistent list-major kernel.  KC = dim_pad / 64 (K chunks of one
 // MFMA), DS = dsub.  Wave w of a block takes 16-row tiles w, w + 4, ... of
@@ -2989,22 +2994,29 @@ __host__ __device__ inline int lm_cb_bytes(int dim_pad) { return dim_pad * kKsub
 // lane / 16) holds query row r's and candidate r's bytes [16g, 16g + 16) of
 // each K chunk, and after the MFMA the products of queries 4g..4g+3 with
 // candidate r.
+// Least waves per SIMD the list-major kernel is compiled for: five (at most
+// 96 registers) where that needs no spill, else no bound.
+constexpr int lm_waves(int kc, int ds) {
+  return kc == 1 || (kc == 2 && ds >= 2) || (kc == 3 && ds >= 4) ? 5 : 1;
+}
+
 template <int KC, int DS>
-__global__ __launch_bounds__(kLmBlock) void k_lm_mfma(DevIndex ix, const float* __restrict__ Q,
+__global__ __launch_bounds__(kLmBlock) __attribute__((amdgpu_waves_per_eu(lm_waves(KC, DS))))
+void k_lm_mfma(DevIndex ix, const float* __restrict__ Q,
                                                       LmArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int Dp = KC * 64;
   constexpr int ND = LmCodes<DS>::ND;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r16 = lane & 15, g = lane >> 4;
-  constexpr int cb_bytes = Dp * kKsub;
+  const int cb_bytes = lm_cb_bytes(ix.M, DS);
   unsigned char* s_cb = smem;
   int8_t* s_q8 = reinterpret_cast<int8_t*>(smem + cb_bytes);  // [16][Dp]
   unsigned long long* s_thr =
       reinterpret_cast<unsigned long long*>(smem + cb_bytes + kLmG * Dp);  // [16]
   int* s_qid = reinterpret_cast<int*>(s_thr + kLmG);                      // [16]
   int* s_it = s_qid + kLmG;  // item, queries, first row, end row, first query slot
-  {  // codebook, zero-padded to dim_pad / DS subspaces
+  {  // codebook, zero-padded to whole lane groups
     const int real16 = (ix.M * kKsub * DS + 15) / 16;
     for (int i = tid; i < cb_bytes / 16; i += kLmBlock)
       reinterpret_cast<int4*>(s_cb)[i] =
@@ -3014,16 +3026,21 @@ __global__ __launch_bounds__(kLmBlock) void k_lm_mfma(DevIndex ix, const float* 
   // in a row (the lane's first code at byte b0[kc] of the first dword);
   // cbk[kc]: the LDS codebook of that first code's subspace.  Dwords past
   // the row's M codes read the next row's bytes (the buffer keeps slack
-  // after its last row): those codes index padded subspaces, whose LDS
-  // codewords are all zero.
+  // after its last row).  In a lane group that holds a real subspace those
+  // codes index padded subspaces, whose LDS codewords are all zero; a lane
+  // group past the M subspaces (real[kc] false) decodes through the first
+  // group's codewords instead: its query bytes are zero, so it adds nothing
+  // to the product, and its bytes are left out of the norm.
   const uint32_t lane_off = (uint32_t)((16 * g / DS) & ~3);
   int b0[KC];
+  bool real[KC];
   const unsigned char* cbk[KC];
 #pragma unroll
   for (int kc = 0; kc < KC; ++kc) {
     const int m0 = (kc * 64 + 16 * g) / DS;
     b0[kc] = m0 & 3;
-    cbk[kc] = s_cb + m0 * kKsub * DS;
+    real[kc] = m0 < ix.M;
+    cbk[kc] = s_cb + (real[kc] ? m0 * kKsub * DS : 0);
   }
   const int nitems = a.ctr[0];
   for (;;) {
@@ -3112,7 +3129,8 @@ __global__ __launch_bounds__(kLmBlock) void k_lm_mfma(DevIndex ix, const float* 
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
           const v4i_t fb = lm_decode<DS>(cbk[kc], cw[u][kc], b0[kc]);
-          rn = sq_bytes(fb, rn);
+          const int rs = sq_bytes(fb, rn);
+          rn = real[kc] ? rs : rn;
           acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[kc], fb, acc, 0, 0, 0);
         }
         rn = sum_lane_groups(rn);  // ||dec'||^2 of candidate r16
@@ -3649,13 +3667,20 @@ hipError_t launch_lmajor(const DevIndex& ix, const float* q, const LaunchCfg& c,
       LmArgs a{lw.loff, lw.ioff, lw.lcnt, lw.invq, lw.thr, lw.cnt2, lw.out2, lw.cap2, lw.ctr,
                lc.tile_rows, G};
       if (lmajor_mfma(ix)) {
-        const size_t lds = (size_t)lm_cb_bytes(ix.dim_pad) + (size_t)kLmG * ix.dim_pad +
+        const size_t lds = (size_t)lm_cb_bytes(ix.M, ix.dsub) + (size_t)kLmG * ix.dim_pad +
                            kLmG * 8 + kLmG * 4 + 8 * 4;
         const LmFn kern = lm_kernel(ix);
         if (lds > 65536)
           (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)lds);
-        const int blocks = lc.blocks > 0 ? lc.blocks : 4 * std::max(1, num_cu);
+        int blocks = lc.blocks;
+        if (blocks <= 0) {  // every block resident at once
+          int per_cu = 0;
+          if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, kLmBlock,
+                                                           lds) != hipSuccess || per_cu < 1)
+            per_cu = 4;
+          blocks = per_cu * std::max(1, num_cu);
+        }
         hipLaunchKernelGGL(kern, dim3(blocks), dim3(kLmBlock), lds, st, ix, q, a);
         return hipGetLastError();
       }

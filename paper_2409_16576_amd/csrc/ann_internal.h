@@ -16,7 +16,9 @@ constexpr int kBlock = 256;           // threads per block (all kernels but the 
 constexpr int kScanBlock = 1024;      // threads per block of the scan kernel
 constexpr int kMergeBlock = 1024;     // threads per block of the merge / re-rank kernels
 constexpr int kLdsPerCu = 160 * 1024;  // LDS bytes per compute unit (gfx950)
-constexpr int kScanRT = 2;            // entries per scan thread per round
+constexpr int kScanRT = 1;            // entries per scan thread per round (one: the top-n
+                                      // buffer keeps a round's worth of room, and a smaller
+                                      // round leaves more of it between cut-backs)
 constexpr int kMaxRerank = 4096;      // largest rerank_n
 constexpr int kMaxM = 64;             // largest number of PQ subspaces
 constexpr int kMaxDim = 2048;

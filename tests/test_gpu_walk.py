@@ -51,7 +51,7 @@ def _run_slots(ix, np_max, max_segs, n):
     worst = np_max * (1 + max_segs)
     if worst <= MAX_SEG_RUNS:
         return worst
-    fixed = _scan_lds(ix, np_max, 0, n + 2048)
+    fixed = _scan_lds(ix, np_max, 0, n + 1024)  # n + one round (1024 threads, one entry each)
     fit = (TWO_PER_CU - 64 - fixed) // 8 - 8 if fixed + 64 < TWO_PER_CU else 0
     return max(2 * np_max, min(worst, fit // 64 * 64))
 

@@ -1,9 +1,9 @@
 """Model of the scan block's meeting protocol (CPU, random interleavings).
 
-The scan's 16 waves walk their share of each round (at most 128 inserted
-keys per wave and round) at their own pace; a wave checks the buffer count
-after each of its rounds and waits at a meeting when the count is above
-T = cap - 2048 or when it has finished.  At a meeting every wave reads the
+The scan's 16 waves walk their share of each round (at most 64 inserted
+keys per wave and round: one entry per lane) at their own pace; a wave checks
+the buffer count after each of its rounds and waits at a meeting when the
+count is above T = cap - 1024 or when it has finished.  At a meeting every wave reads the
 same decision (cut back, or all done).  A cut-back first keeps the keys whose
 distance is at most the n-th smallest distance (ties may keep more than n),
 and cuts exactly to n only when that would still leave more than T: so it
@@ -16,7 +16,7 @@ import random
 
 import pytest
 
-WAVES, PER_WAVE, ROUND = 16, 128, 2048
+WAVES, PER_WAVE, ROUND = 16, 64, 1024
 
 
 def _run(seed, rounds, cap, n):

@@ -77,8 +77,9 @@ def setup(tmp_path_factory, orc, ann):
     out["many"] = (orc.read_index(p), ann.Index(p, 0))
     p, _ = fx.built(d, "few", X, "u8", nlist=64, M=8)               # few groups per list
     out["few"] = (orc.read_index(p), ann.Index(p, 0))
-    # 64 subspaces: the 64 KB table leaves no room for extra run slots, so
-    # queries with many surviving groups test their entries one by one
+    # 64 subspaces: the 64 KB table (with the buffer of n = 800) leaves no
+    # room for extra run slots, so queries with many surviving groups test
+    # their entries one by one
     X = fx.mixture(73, 30000, 64, "u8", n_centres=16, hi=255)
     p, _ = fx.built(d, "tight", X, "u8", nlist=256, M=64, eps=1.0)
     out["tight"] = (orc.read_index(p), ann.Index(p, 0))
@@ -124,14 +125,17 @@ def test_run_layouts_parity_and_walk(ann, setup, orc, name, npb):
     _say(name, "nprobe up to", npb)
     Q = torch.from_numpy(Qh).cuda()
     NP = torch.from_numpy(npq).cuda()
-    r = orc.search(ix, Qh, npq, 10, 200)
-    ids, d = g.search(Q, NP, 10, 200)
+    # "tight": the 64 KB table and a top-n buffer of n = 800 (+ one round)
+    # leave no LDS for run slots past two per probed list
+    n = 800 if name == "tight" else 200
+    r = orc.search(ix, Qh, npq, 10, n)
+    ids, d = g.search(Q, NP, 10, n)
     assert np.array_equal(ids.cpu().numpy(), r.ids) and np.array_equal(d.cpu().numpy(), r.dists)
-    tid, tadc, nc, nw = g.search_topn(Q, NP, 200, walked=True)
+    tid, tadc, nc, nw = g.search_topn(Q, NP, n, walked=True)
     torch.cuda.synchronize()
     assert np.array_equal(nc.cpu().numpy(), r.ncand)
     lists, _ = orc.probe(ix, Qh, npq)
-    want, used = _expected_walk(ix, lists, int(npq.max()), 200)
+    want, used = _expected_walk(ix, lists, int(npq.max()), n)
     assert np.array_equal(nw.cpu().numpy(), want)
     if name == "tight" and npb >= 64:  # both layouts occur in this batch
         assert used.any() and not used.all(), used.mean()

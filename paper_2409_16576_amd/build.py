@@ -40,12 +40,19 @@ def _run(cmd):
         sys.stderr.write("\n".join(noise) + "\n")
 
 
+# Per-source additions: the search kernels take their MFMA accumulators in
+# ordinary vector registers (no accumulation-register copies; the small-batch
+# probe fits four waves per SIMD instead of three).
+SOURCE_FLAGS = {"ann_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def build_libann(jobs: int = 4) -> str:
     objs = []
     procs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, *HIP_FLAGS, "-x", "hip", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+        cmd = [HIPCC, *HIP_FLAGS, *SOURCE_FLAGS.get(src, []), "-x", "hip",
+               "-I", os.path.join(ROOT, "include"), "-I", CSRC,
                "-c", os.path.join(CSRC, src), "-o", obj]
         procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
                                        text=True), cmd))

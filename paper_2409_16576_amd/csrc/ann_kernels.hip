@@ -2876,15 +2876,25 @@ __global__ __launch_bounds__(1024) void k_lm_offsets_add(DevIndex ix, int32_t* _
 
 // Work item `it`: its list (largest l with ioff[l] <= it), query group and
 // row tile -> s_it[1..4] = queries in the group, first row, end row, first
-// slot of the group in invq.  Groups of one tile are adjacent items.
+// slot of the group in invq.  Groups of one tile are adjacent items.  Called
+// by every lane of one wave: the list is found by a 64-way search (each
+// round probes 64 points of the remaining range at once, so 65,536 lists
+// take three dependent loads), lane 0 writes the result.
 __device__ __forceinline__ void lm_item(const DevIndex& ix, const LmArgs& a, int it, int G,
                                         int* s_it) {
-  int lo = 0, hi = ix.nlist - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.ioff[mid] <= it) lo = mid;
-    else hi = mid - 1;
+  const int lane = threadIdx.x & 63;
+  int lo = 0, hi = ix.nlist - 1;  // the list is in [lo, hi]; ioff[0] = 0 <= it
+  while (hi > lo) {                // wave-uniform
+    // probes in (lo, hi], nondecreasing with the lane, the last at hi: the
+    // lanes whose probe passes form a prefix
+    const int pr = lo + (int)(((int64_t)(hi - lo) * (lane + 1) + 63) / 64);
+    const int np = __popcll(__ballot(a.ioff[pr] <= it));
+    const int nlo = np > 0 ? __shfl(pr, np - 1, 64) : lo;
+    const int nhi = np < 64 ? __shfl(pr, np, 64) - 1 : hi;
+    lo = nlo;
+    hi = nhi;
   }
+  if (lane != 0) return;
   const int l = lo, local = it - a.ioff[l], nql = a.lcnt[l];
   const int ng = (nql + G - 1) / G;
   const int grp = local % ng, tile = local / ng;
@@ -3044,12 +3054,12 @@ void k_lm_mfma(DevIndex ix, const float* __restrict__ Q,
   }
   const int nitems = a.ctr[0];
   for (;;) {
-    if (tid == 0) {
-      const int it = atomicAdd(&a.ctr[1], 1);
-      s_it[0] = it;
-      if (it < nitems) {
-        lm_item(ix, a, it, kLmG, s_it);
-      }
+    if (tid < 64) {  // wave 0 takes the next item and looks it up
+      int it = 0;
+      if (tid == 0) it = atomicAdd(&a.ctr[1], 1);
+      it = __shfl(it, 0, 64);
+      if (tid == 0) s_it[0] = it;
+      if (it < nitems) lm_item(ix, a, it, kLmG, s_it);
     }
     __syncthreads();
     if (s_it[0] >= nitems) break;  // block-uniform
@@ -3191,9 +3201,11 @@ __global__ __launch_bounds__(kLutBlock) void k_lm_lut(DevIndex ix, const float* 
   const uint64_t lanemask = (1ull << lane) - 1ull;
   const int nitems = a.ctr[0];
   for (;;) {
-    if (tid == 0) {
-      const int it = atomicAdd(&a.ctr[1], 1);
-      s_it[0] = it;
+    if (tid < 64) {  // wave 0 takes the next item and looks it up
+      int it = 0;
+      if (tid == 0) it = atomicAdd(&a.ctr[1], 1);
+      it = __shfl(it, 0, 64);
+      if (tid == 0) s_it[0] = it;
       if (it < nitems) lm_item(ix, a, it, G, s_it);
     }
     __syncthreads();
